@@ -1,0 +1,222 @@
+/*
+ * tacaw.h - C ABI of libtacaw, the MI355X (gfx950) TACAW hot path.
+ *
+ * The library computes, for a trajectory of atomic positions, the exit waves
+ * of a frame-resolved multislice simulation and the TACAW spectrum
+ *     I(k, w) = | F_t[ psi(k, t) - <psi(k, t)>_t ] |^2
+ * (PySlice, arXiv 2602.10064: Methods 2.1 "Workflow Architecture" for the
+ * time transform; Methods 2.2 "Multislice Propagation" and "Atomic Scattering
+ * Potentials" for the scattering; Supplement "Extensibility to Other Atomistic
+ * Dynamics" for the inputs: positions (frames, atoms, 3), species and cell;
+ * Supplement "Minimal Working Example" for the calculator parameters:
+ * aperture, beam energy, sampling, slice thickness and probe positions).
+ *
+ * Conventions shared by every call:
+ *   - Lengths in Angstrom, beam energy in volts, frame spacing in fs,
+ *     frequencies in THz, spatial frequencies in cycles/Angstrom.
+ *   - Arrays are C-contiguous (row-major).  Reciprocal-space arrays are
+ *     unshifted (DC at index 0, numpy fftfreq order) with kx fastest:
+ *     [ky][kx].
+ *   - All pointers are host pointers unless the argument says a device
+ *     pointer may be given.  Inputs are copied; the caller keeps ownership
+ *     of everything it passes in.
+ *   - Every call returns a tacaw_status.  No C++ exception crosses the ABI.
+ *     On failure tacaw_last_error() returns a message for the calling thread.
+ *   - A job is used by one caller thread at a time.
+ */
+#ifndef TACAW_H
+#define TACAW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TACAW_OK = 0,
+  TACAW_EINVAL = 1,        /* an argument is out of range or inconsistent          */
+  TACAW_ENOMEM = 2,        /* the job can never fit the context's memory budget   */
+  TACAW_EDEVICE = 3,       /* a HIP runtime call failed                            */
+  TACAW_EBUSY = 4,         /* the job is queued or running in the serving loop     */
+  TACAW_ENOTREADY = 5,     /* no result yet (the job has not been run)             */
+  TACAW_ECANCELLED = 6,    /* the job was cancelled before it finished             */
+  TACAW_EUNSUPPORTED = 7   /* valid, but a grid size this build does not provide   */
+} tacaw_status;
+
+/* Number of Gaussian terms per species in the form factor. */
+#define TACAW_N_GAUSS 5
+
+/* tacaw_job_desc.flags */
+#define TACAW_TWO_SIDED 1u        /* keep all F frequency bins instead of F/2      */
+#define TACAW_KEEP_EXIT_WAVES 2u  /* keep psi(k, t) readable after the time stage  */
+
+typedef struct tacaw_ctx tacaw_ctx;
+typedef struct tacaw_job tacaw_job;
+
+/*
+ * Problem statement of one job.
+ *
+ * Potential (Methods 2.2, "Atomic Scattering Potentials", with the tabulated
+ * Kirkland form replaced by a Gaussian form factor):  species s has the
+ * electron form factor f_s(q) = C sum_i gauss_a[s][i] exp(-gauss_b[s][i] q^2),
+ * q in cycles/A, a in A, b in A^2, C = 2 pi a0 e = 47.8776 V A^2.  Its
+ * projected potential v_s(r) = C sum_i a_i (pi/b_i) exp(-pi^2 r^2 / b_i) (V A)
+ * is point-sampled at grid nodes r_p = (p_x Lx/Nx, p_y Ly/Ny) and summed over
+ * the atoms of a slice and their periodic images.  The library truncates each
+ * atom at r_c = sqrt(b_max ln 1e8)/pi, which changes V by at most 1e-8 of an
+ * atom's peak.
+ *
+ * Slices (Methods 2.2, "atoms within the slice z-bounds"): atom j belongs to
+ * slice floor((zbar_j mod Lz)/dz), clamped to [0, n_slices), where zbar_j is
+ * its FP64 mean z over all frames and dz = Lz / n_slices.
+ *
+ * Multislice (Methods 2.2, "Multislice Propagation"): in every slice the wave
+ * is multiplied by t = exp(i sigma V) and then propagated by
+ * P(k) = exp(-i pi lambda dz |k|^2) in reciprocal space (relativistic lambda
+ * and sigma = 2 pi gamma m0 e lambda / h^2).  The exit wave is the
+ * reciprocal-space wave after the last propagator, with unitary (ortho) FFTs.
+ *
+ * Illumination (Supplement, Minimal Working Example: aperture=0 is a parallel
+ * beam, aperture=30 a 30 mrad convergent probe at probe_xs/probe_ys):
+ * aperture_mrad == 0 -> plane wave 1/sqrt(Nx Ny) (probe_xy ignored, one wave
+ * per frame).  aperture_mrad > 0 -> for each probe position an aberration-free
+ * hard-aperture probe: A(k) = 1 where lambda |k| <= alpha, times
+ * exp(-2 pi i k.r_p), inverse-transformed and normalised to unit norm.
+ *
+ * Windows: pot_nx/pot_ny == 0 (or equal to nx/ny) -> the wave grid covers the
+ * cell.  Otherwise the potential is built on the full-cell pot_nx x pot_ny
+ * grid and every probe propagates on an nx x ny window of it (same pixel
+ * size), cropped with periodic wrap at origin floor(r_p / d) - N/2.
+ *
+ * Time transform (Methods 2.1): per (probe, k), the FP64 mean over all frames
+ * is subtracted and I_m = |(1/F) sum_f dpsi_f exp(-2 pi i m f / F)|^2 is
+ * returned for m = 0..F/2-1 (or all F with TACAW_TWO_SIDED).  Frequencies
+ * f_m = m / (F dt) (Supplement, "Sampling Considerations").
+ */
+typedef struct {
+  double cell[3];              /* orthorhombic Lx, Ly, Lz [A], all > 0                  */
+  int32_t nx, ny;              /* wave grid; each a product of 2, 3, 5 (EINVAL otherwise) */
+  int32_t n_slices;            /* >= 1                                                   */
+  double voltage_V;            /* beam energy [V], > 0                                   */
+  double aperture_mrad;        /* 0 -> plane wave; > 0 -> probe semi-angle [mrad]        */
+  int32_t n_probes;            /* probe count (>= 1 when aperture_mrad > 0)              */
+  const double* probe_xy;      /* n_probes x 2 probe positions [A] (host)                */
+  int32_t pot_nx, pot_ny;      /* full-cell potential grid for windows, or 0             */
+  double dt_fs;                /* frame spacing [fs], > 0                                */
+  int32_t n_frames;            /* >= 2, a product of 2, 3, 5                             */
+  int32_t n_atoms;             /* >= 0                                                   */
+  int32_t n_species;           /* >= 1                                                   */
+  const int32_t* species_Z;    /* n_species atomic numbers (labels only)                 */
+  const double* gauss_a;       /* n_species x 5 form-factor amplitudes [A], > 0          */
+  const double* gauss_b;       /* n_species x 5 form-factor widths [A^2], > 0            */
+  uint32_t flags;              /* TACAW_TWO_SIDED | TACAW_KEEP_EXIT_WAVES                */
+} tacaw_job_desc;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes caps the device
+ * memory that jobs of this context may hold at once (0 -> 90% of the device's
+ * free memory at creation).  The context owns the serving thread and the
+ * tuning state.  Errors: EINVAL (bad device), EDEVICE. */
+tacaw_status tacaw_ctx_create(int device, size_t hbm_budget_bytes, tacaw_ctx** out);
+
+/* Destroy a context.  Jobs still queued in its serving loop are cancelled and
+ * waited for; jobs themselves must still be destroyed by the caller, before
+ * or after. */
+tacaw_status tacaw_ctx_destroy(tacaw_ctx* ctx);
+
+/* ---- jobs ---------------------------------------------------------------- */
+
+/* Device bytes a job with this description holds while resident (positions,
+ * potentials, exit waves, spectrum, tables).  Validates the description. */
+tacaw_status tacaw_job_footprint(const tacaw_job_desc* desc, size_t* bytes);
+
+/* Create a job: validate, bin atoms into slices, encode positions, allocate
+ * the job's device buffers and upload its inputs.  atom_species: n_atoms
+ * indices into species_Z (host).  positions: n_frames x n_atoms x 3 [A]
+ * (host, float64).  Errors: EINVAL (invalid description or species index),
+ * ENOMEM (footprint above the context budget), EUNSUPPORTED (grid size
+ * without a kernel in this build), EDEVICE. */
+tacaw_status tacaw_job_create(tacaw_ctx* ctx, const tacaw_job_desc* desc,
+                              const int32_t* atom_species, const double* positions,
+                              tacaw_job** out);
+
+/* Plain per-job form: enqueue the whole hot path (potentials, multislice over
+ * every (probe, frame) wave, exit-wave capture, FP64 frame mean, time FFT and
+ * |.|^2) on `hip_stream` (a hipStream_t, or NULL for the default stream) and
+ * return without waiting.  May be called again to recompute.  EBUSY while the
+ * job is in the serving loop. */
+tacaw_status tacaw_run(tacaw_job* job, void* hip_stream);
+
+/* Serving form: hand the job to the context's continuous-batching loop.
+ * The loop admits it once its footprint fits the budget next to the jobs
+ * already resident and interleaves its slice steps with theirs. */
+tacaw_status tacaw_submit(tacaw_ctx* ctx, tacaw_job* job);
+
+/* *done = 1 once a submitted job has its spectrum (or was cancelled). */
+tacaw_status tacaw_poll(tacaw_job* job, int* done);
+
+/* Block until a submitted job finishes.  ECANCELLED if it was cancelled. */
+tacaw_status tacaw_wait(tacaw_job* job);
+
+/* Cancel a submitted job.  Jobs not yet admitted are dropped; a running job
+ * stops at its next frame batch.  Other jobs are unaffected. */
+tacaw_status tacaw_cancel(tacaw_job* job);
+
+/* Copy the spectrum I[p][m][ky][kx] (float32, n = n_probes * M * ny * nx,
+ * M = F/2 or F) into dst, a host pointer or (dst_on_device != 0) a device
+ * pointer.  Waits for the job's work first.  ENOTREADY before a run. */
+tacaw_status tacaw_get_spectrum(tacaw_job* job, float* dst, size_t n, int dst_on_device);
+
+/* Copy the exit waves psi[p][f][ky][kx] (complex64 as interleaved float re,im;
+ * n = n_probes * F * ny * nx complex values) into dst (host or device).
+ * Needs TACAW_KEEP_EXIT_WAVES. */
+tacaw_status tacaw_get_exit_waves(tacaw_job* job, void* dst_c64, size_t n, int dst_on_device);
+
+/* Output axes: kx[nx], ky[ny] in cycles/A (fftfreq order, spacing 1/(N d)),
+ * f_THz[M] (m / (F dt), fftfreq order when two-sided).  Any pointer may be
+ * NULL. */
+tacaw_status tacaw_axes(const tacaw_job_desc* desc, double* kx, double* ky, double* f_THz);
+
+/* Slice index of every atom (n_atoms int32, host), as the planner binned it. */
+tacaw_status tacaw_job_slices(const tacaw_job* job, int32_t* slice_of_atom, size_t n);
+
+/* Release a job's device memory.  EBUSY while it is in the serving loop. */
+tacaw_status tacaw_job_destroy(tacaw_job* job);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* tacaw_last_error(void);
+
+/* ---- measurement ---------------------------------------------------------- */
+
+/* Kernel classes timed by the library when timing is on. */
+typedef enum {
+  TACAW_K_SPLAT = 0,      /* projected potentials                      */
+  TACAW_K_ROW = 1,        /* row pass: iFFT_x, transmission, FFT_x     */
+  TACAW_K_COL = 2,        /* column pass: FFT_y, propagator, iFFT_y    */
+  TACAW_K_TIME = 3,       /* FP64 mean, time FFT, |.|^2                */
+  TACAW_K_OTHER = 4,      /* tables, probes, fused/persistent kernels  */
+  TACAW_K_FUSED = 5,      /* fused whole-multislice kernel             */
+  TACAW_K_COUNT = 6
+} tacaw_kernel_class;
+
+/* Turn per-kernel HIP-event timing on (1) or off (0) for jobs of this
+ * context; turning it on clears the accumulated figures.  Events are
+ * recorded on the stream each kernel is launched on. */
+tacaw_status tacaw_timing_enable(tacaw_ctx* ctx, int on);
+
+/* Accumulated kernel time (ms) and launch count of one class since timing
+ * was enabled; synchronises the recorded events first. */
+tacaw_status tacaw_timing_get(tacaw_ctx* ctx, int kernel_class, double* total_ms,
+                              int64_t* launches);
+
+/* Library version string. */
+const char* tacaw_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TACAW_H */

@@ -1,0 +1,571 @@
+// C ABI of libtacaw: contexts, jobs, the plain per-job run, results, timing.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "runtime.h"
+
+namespace tacaw {
+const char* last_error_text();
+void encode_positions(const HostPlan& hp, const double* pos, int f0, int f1, AtomPos* out);
+tacaw_status run_batch_range(tacaw_job* job, hipStream_t s, int f_begin, int f_end);
+tacaw_status run_time_stage(tacaw_job* job, hipStream_t s);
+}  // namespace tacaw
+
+using namespace tacaw;
+
+#define HIP_TRY(call)                                                                     \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess) {                                                               \
+      set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, __LINE__); \
+      return TACAW_EDEVICE;                                                               \
+    }                                                                                     \
+  } while (0)
+
+namespace {
+
+template <typename T>
+hipError_t dalloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  return hipMalloc((void**)p, count * sizeof(T));
+}
+
+void free_job_buffers(tacaw_job* j) {
+  void* bufs[] = {j->d_exit,    j->d_spec,   j->d_V,      j->d_pos,     j->d_species,   j->d_tile_start,
+                  j->d_tile_atoms, j->d_coef, j->d_tw_x,  j->d_tw_y,    j->d_tw_t,      j->d_px,
+                  j->d_py,      j->d_px_last, j->d_py_last, j->d_probe0, j->d_origin,   j->d_rloc,
+                  j->d_count};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  j->d_exit = nullptr;
+  j->d_spec = nullptr;
+  j->d_V = nullptr;
+  j->d_pos = nullptr;
+  j->d_species = nullptr;
+  j->d_tile_start = nullptr;
+  j->d_tile_atoms = nullptr;
+  j->d_coef = nullptr;
+  j->d_tw_x = j->d_tw_y = j->d_tw_t = nullptr;
+  j->d_px = j->d_py = j->d_px_last = j->d_py_last = nullptr;
+  j->d_probe0 = nullptr;
+  j->d_origin = nullptr;
+  j->d_rloc = nullptr;
+  j->d_count = nullptr;
+}
+
+hipEvent_t take_event(tacaw_ctx* c) {
+  if (!c->event_pool.empty()) {
+    hipEvent_t e = c->event_pool.back();
+    c->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void drain_records(tacaw_ctx* c) {
+  for (auto& r : c->records) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.stop) == hipSuccess && hipEventElapsedTime(&ms, r.start, r.stop) == hipSuccess) {
+      c->total_ms[r.cls] += ms;
+      c->launches[r.cls] += 1;
+    }
+    c->event_pool.push_back(r.start);
+    c->event_pool.push_back(r.stop);
+  }
+  c->records.clear();
+}
+
+}  // namespace
+
+namespace tacaw {
+
+// Launch wrapper: brackets the launch with events on its stream when timing.
+template <typename F>
+static tacaw_status timed(tacaw_job* job, int cls, hipStream_t s, F&& launch) {
+  tacaw_ctx* c = job->ctx;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  bool tm = false;
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    tm = c->timing;
+    if (tm) {
+      if (c->records.size() > 8192) drain_records(c);
+      e0 = take_event(c);
+      e1 = take_event(c);
+    }
+  }
+  if (tm && e0) (void)hipEventRecord(e0, s);
+  hipError_t e = launch();
+  if (tm && e1) (void)hipEventRecord(e1, s);
+  if (tm && e0 && e1) {
+    std::lock_guard<std::mutex> lk(c->mu);
+    c->records.push_back({cls, e0, e1});
+  }
+  if (e != hipSuccess) {
+    set_error("kernel launch failed: %s", hipGetErrorString(e));
+    return TACAW_EDEVICE;
+  }
+  return TACAW_OK;
+}
+
+static PassArgs pass_args(tacaw_job* j) {
+  const HostPlan& hp = j->hp;
+  PassArgs a{};
+  a.exit = j->d_exit;
+  a.V = j->d_V;
+  a.probe0 = j->d_probe0;
+  a.origin = j->d_origin;
+  a.tw_x = j->d_tw_x;
+  a.tw_y = j->d_tw_y;
+  a.px = j->d_px;
+  a.py = j->d_py;
+  a.nx = hp.nx;
+  a.ny = hp.ny;
+  a.pnx = hp.pnx;
+  a.pny = hp.pny;
+  a.n_frames = hp.F;
+  a.n_probes = hp.P;
+  a.n_slices = hp.ns;
+  a.sigma = (float)hp.sigma;
+  a.plane_amp = (float)(1.0 / sqrt((double)hp.nx * hp.ny));
+  a.plane = hp.plane ? 1 : 0;
+  return a;
+}
+
+// Splat + all slices for frames [f_begin, f_end) (one or more frame batches).
+tacaw_status run_batch_range(tacaw_job* job, hipStream_t s, int f_begin, int f_end) {
+  const HostPlan& hp = job->hp;
+  for (int f0 = f_begin; f0 < f_end; f0 += hp.fb) {
+    const int fb = std::min(hp.fb, f_end - f0);
+    SplatArgs sa{};
+    sa.pos = job->d_pos;
+    sa.species = job->d_species;
+    sa.tile_start = job->d_tile_start;
+    sa.tile_atoms = job->d_tile_atoms;
+    sa.coef = job->d_coef;
+    sa.V = job->d_V;
+    sa.n_atoms = hp.A;
+    sa.f0 = f0;
+    sa.fb = fb;
+    sa.n_slices = hp.ns;
+    sa.pnx = hp.pnx;
+    sa.pny = hp.pny;
+    sa.tiles_x = hp.tiles_x;
+    sa.tiles_y = hp.tiles_y;
+    sa.rcx = hp.rcx;
+    sa.rcy = hp.rcy;
+    sa.img_x = hp.img_x;
+    sa.img_y = hp.img_y;
+    tacaw_status st = timed(job, TACAW_K_SPLAT, s, [&] { return launch_splat(sa, s); });
+    if (st != TACAW_OK) return st;
+    PassArgs a = pass_args(job);
+    a.f0 = f0;
+    a.fb = fb;
+    for (int sl = 0; sl < hp.ns; ++sl) {
+      a.slice = sl;
+      const int rmode = sl == 0 ? ROW_FIRST : ROW_REGULAR;
+      st = timed(job, TACAW_K_ROW, s, [&] { return launch_row_pass(a, rmode, s); });
+      if (st != TACAW_OK) return st;
+      const bool last = sl == hp.ns - 1;
+      PassArgs ca = a;
+      if (last) {
+        ca.px = job->d_px_last;
+        ca.py = job->d_py_last;
+      }
+      st = timed(job, TACAW_K_COL, s, [&] { return launch_col_pass(ca, last ? COL_LAST : COL_REGULAR, s); });
+      if (st != TACAW_OK) return st;
+    }
+  }
+  return TACAW_OK;
+}
+
+tacaw_status run_time_stage(tacaw_job* job, hipStream_t s) {
+  const HostPlan& hp = job->hp;
+  TimeArgs t{};
+  t.exit = job->d_exit;
+  t.spec = job->d_spec;
+  t.tw = job->d_tw_t;
+  t.n_k = hp.nx * hp.ny;
+  t.n_frames = hp.F;
+  t.n_bins = hp.M;
+  t.n_probes = hp.P;
+  t.kt = time_stage_kt(hp.F, t.n_k);
+  t.inv_f2 = (float)(1.0 / ((double)hp.F * hp.F));
+  return timed(job, TACAW_K_TIME, s, [&] { return launch_time_stage(t, s); });
+}
+
+}  // namespace tacaw
+
+extern "C" {
+
+const char* tacaw_last_error(void) { return last_error_text(); }
+
+const char* tacaw_version(void) { return "libtacaw 0.1 (gfx950)"; }
+
+tacaw_status tacaw_ctx_create(int device, size_t hbm_budget_bytes, tacaw_ctx** out) {
+  clear_error();
+  if (!out) {
+    set_error("out is NULL");
+    return TACAW_EINVAL;
+  }
+  *out = nullptr;
+  int n = 0;
+  HIP_TRY(hipGetDeviceCount(&n));
+  if (device < 0 || device >= n) {
+    set_error("device %d not in [0, %d)", device, n);
+    return TACAW_EINVAL;
+  }
+  HIP_TRY(hipSetDevice(device));
+  size_t fr = 0, tot = 0;
+  HIP_TRY(hipMemGetInfo(&fr, &tot));
+  tacaw_ctx* c = new tacaw_ctx();
+  c->device = device;
+  c->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)fr);
+  *out = c;
+  return TACAW_OK;
+}
+
+void tacaw_serve_shutdown(tacaw_ctx* c);
+
+tacaw_status tacaw_ctx_destroy(tacaw_ctx* c) {
+  clear_error();
+  if (!c) return TACAW_OK;
+  tacaw_serve_shutdown(c);
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    drain_records(c);
+    for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
+    c->event_pool.clear();
+  }
+  delete c;
+  return TACAW_OK;
+}
+
+tacaw_status tacaw_job_footprint(const tacaw_job_desc* d, size_t* bytes) {
+  clear_error();
+  tacaw_status st = validate_desc(d);
+  if (st != TACAW_OK) return st;
+  if (!bytes) {
+    set_error("bytes is NULL");
+    return TACAW_EINVAL;
+  }
+  // tile lists are not known before planning: bound them by 32 entries per atom
+  *bytes = footprint_of(d, choose_frame_batch(d), (size_t)d->n_atoms * 32 + 1).total();
+  return TACAW_OK;
+}
+
+tacaw_status tacaw_job_create(tacaw_ctx* ctx, const tacaw_job_desc* d, const int32_t* atom_species,
+                              const double* positions, tacaw_job** out) {
+  clear_error();
+  if (!ctx || !out) {
+    set_error("ctx and out must not be NULL");
+    return TACAW_EINVAL;
+  }
+  *out = nullptr;
+  tacaw_status st = validate_desc(d);
+  if (st != TACAW_OK) return st;
+  if (d->n_atoms > 0 && (!atom_species || !positions)) {
+    set_error("atom_species and positions must not be NULL when n_atoms > 0");
+    return TACAW_EINVAL;
+  }
+  HIP_TRY(hipSetDevice(ctx->device));
+  tacaw_job* j = new tacaw_job();
+  j->ctx = ctx;
+  j->desc = *d;
+  const bool plane = d->aperture_mrad == 0.0;
+  if (!plane) j->probe_xy.assign(d->probe_xy, d->probe_xy + 2 * (size_t)d->n_probes);
+  j->species_Z.assign(d->species_Z, d->species_Z + d->n_species);
+  j->gauss_a.assign(d->gauss_a, d->gauss_a + (size_t)d->n_species * TACAW_N_GAUSS);
+  j->gauss_b.assign(d->gauss_b, d->gauss_b + (size_t)d->n_species * TACAW_N_GAUSS);
+  j->desc.probe_xy = plane ? nullptr : j->probe_xy.data();
+  j->desc.species_Z = j->species_Z.data();
+  j->desc.gauss_a = j->gauss_a.data();
+  j->desc.gauss_b = j->gauss_b.data();
+  if (plane) j->desc.n_probes = 1;
+
+  static const double no_pos[1] = {0.0};
+  static const int32_t no_sp[1] = {0};
+  st = plan_job(&j->desc, d->n_atoms ? atom_species : no_sp, d->n_atoms ? positions : no_pos, j->hp);
+  if (st != TACAW_OK) {
+    delete j;
+    return st;
+  }
+  HostPlan& hp = j->hp;
+  j->fp = footprint_of(&j->desc, hp.fb, hp.tile_atoms.size());
+  if (j->fp.total() > ctx->budget) {
+    set_error("job needs %.3f GiB of device memory, above the context budget of %.3f GiB",
+              j->fp.total() / 1073741824.0, ctx->budget / 1073741824.0);
+    delete j;
+    return TACAW_ENOMEM;
+  }
+
+  auto fail = [&](const char* what, hipError_t e) {
+    set_error("%s: %s", what, hipGetErrorString(e));
+    free_job_buffers(j);
+    delete j;
+    return e == hipErrorOutOfMemory ? TACAW_ENOMEM : TACAW_EDEVICE;
+  };
+  hipError_t e;
+  const size_t nk = (size_t)hp.nx * hp.ny;
+#define ALLOC(ptr, count) \
+  if ((e = dalloc(&(ptr), (count))) != hipSuccess) return fail("hipMalloc " #ptr, e);
+  ALLOC(j->d_exit, (size_t)hp.P * hp.F * nk);
+  ALLOC(j->d_spec, (size_t)hp.P * hp.M * nk);
+  ALLOC(j->d_V, (size_t)hp.fb * hp.ns * hp.pnx * hp.pny);
+  ALLOC(j->d_pos, (size_t)hp.F * hp.A);
+  ALLOC(j->d_species, (size_t)hp.A);
+  ALLOC(j->d_tile_start, hp.tile_start.size());
+  ALLOC(j->d_tile_atoms, hp.tile_atoms.size());
+  ALLOC(j->d_coef, hp.coef.size());
+  ALLOC(j->d_tw_x, (size_t)hp.nx);
+  ALLOC(j->d_tw_y, (size_t)hp.ny);
+  ALLOC(j->d_tw_t, (size_t)hp.F);
+  ALLOC(j->d_px, (size_t)hp.nx);
+  ALLOC(j->d_py, (size_t)hp.ny);
+  ALLOC(j->d_px_last, (size_t)hp.nx);
+  ALLOC(j->d_py_last, (size_t)hp.ny);
+  ALLOC(j->d_origin, (size_t)hp.P * 2);
+  ALLOC(j->d_rloc, (size_t)hp.P * 2);
+  ALLOC(j->d_count, 1);
+  if (!hp.plane) ALLOC(j->d_probe0, (size_t)hp.P * nk);
+#undef ALLOC
+
+  // uploads (synchronous; inputs are copied so the caller keeps its arrays)
+  if (hp.A > 0) {
+    std::vector<AtomPos> enc((size_t)hp.F * hp.A);
+    encode_positions(hp, positions, 0, hp.F, enc.data());
+    if ((e = hipMemcpy(j->d_pos, enc.data(), enc.size() * sizeof(AtomPos), hipMemcpyHostToDevice)) != hipSuccess)
+      return fail("upload positions", e);
+    if ((e = hipMemcpy(j->d_species, hp.sorted_species.data(), hp.A * sizeof(int32_t), hipMemcpyHostToDevice)) !=
+        hipSuccess)
+      return fail("upload species", e);
+  }
+  if ((e = hipMemcpy(j->d_tile_start, hp.tile_start.data(), hp.tile_start.size() * sizeof(int32_t),
+                     hipMemcpyHostToDevice)) != hipSuccess)
+    return fail("upload tiles", e);
+  if (!hp.tile_atoms.empty() &&
+      (e = hipMemcpy(j->d_tile_atoms, hp.tile_atoms.data(), hp.tile_atoms.size() * sizeof(int32_t),
+                     hipMemcpyHostToDevice)) != hipSuccess)
+    return fail("upload tile atoms", e);
+  if ((e = hipMemcpy(j->d_coef, hp.coef.data(), hp.coef.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess)
+    return fail("upload coefficients", e);
+  if ((e = hipMemcpy(j->d_origin, hp.origin.data(), hp.origin.size() * sizeof(int32_t), hipMemcpyHostToDevice)) !=
+      hipSuccess)
+    return fail("upload origins", e);
+  if ((e = hipMemcpy(j->d_rloc, hp.rloc.data(), hp.rloc.size() * sizeof(double), hipMemcpyHostToDevice)) !=
+      hipSuccess)
+    return fail("upload probe positions", e);
+
+  // tables and incident probes on the device (null stream, then synchronise)
+  hipStream_t s0 = nullptr;
+  const double sx = 1.0 / hp.nx, sy = 1.0 / hp.ny;
+  const double lx = 1.0 / sqrt((double)hp.nx), ly = 1.0 / sqrt((double)hp.ny);
+  if ((e = launch_twiddles(j->d_tw_x, hp.nx, s0)) != hipSuccess) return fail("twiddles", e);
+  if ((e = launch_twiddles(j->d_tw_y, hp.ny, s0)) != hipSuccess) return fail("twiddles", e);
+  if ((e = launch_twiddles(j->d_tw_t, hp.F, s0)) != hipSuccess) return fail("twiddles", e);
+  if ((e = launch_prop_factor(j->d_px, hp.nx, hp.dx, hp.lam, hp.dz, sx, s0)) != hipSuccess) return fail("prop", e);
+  if ((e = launch_prop_factor(j->d_py, hp.ny, hp.dy, hp.lam, hp.dz, sy, s0)) != hipSuccess) return fail("prop", e);
+  if ((e = launch_prop_factor(j->d_px_last, hp.nx, hp.dx, hp.lam, hp.dz, lx, s0)) != hipSuccess)
+    return fail("prop", e);
+  if ((e = launch_prop_factor(j->d_py_last, hp.ny, hp.dy, hp.lam, hp.dz, ly, s0)) != hipSuccess)
+    return fail("prop", e);
+  if (!hp.plane) {
+    if ((e = hipMemset(j->d_count, 0, sizeof(int))) != hipSuccess) return fail("memset", e);
+    if ((e = launch_aperture_count(j->d_count, hp.nx, hp.ny, hp.dx, hp.dy, hp.lam, hp.alpha, s0)) != hipSuccess)
+      return fail("aperture", e);
+    if ((e = launch_probe_fill(j->d_probe0, j->d_rloc, j->d_count, hp.P, hp.nx, hp.ny, hp.dx, hp.dy, hp.lam,
+                               hp.alpha, s0)) != hipSuccess)
+      return fail("probe fill", e);
+    PassArgs a = pass_args(j);
+    a.exit = j->d_probe0;
+    a.n_frames = 1;
+    a.f0 = 0;
+    a.fb = 1;
+    if ((e = launch_col_pass(a, COL_INVERSE_ONLY, s0)) != hipSuccess) return fail("probe iFFT_y", e);
+    if ((e = launch_row_pass(a, ROW_INVERSE_ONLY, s0)) != hipSuccess) return fail("probe iFFT_x", e);
+  }
+  if ((e = hipDeviceSynchronize()) != hipSuccess) return fail("job setup", e);
+  *out = j;
+  return TACAW_OK;
+}
+
+tacaw_status tacaw_run(tacaw_job* job, void* hip_stream) {
+  clear_error();
+  if (!job) {
+    set_error("job is NULL");
+    return TACAW_EINVAL;
+  }
+  const int ss = job->serve_state.load();
+  if (ss == 1 || ss == 2) {
+    set_error("job is in the serving loop");
+    return TACAW_EBUSY;
+  }
+  HIP_TRY(hipSetDevice(job->ctx->device));
+  hipStream_t s = (hipStream_t)hip_stream;
+  job->last_stream = s;
+  tacaw_status st = run_batch_range(job, s, 0, job->hp.F);
+  if (st != TACAW_OK) return st;
+  st = run_time_stage(job, s);
+  if (st != TACAW_OK) return st;
+  job->has_result = true;
+  return TACAW_OK;
+}
+
+static tacaw_status copy_out(tacaw_job* job, void* dst, const void* src, size_t bytes, int on_device) {
+  if (on_device) {
+    HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, job->last_stream));
+    HIP_TRY(hipStreamSynchronize(job->last_stream));
+  } else {
+    HIP_TRY(hipStreamSynchronize(job->last_stream));
+    HIP_TRY(hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost));
+  }
+  return TACAW_OK;
+}
+
+tacaw_status tacaw_get_spectrum(tacaw_job* job, float* dst, size_t n, int dst_on_device) {
+  clear_error();
+  if (!job || !dst) {
+    set_error("job and dst must not be NULL");
+    return TACAW_EINVAL;
+  }
+  const int ss = job->serve_state.load();
+  if (ss == 1 || ss == 2) {
+    set_error("job is still in the serving loop");
+    return TACAW_EBUSY;
+  }
+  if (ss == 4) {
+    set_error("job was cancelled");
+    return TACAW_ECANCELLED;
+  }
+  if (!job->has_result) {
+    set_error("job has not been run");
+    return TACAW_ENOTREADY;
+  }
+  const HostPlan& hp = job->hp;
+  const size_t need = (size_t)hp.P * hp.M * hp.nx * hp.ny;
+  if (n != need) {
+    set_error("spectrum has %zu values, dst holds %zu", need, n);
+    return TACAW_EINVAL;
+  }
+  HIP_TRY(hipSetDevice(job->ctx->device));
+  return copy_out(job, dst, job->d_spec, need * sizeof(float), dst_on_device);
+}
+
+tacaw_status tacaw_get_exit_waves(tacaw_job* job, void* dst, size_t n, int dst_on_device) {
+  clear_error();
+  if (!job || !dst) {
+    set_error("job and dst must not be NULL");
+    return TACAW_EINVAL;
+  }
+  if (!(job->desc.flags & TACAW_KEEP_EXIT_WAVES)) {
+    set_error("job was created without TACAW_KEEP_EXIT_WAVES");
+    return TACAW_EINVAL;
+  }
+  const int ss = job->serve_state.load();
+  if (ss == 1 || ss == 2) {
+    set_error("job is still in the serving loop");
+    return TACAW_EBUSY;
+  }
+  if (!job->has_result) {
+    set_error("job has not been run");
+    return TACAW_ENOTREADY;
+  }
+  const HostPlan& hp = job->hp;
+  const size_t need = (size_t)hp.P * hp.F * hp.nx * hp.ny;
+  if (n != need) {
+    set_error("exit-wave store has %zu complex values, dst holds %zu", need, n);
+    return TACAW_EINVAL;
+  }
+  HIP_TRY(hipSetDevice(job->ctx->device));
+  return copy_out(job, dst, job->d_exit, need * sizeof(float2), dst_on_device);
+}
+
+tacaw_status tacaw_axes(const tacaw_job_desc* d, double* kx, double* ky, double* f) {
+  clear_error();
+  tacaw_status st = validate_desc(d);
+  if (st != TACAW_OK && st != TACAW_EUNSUPPORTED) return st;
+  const int pnx = d->pot_nx > 0 ? d->pot_nx : d->nx;
+  const int pny = d->pot_ny > 0 ? d->pot_ny : d->ny;
+  const double dx = d->cell[0] / pnx, dy = d->cell[1] / pny;
+  auto fill = [](double* out, int n, double dd) {
+    const double val = 1.0 / ((double)n * dd);
+    for (int i = 0; i < n; ++i) out[i] = (double)((i < (n + 1) / 2) ? i : i - n) * val;
+  };
+  if (kx) fill(kx, d->nx, dx);
+  if (ky) fill(ky, d->ny, dy);
+  if (f) {
+    const int F = d->n_frames;
+    const bool two = (d->flags & TACAW_TWO_SIDED) != 0;
+    const int M = two ? F : F / 2;
+    const double val = 1.0 / ((double)F * (d->dt_fs * 1e-3));
+    for (int m = 0; m < M; ++m) f[m] = (double)((m < (F + 1) / 2) ? m : m - F) * val;
+  }
+  return TACAW_OK;
+}
+
+tacaw_status tacaw_job_slices(const tacaw_job* job, int32_t* out, size_t n) {
+  clear_error();
+  if (!job || (!out && n)) {
+    set_error("job and out must not be NULL");
+    return TACAW_EINVAL;
+  }
+  if (n != job->hp.slice_of.size()) {
+    set_error("job has %zu atoms, out holds %zu", job->hp.slice_of.size(), n);
+    return TACAW_EINVAL;
+  }
+  std::copy(job->hp.slice_of.begin(), job->hp.slice_of.end(), out);
+  return TACAW_OK;
+}
+
+tacaw_status tacaw_job_destroy(tacaw_job* job) {
+  clear_error();
+  if (!job) return TACAW_OK;
+  const int ss = job->serve_state.load();
+  if (ss == 1 || ss == 2) {
+    set_error("job is in the serving loop: cancel and wait first");
+    return TACAW_EBUSY;
+  }
+  (void)hipSetDevice(job->ctx->device);
+  (void)hipDeviceSynchronize();
+  free_job_buffers(job);
+  delete job;
+  return TACAW_OK;
+}
+
+tacaw_status tacaw_timing_enable(tacaw_ctx* c, int on) {
+  clear_error();
+  if (!c) {
+    set_error("ctx is NULL");
+    return TACAW_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(c->mu);
+  drain_records(c);
+  c->timing = on != 0;
+  if (on)
+    for (int i = 0; i < TACAW_K_COUNT; ++i) {
+      c->total_ms[i] = 0.0;
+      c->launches[i] = 0;
+    }
+  return TACAW_OK;
+}
+
+tacaw_status tacaw_timing_get(tacaw_ctx* c, int cls, double* total_ms, int64_t* launches) {
+  clear_error();
+  if (!c || cls < 0 || cls >= TACAW_K_COUNT) {
+    set_error("bad context or kernel class");
+    return TACAW_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(c->mu);
+  drain_records(c);
+  if (total_ms) *total_ms = c->total_ms[cls];
+  if (launches) *launches = c->launches[cls];
+  return TACAW_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,373 @@
+// Host planner: validation, constants, slice binning, position encoding,
+// splat candidate lists, probe windows and device footprint (FP64 on the host).
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <numeric>
+
+#include "runtime.h"
+
+namespace tacaw {
+
+// CODATA 2018 (SI)
+static const double kH = 6.62607015e-34;
+static const double kMe = 9.1093837015e-31;
+static const double kQe = 1.602176634e-19;
+static const double kC = 299792458.0;
+static const double kBohrA = 0.529177210903;        // A
+static const double kCoulombEVA = 14.399645478425668;  // e^2 / (4 pi eps0) in eV A
+
+static thread_local char g_err[1024];
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+void clear_error() { g_err[0] = 0; }
+const char* last_error_text() { return g_err; }
+
+// Relativistic wavelength lambda = h / sqrt(2 m0 e E (1 + e E / (2 m0 c^2))), in A
+// (Methods 2.2, Multislice Propagation: "m_e includes relativistic corrections").
+double wavelength_A(double volt) {
+  const double ej = kQe * volt;
+  const double p = sqrt(2.0 * kMe * ej * (1.0 + ej / (2.0 * kMe * kC * kC)));
+  return kH / p * 1e10;
+}
+
+// sigma = 2 pi gamma m0 e lambda / h^2 in rad / (V A).  The paper prints the
+// interaction parameter without the electron charge; it is restored here.
+double sigma_rad_per_VA(double volt) {
+  const double gamma = 1.0 + kQe * volt / (kMe * kC * kC);
+  const double lam = wavelength_A(volt) * 1e-10;
+  return 2.0 * M_PI * gamma * kMe * kQe * lam / (kH * kH) * 1e-10;
+}
+
+static bool smooth235(int n) {
+  if (n < 1) return false;
+  for (int p : {2, 3, 5})
+    while (n % p == 0) n /= p;
+  return n == 1;
+}
+
+tacaw_status validate_desc(const tacaw_job_desc* d) {
+  if (!d) {
+    set_error("job description is NULL");
+    return TACAW_EINVAL;
+  }
+  for (int i = 0; i < 3; ++i)
+    if (!(d->cell[i] > 0.0) || !isfinite(d->cell[i])) {
+      set_error("cell[%d] must be a positive finite length (got %g)", i, d->cell[i]);
+      return TACAW_EINVAL;
+    }
+  if (d->nx <= 0 || d->ny <= 0 || !smooth235(d->nx) || !smooth235(d->ny)) {
+    set_error("grid %dx%d: each side must be a positive product of 2, 3 and 5", d->nx, d->ny);
+    return TACAW_EINVAL;
+  }
+  if (d->n_slices < 1) {
+    set_error("n_slices must be >= 1 (got %d)", d->n_slices);
+    return TACAW_EINVAL;
+  }
+  if (!(d->voltage_V > 0.0) || !isfinite(d->voltage_V)) {
+    set_error("voltage_V must be positive (got %g)", d->voltage_V);
+    return TACAW_EINVAL;
+  }
+  if (!(d->dt_fs > 0.0) || !isfinite(d->dt_fs)) {
+    set_error("dt_fs must be positive (got %g)", d->dt_fs);
+    return TACAW_EINVAL;
+  }
+  if (d->n_frames < 2 || !smooth235(d->n_frames)) {
+    set_error("n_frames must be >= 2 and a product of 2, 3 and 5 (got %d)", d->n_frames);
+    return TACAW_EINVAL;
+  }
+  if (d->n_frames > 2048) {
+    set_error("n_frames %d above the 2048 this build's time stage holds in LDS", d->n_frames);
+    return TACAW_EUNSUPPORTED;
+  }
+  if (d->n_atoms < 0) {
+    set_error("n_atoms must be >= 0");
+    return TACAW_EINVAL;
+  }
+  if (d->n_species < 1 || !d->gauss_a || !d->gauss_b || !d->species_Z) {
+    set_error("need n_species >= 1 with species_Z, gauss_a and gauss_b");
+    return TACAW_EINVAL;
+  }
+  for (int i = 0; i < d->n_species * TACAW_N_GAUSS; ++i)
+    if (!(d->gauss_a[i] > 0.0) || !(d->gauss_b[i] > 0.0) || !isfinite(d->gauss_a[i]) ||
+        !isfinite(d->gauss_b[i])) {
+      set_error("gauss_a and gauss_b must be positive and finite (entry %d)", i);
+      return TACAW_EINVAL;
+    }
+  if (d->aperture_mrad < 0.0 || !isfinite(d->aperture_mrad)) {
+    set_error("aperture_mrad must be >= 0");
+    return TACAW_EINVAL;
+  }
+  const bool plane = d->aperture_mrad == 0.0;
+  const int pnx = d->pot_nx > 0 ? d->pot_nx : d->nx;
+  const int pny = d->pot_ny > 0 ? d->pot_ny : d->ny;
+  const bool windowed = pnx != d->nx || pny != d->ny;
+  if (windowed) {
+    if (plane) {
+      set_error("a plane wave covers the cell: pot_nx/pot_ny must be 0 or equal nx/ny");
+      return TACAW_EINVAL;
+    }
+    if (pnx < d->nx || pny < d->ny) {
+      set_error("window %dx%d larger than the potential grid %dx%d", d->nx, d->ny, pnx, pny);
+      return TACAW_EINVAL;
+    }
+  }
+  if (!plane) {
+    if (d->n_probes < 1 || !d->probe_xy) {
+      set_error("a probe needs n_probes >= 1 and probe_xy");
+      return TACAW_EINVAL;
+    }
+    for (int i = 0; i < 2 * d->n_probes; ++i)
+      if (!isfinite(d->probe_xy[i])) {
+        set_error("probe_xy[%d] is not finite", i);
+        return TACAW_EINVAL;
+      }
+    const double dx = d->cell[0] / pnx, dy = d->cell[1] / pny;
+    const double kny = 0.5 / std::max(dx, dy);
+    const double ka = d->aperture_mrad * 1e-3 / wavelength_A(d->voltage_V);
+    if (ka >= kny) {
+      set_error("probe aperture alpha/lambda = %.4f 1/A does not fit below the Nyquist frequency %.4f 1/A",
+                ka, kny);
+      return TACAW_EINVAL;
+    }
+  }
+  if (!grid_supported(d->nx) || !grid_supported(d->ny)) {
+    set_error("grid %dx%d: this build has kernels for 16, 32, 48, 64, 96, 128, 160, 192, 256, 320, "
+              "384, 512, 640, 768, 1024",
+              d->nx, d->ny);
+    return TACAW_EUNSUPPORTED;
+  }
+  return TACAW_OK;
+}
+
+// Frames whose potentials are materialised at once: up to ~4 GiB of V.
+int choose_frame_batch(const tacaw_job_desc* d) {
+  const int pnx = d->pot_nx > 0 ? d->pot_nx : d->nx;
+  const int pny = d->pot_ny > 0 ? d->pot_ny : d->ny;
+  const double per_frame = (double)d->n_slices * pnx * pny * sizeof(float);
+  double budget = 4.0 * (1ull << 30);
+  if (const char* e = getenv("TACAW_V_BUDGET_MB")) budget = atof(e) * (1 << 20);
+  int fb = (int)std::max(1.0, floor(budget / per_frame));
+  return std::min(fb, d->n_frames);
+}
+
+Footprint footprint_of(const tacaw_job_desc* d, int fb, size_t n_tile_atoms) {
+  Footprint f;
+  const bool plane = d->aperture_mrad == 0.0;
+  const size_t P = plane ? 1 : (size_t)d->n_probes;
+  const size_t nk = (size_t)d->nx * d->ny;
+  const int pnx = d->pot_nx > 0 ? d->pot_nx : d->nx;
+  const int pny = d->pot_ny > 0 ? d->pot_ny : d->ny;
+  const size_t M = (d->flags & TACAW_TWO_SIDED) ? d->n_frames : d->n_frames / 2;
+  f.exit = P * d->n_frames * nk * sizeof(float2);
+  f.spec = P * M * nk * sizeof(float);
+  f.V = (size_t)fb * d->n_slices * pnx * pny * sizeof(float);
+  f.pos = (size_t)d->n_frames * d->n_atoms * sizeof(AtomPos) + (size_t)d->n_atoms * sizeof(int32_t);
+  f.tiles = n_tile_atoms * sizeof(int32_t);
+  f.probes = plane ? 0 : P * nk * sizeof(float2) + P * (2 * sizeof(int32_t) + 2 * sizeof(double));
+  f.tables = (size_t)(2 * d->nx + 2 * d->ny + d->nx + d->ny + d->n_frames) * sizeof(float2) +
+             (size_t)d->n_species * N_GAUSS * 3 * sizeof(float) + 64;
+  return f;
+}
+
+static inline double wrap_min_image(double d, double L) { return d - L * nearbyint(d / L); }
+
+tacaw_status plan_job(const tacaw_job_desc* d, const int32_t* atom_species, const double* pos,
+                      HostPlan& hp) {
+  hp.nx = d->nx;
+  hp.ny = d->ny;
+  hp.pnx = d->pot_nx > 0 ? d->pot_nx : d->nx;
+  hp.pny = d->pot_ny > 0 ? d->pot_ny : d->ny;
+  hp.ns = d->n_slices;
+  hp.F = d->n_frames;
+  hp.A = d->n_atoms;
+  hp.S = d->n_species;
+  hp.plane = d->aperture_mrad == 0.0;
+  hp.P = hp.plane ? 1 : d->n_probes;
+  hp.windowed = hp.pnx != hp.nx || hp.pny != hp.ny;
+  hp.two_sided = (d->flags & TACAW_TWO_SIDED) != 0;
+  hp.M = hp.two_sided ? hp.F : hp.F / 2;
+  hp.lx = d->cell[0];
+  hp.ly = d->cell[1];
+  hp.lz = d->cell[2];
+  hp.dx = hp.lx / hp.pnx;
+  hp.dy = hp.ly / hp.pny;
+  hp.dz = hp.lz / hp.ns;
+  hp.lam = wavelength_A(d->voltage_V);
+  hp.sigma = sigma_rad_per_VA(d->voltage_V);
+  hp.alpha = d->aperture_mrad * 1e-3;
+  hp.fb = choose_frame_batch(d);
+
+  for (int j = 0; j < hp.A; ++j)
+    if (atom_species[j] < 0 || atom_species[j] >= hp.S) {
+      set_error("atom %d has species index %d outside [0, %d)", j, atom_species[j], hp.S);
+      return TACAW_EINVAL;
+    }
+  for (size_t i = 0; i < (size_t)hp.F * hp.A * 3; ++i)
+    if (!isfinite(pos[i])) {
+      set_error("positions[%zu] is not finite", i);
+      return TACAW_EINVAL;
+    }
+
+  // Slice binning by the FP64 frame-mean z; half-open slices, clamped.
+  hp.slice_of.assign(hp.A, 0);
+  std::vector<double> zbar(hp.A, 0.0);
+  for (int f = 0; f < hp.F; ++f)
+    for (int j = 0; j < hp.A; ++j) zbar[j] += pos[((size_t)f * hp.A + j) * 3 + 2];
+  for (int j = 0; j < hp.A; ++j) {
+    const double z = zbar[j] / (double)hp.F;
+    double zm = fmod(z, hp.lz);
+    if (zm != 0.0 && zm < 0.0) zm += hp.lz;
+    long s = (long)floor(zm / hp.dz);
+    if (s < 0) s = 0;
+    if (s > hp.ns - 1) s = hp.ns - 1;
+    hp.slice_of[j] = (int32_t)s;
+  }
+  hp.order.resize(hp.A);
+  std::iota(hp.order.begin(), hp.order.end(), 0);
+  std::stable_sort(hp.order.begin(), hp.order.end(),
+                   [&](int a, int b) { return hp.slice_of[a] < hp.slice_of[b]; });
+  std::vector<int32_t> slice_start(hp.ns + 1, 0);
+  for (int j = 0; j < hp.A; ++j) slice_start[hp.slice_of[j] + 1]++;
+  for (int s = 0; s < hp.ns; ++s) slice_start[s + 1] += slice_start[s];
+  hp.sorted_species.resize(hp.A);
+  for (int j = 0; j < hp.A; ++j) hp.sorted_species[j] = atom_species[hp.order[j]];
+
+  // Truncation radius: exp(-pi^2 r^2 / b) <= 1e-8 for the widest term.
+  double bmax = 0.0;
+  for (int i = 0; i < hp.S * TACAW_N_GAUSS; ++i) bmax = std::max(bmax, d->gauss_b[i]);
+  hp.rc = sqrt(bmax * log(1e8)) / M_PI;
+  hp.rcx = (float)(hp.rc / hp.dx);
+  hp.rcy = (float)(hp.rc / hp.dy);
+  auto images = [](double rcp, int n) {
+    if (rcp < n / 2 - 1) return 0;
+    return (int)ceil((rcp + n / 2 + 1) / n);
+  };
+  hp.img_x = images(hp.rcx, hp.pnx);
+  hp.img_y = images(hp.rcy, hp.pny);
+
+  // Per-species coefficients: amplitude C a pi / b (V A), exp2 factors per
+  // pixel^2 along x and y.
+  const double cpref = 2.0 * M_PI * kBohrA * kCoulombEVA;
+  hp.coef.resize((size_t)hp.S * N_GAUSS * 3);
+  for (int s = 0; s < hp.S; ++s)
+    for (int i = 0; i < N_GAUSS; ++i) {
+      const double a = d->gauss_a[s * N_GAUSS + i], b = d->gauss_b[s * N_GAUSS + i];
+      const double c = M_PI * M_PI / b;
+      float* o = &hp.coef[((size_t)s * N_GAUSS + i) * 3];
+      o[0] = (float)(cpref * a * M_PI / b);
+      o[1] = (float)(c * hp.dx * hp.dx / M_LN2);
+      o[2] = (float)(c * hp.dy * hp.dy / M_LN2);
+    }
+
+  // Candidate atoms per (slice, tile): every atom whose mean position, widened
+  // by the truncation radius and the largest displacement from that mean, can
+  // reach the tile (box test per axis, periodic).
+  std::vector<double> xbar(hp.A), ybar(hp.A);
+  double dmx = 0.0, dmy = 0.0;
+  for (int j = 0; j < hp.A; ++j) {
+    const double x0 = pos[(size_t)j * 3], y0 = pos[(size_t)j * 3 + 1];
+    double sx = 0.0, sy = 0.0;
+    for (int f = 0; f < hp.F; ++f) {
+      sx += wrap_min_image(pos[((size_t)f * hp.A + j) * 3] - x0, hp.lx);
+      sy += wrap_min_image(pos[((size_t)f * hp.A + j) * 3 + 1] - y0, hp.ly);
+    }
+    xbar[j] = x0 + sx / hp.F;
+    ybar[j] = y0 + sy / hp.F;
+  }
+  for (int f = 0; f < hp.F; ++f)
+    for (int j = 0; j < hp.A; ++j) {
+      dmx = std::max(dmx, fabs(wrap_min_image(pos[((size_t)f * hp.A + j) * 3] - xbar[j], hp.lx)));
+      dmy = std::max(dmy, fabs(wrap_min_image(pos[((size_t)f * hp.A + j) * 3 + 1] - ybar[j], hp.ly)));
+    }
+  hp.tiles_x = (hp.pnx + SPLAT_TX - 1) / SPLAT_TX;
+  hp.tiles_y = (hp.pny + SPLAT_TY - 1) / SPLAT_TY;
+  const int nt = hp.tiles_x * hp.tiles_y;
+  const double reach_x = hp.rc + dmx + 2.0 * hp.dx;
+  const double reach_y = hp.rc + dmy + 2.0 * hp.dy;
+  hp.tile_start.assign((size_t)hp.ns * nt + 1, 0);
+  hp.tile_atoms.clear();
+  // per-axis lists: which tiles along x (resp. y) each atom reaches
+  std::vector<std::vector<int>> tx_of(hp.A), ty_of(hp.A);
+  for (int j = 0; j < hp.A; ++j) {
+    const int oj = hp.order[j];
+    for (int tx = 0; tx < hp.tiles_x; ++tx) {
+      const double a0 = tx * SPLAT_TX * hp.dx;
+      const double a1 = (std::min((tx + 1) * SPLAT_TX, hp.pnx) - 1) * hp.dx;
+      const double c = 0.5 * (a0 + a1), h = 0.5 * (a1 - a0);
+      const double dist = fabs(wrap_min_image(xbar[oj] - c, hp.lx)) - h;
+      if (dist <= reach_x) tx_of[j].push_back(tx);
+    }
+    for (int ty = 0; ty < hp.tiles_y; ++ty) {
+      const double a0 = ty * SPLAT_TY * hp.dy;
+      const double a1 = (std::min((ty + 1) * SPLAT_TY, hp.pny) - 1) * hp.dy;
+      const double c = 0.5 * (a0 + a1), h = 0.5 * (a1 - a0);
+      const double dist = fabs(wrap_min_image(ybar[oj] - c, hp.ly)) - h;
+      if (dist <= reach_y) ty_of[j].push_back(ty);
+    }
+  }
+  std::vector<std::vector<int32_t>> bucket(nt);
+  for (int s = 0; s < hp.ns; ++s) {
+    for (auto& b : bucket) b.clear();
+    for (int j = slice_start[s]; j < slice_start[s + 1]; ++j)
+      for (int ty : ty_of[j])
+        for (int tx : tx_of[j]) bucket[ty * hp.tiles_x + tx].push_back(j);
+    for (int t = 0; t < nt; ++t) {
+      hp.tile_start[(size_t)s * nt + t] = (int32_t)hp.tile_atoms.size();
+      hp.tile_atoms.insert(hp.tile_atoms.end(), bucket[t].begin(), bucket[t].end());
+    }
+  }
+  hp.tile_start[(size_t)hp.ns * nt] = (int32_t)hp.tile_atoms.size();
+
+  // Probe windows: origin floor(r/d) - N/2 (wrapped for the crop); the probe
+  // sits at r - origin * d inside the window.
+  hp.origin.assign((size_t)hp.P * 2, 0);
+  hp.rloc.assign((size_t)hp.P * 2, 0.0);
+  if (!hp.plane) {
+    for (int p = 0; p < hp.P; ++p) {
+      const double rx = d->probe_xy[2 * p], ry = d->probe_xy[2 * p + 1];
+      if (hp.windowed) {
+        const long ox = (long)floor(rx / hp.dx) - hp.nx / 2;
+        const long oy = (long)floor(ry / hp.dy) - hp.ny / 2;
+        hp.origin[2 * p] = (int32_t)(((ox % hp.pnx) + hp.pnx) % hp.pnx);
+        hp.origin[2 * p + 1] = (int32_t)(((oy % hp.pny) + hp.pny) % hp.pny);
+        hp.rloc[2 * p] = rx - (double)ox * hp.dx;
+        hp.rloc[2 * p + 1] = ry - (double)oy * hp.dy;
+      } else {
+        hp.rloc[2 * p] = rx;
+        hp.rloc[2 * p + 1] = ry;
+      }
+    }
+  }
+  return TACAW_OK;
+}
+
+// Encode positions of frames [f0, f1) in sorted atom order: integer pixel and
+// sub-pixel offset on the potential grid.
+void encode_positions(const HostPlan& hp, const double* pos, int f0, int f1, AtomPos* out) {
+  for (int f = f0; f < f1; ++f)
+    for (int j = 0; j < hp.A; ++j) {
+      const double* p = pos + ((size_t)f * hp.A + hp.order[j]) * 3;
+      const double ux = p[0] / hp.dx, uy = p[1] / hp.dy;
+      const double fxl = floor(ux), fyl = floor(uy);
+      long ix = (long)fxl, iy = (long)fyl;
+      AtomPos a;
+      a.fx = (float)(ux - fxl);
+      a.fy = (float)(uy - fyl);
+      if (a.fx >= 1.0f) { a.fx = 0.0f; ix += 1; }  // rounding up to 1.0f
+      if (a.fy >= 1.0f) { a.fy = 0.0f; iy += 1; }
+      a.ix = (int32_t)(((ix % hp.pnx) + hp.pnx) % hp.pnx);
+      a.iy = (int32_t)(((iy % hp.pny) + hp.pny) % hp.pny);
+      out[(size_t)(f - f0) * hp.A + j] = a;
+    }
+}
+
+}  // namespace tacaw

@@ -1,0 +1,123 @@
+// Host runtime of libtacaw: context, job, planner.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "tacaw.h"
+#include "tacaw_internal.h"
+
+namespace tacaw {
+
+void set_error(const char* fmt, ...);
+void clear_error();
+
+// Everything the planner derives on the host from a job description and its
+// inputs (FP64), ready to upload.
+struct HostPlan {
+  int nx = 0, ny = 0, pnx = 0, pny = 0, ns = 0, F = 0, P = 0, A = 0, S = 0, M = 0;
+  bool plane = true, windowed = false, two_sided = false;
+  double lx = 0, ly = 0, lz = 0, dx = 0, dy = 0, dz = 0, lam = 0, sigma = 0, alpha = 0, rc = 0;
+  float rcx = 0, rcy = 0;
+  int img_x = 0, img_y = 0, tiles_x = 0, tiles_y = 0;
+  int fb = 1;                          // frames per batch
+  std::vector<int32_t> slice_of;       // per input atom
+  std::vector<int32_t> order;          // sorted position -> input atom
+  std::vector<int32_t> tile_start;     // [ns * tiles + 1]
+  std::vector<int32_t> tile_atoms;     // sorted-atom indices
+  std::vector<float> coef;             // [S][5][3]
+  std::vector<int32_t> sorted_species; // [A]
+  std::vector<int32_t> origin;         // [P][2] wrapped window origin
+  std::vector<double> rloc;            // [P][2] probe position relative to the window
+};
+
+// Device bytes of each buffer of a job.
+struct Footprint {
+  size_t exit = 0, spec = 0, V = 0, pos = 0, tiles = 0, probes = 0, tables = 0;
+  size_t total() const { return exit + spec + V + pos + tiles + probes + tables; }
+};
+
+tacaw_status validate_desc(const tacaw_job_desc* d);
+int choose_frame_batch(const tacaw_job_desc* d);
+Footprint footprint_of(const tacaw_job_desc* d, int fb, size_t n_tile_atoms_estimate);
+double wavelength_A(double volt);
+double sigma_rad_per_VA(double volt);
+tacaw_status plan_job(const tacaw_job_desc* d, const int32_t* atom_species, const double* positions,
+                      HostPlan& hp);
+
+struct TimingRecord {
+  int cls;
+  hipEvent_t start, stop;
+};
+
+struct JobState;
+
+struct tacaw_ctx_impl;
+
+}  // namespace tacaw
+
+struct tacaw_ctx {
+  int device = 0;
+  size_t budget = 0;
+  std::mutex mu;
+  size_t resident = 0;           // bytes held by jobs admitted by the serving loop
+  // timing
+  bool timing = false;
+  std::vector<tacaw::TimingRecord> records;
+  std::vector<hipEvent_t> event_pool;
+  double total_ms[TACAW_K_COUNT] = {0};
+  int64_t launches[TACAW_K_COUNT] = {0};
+  // serving loop
+  std::thread server;
+  std::condition_variable cv;
+  std::deque<tacaw_job*> queue;  // submitted, not yet admitted
+  std::vector<tacaw_job*> active;
+  bool stop = false;
+  bool server_started = false;
+  hipStream_t serve_stream = nullptr;
+};
+
+struct tacaw_job {
+  tacaw_ctx* ctx = nullptr;
+  tacaw_job_desc desc{};
+  std::vector<double> probe_xy;
+  std::vector<int32_t> species_Z;
+  std::vector<double> gauss_a, gauss_b;
+  tacaw::HostPlan hp;
+  tacaw::Footprint fp;
+  // device buffers
+  float2* d_exit = nullptr;
+  float* d_spec = nullptr;
+  float* d_V = nullptr;
+  tacaw::AtomPos* d_pos = nullptr;
+  int32_t* d_species = nullptr;
+  int32_t* d_tile_start = nullptr;
+  int32_t* d_tile_atoms = nullptr;
+  float* d_coef = nullptr;
+  float2* d_tw_x = nullptr;
+  float2* d_tw_y = nullptr;
+  float2* d_tw_t = nullptr;
+  float2* d_px = nullptr;        // regular slices
+  float2* d_py = nullptr;
+  float2* d_px_last = nullptr;   // last slice
+  float2* d_py_last = nullptr;
+  float2* d_probe0 = nullptr;
+  int32_t* d_origin = nullptr;
+  double* d_rloc = nullptr;
+  int* d_count = nullptr;
+  hipStream_t last_stream = nullptr;
+  bool has_result = false;
+  // serving state
+  std::atomic<int> serve_state{0};   // 0 idle, 1 queued, 2 running, 3 done, 4 cancelled, 5 failed
+  std::atomic<bool> cancel_req{false};
+  int next_frame = 0;                // serving: next frame batch start
+  int next_slice = 0;
+  double t_submit = 0, t_done = 0;
+};

@@ -1,0 +1,83 @@
+// Internal declarations shared by the host runtime and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tacaw {
+
+// Atom position of one frame, in pixel units of the potential grid: the
+// integer pixel (ix, iy) and the sub-pixel offset (fx, fy) in [0, 1).  The
+// split keeps FP32 distances exact to ~1e-7 pixel on any grid size.
+struct AtomPos {
+  int32_t ix, iy;
+  float fx, fy;
+};
+
+constexpr int N_GAUSS = 5;
+constexpr int SPLAT_TX = 64;   // splat tile: columns
+constexpr int SPLAT_TY = 16;   // splat tile: rows
+constexpr int SPLAT_MC = 16;   // candidate atoms staged in LDS per round
+constexpr int COL_CT = 8;      // columns per column-pass workgroup
+
+// Projected potentials of a batch of frames.
+struct SplatArgs {
+  const AtomPos* pos;          // [F][A], atoms sorted by slice
+  const int32_t* species;      // [A] species index, sorted order
+  const int32_t* tile_start;   // [n_slices * tiles + 1] CSR offsets
+  const int32_t* tile_atoms;   // sorted-atom indices
+  const float* coef;           // [S][5][3]: amplitude (V A), exp2 factor x, exp2 factor y
+  float* V;                    // [fb][n_slices][pny][pnx]
+  int n_atoms, f0, fb, n_slices, pnx, pny, tiles_x, tiles_y;
+  float rcx, rcy;              // truncation radius in pixels along x and y
+  int img_x, img_y;            // periodic images -img..img searched per axis
+};
+
+// One row or column pass over a batch of (probe, frame) waves.
+struct PassArgs {
+  float2* exit;                // [P][F][ny][nx] exit store, also the in-flight waves
+  const float* V;              // [fb][n_slices][pny][pnx]
+  const float2* probe0;        // [P][ny][nx] incident probes (real space)
+  const int32_t* origin;       // [P][2] window origin on the potential grid
+  const float2* tw_x;          // [nx] exp(-2 pi i m / nx)
+  const float2* tw_y;          // [ny]
+  const float2* px;            // [nx] propagator factor along kx (scaled)
+  const float2* py;            // [ny]
+  int nx, ny, pnx, pny, n_frames, f0, fb, n_probes, n_slices, slice;
+  float sigma;                 // interaction parameter [rad / (V A)]
+  float plane_amp;             // 1 / sqrt(nx ny)
+  int plane;                   // 1: plane-wave incident wave
+};
+
+struct TimeArgs {
+  const float2* exit;          // [P][F][n_k]
+  float* spec;                 // [P][M][n_k]
+  const float2* tw;            // [F] exp(-2 pi i m / F)
+  int n_k, n_frames, n_bins, n_probes, kt;
+  float inv_f2;                // 1 / F^2
+};
+
+enum RowMode { ROW_FIRST = 0, ROW_REGULAR = 1, ROW_INVERSE_ONLY = 2 };
+enum ColMode { COL_REGULAR = 0, COL_LAST = 1, COL_INVERSE_ONLY = 2 };
+
+// Kernel launchers (kernels.hip).  Each returns hipSuccess or the launch error.
+bool grid_supported(int n);
+hipError_t launch_splat(const SplatArgs& a, hipStream_t s);
+hipError_t launch_row_pass(const PassArgs& a, int mode, hipStream_t s);
+hipError_t launch_col_pass(const PassArgs& a, int mode, hipStream_t s);
+hipError_t launch_time_stage(const TimeArgs& a, hipStream_t s);
+int time_stage_kt(int n_frames, int n_k);
+
+// Setup kernels: twiddle table exp(-2 pi i m / n) (FP64 -> FP32); separable
+// propagator factors exp(-i pi lambda dz k^2) * scale along one axis; probe
+// aperture fill in reciprocal space.
+hipError_t launch_twiddles(float2* tw, int n, hipStream_t s);
+hipError_t launch_prop_factor(float2* out, int n, double d, double lam, double dz, double scale,
+                              hipStream_t s);
+hipError_t launch_aperture_count(int* count, int nx, int ny, double dx, double dy, double lam,
+                                 double alpha, hipStream_t s);
+hipError_t launch_probe_fill(float2* out, const double* rloc /*[P][2]*/, const int* count, int n_probes,
+                             int nx, int ny, double dx, double dy, double lam, double alpha,
+                             hipStream_t s);
+
+}  // namespace tacaw

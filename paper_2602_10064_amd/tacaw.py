@@ -1,0 +1,295 @@
+"""ctypes binding of libtacaw (C ABI in include/tacaw.h).
+
+Argument marshalling only: every step of the hot path runs in the library's
+HIP kernels.  If ``libtacaw.so`` has not been built, loading fails loudly;
+there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libtacaw.so")
+
+TACAW_OK = 0
+STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "EBUSY", 5: "ENOTREADY",
+                6: "ECANCELLED", 7: "EUNSUPPORTED"}
+TWO_SIDED = 1
+KEEP_EXIT_WAVES = 2
+
+K_SPLAT, K_ROW, K_COL, K_TIME, K_OTHER, K_FUSED = range(6)
+KERNEL_CLASSES = {"splat": K_SPLAT, "row": K_ROW, "col": K_COL, "time": K_TIME, "other": K_OTHER,
+                  "fused": K_FUSED}
+
+
+class TacawError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class JobDesc(ctypes.Structure):
+    _fields_ = [
+        ("cell", ctypes.c_double * 3),
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("n_slices", ctypes.c_int32),
+        ("voltage_V", ctypes.c_double),
+        ("aperture_mrad", ctypes.c_double),
+        ("n_probes", ctypes.c_int32),
+        ("probe_xy", ctypes.POINTER(ctypes.c_double)),
+        ("pot_nx", ctypes.c_int32), ("pot_ny", ctypes.c_int32),
+        ("dt_fs", ctypes.c_double),
+        ("n_frames", ctypes.c_int32),
+        ("n_atoms", ctypes.c_int32),
+        ("n_species", ctypes.c_int32),
+        ("species_Z", ctypes.POINTER(ctypes.c_int32)),
+        ("gauss_a", ctypes.POINTER(ctypes.c_double)),
+        ("gauss_b", ctypes.POINTER(ctypes.c_double)),
+        ("flags", ctypes.c_uint32),
+    ]
+
+
+_lib = None
+
+EXPORTED = [
+    "tacaw_ctx_create", "tacaw_ctx_destroy", "tacaw_job_footprint", "tacaw_job_create", "tacaw_run",
+    "tacaw_submit", "tacaw_poll", "tacaw_wait", "tacaw_cancel", "tacaw_get_spectrum",
+    "tacaw_get_exit_waves", "tacaw_axes", "tacaw_job_slices", "tacaw_job_destroy", "tacaw_last_error",
+    "tacaw_timing_enable", "tacaw_timing_get", "tacaw_version",
+]
+
+
+def lib() -> ctypes.CDLL:
+    """Load libtacaw.so (built in-tree by paper_2602_10064_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2602_10064_amd.build`"
+                           " (the HIP library is the only implementation)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, sz, i32, dp = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_double
+    P = ctypes.POINTER
+    sig = {
+        "tacaw_ctx_create": [ctypes.c_int, sz, P(vp)],
+        "tacaw_ctx_destroy": [vp],
+        "tacaw_job_footprint": [P(JobDesc), P(sz)],
+        "tacaw_job_create": [vp, P(JobDesc), P(i32), P(dp), P(vp)],
+        "tacaw_run": [vp, vp],
+        "tacaw_submit": [vp, vp],
+        "tacaw_poll": [vp, P(ctypes.c_int)],
+        "tacaw_wait": [vp],
+        "tacaw_cancel": [vp],
+        "tacaw_get_spectrum": [vp, vp, sz, ctypes.c_int],
+        "tacaw_get_exit_waves": [vp, vp, sz, ctypes.c_int],
+        "tacaw_axes": [P(JobDesc), P(dp), P(dp), P(dp)],
+        "tacaw_job_slices": [vp, P(i32), sz],
+        "tacaw_job_destroy": [vp],
+        "tacaw_timing_enable": [vp, ctypes.c_int],
+        "tacaw_timing_get": [vp, ctypes.c_int, P(dp), P(ctypes.c_int64)],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    L.tacaw_last_error.restype = ctypes.c_char_p
+    L.tacaw_last_error.argtypes = []
+    L.tacaw_version.restype = ctypes.c_char_p
+    L.tacaw_version.argtypes = []
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != TACAW_OK:
+        raise TacawError(status, lib().tacaw_last_error().decode(errors="replace"))
+
+
+def _ptr(a: np.ndarray, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+class _DescHolder:
+    """A JobDesc plus the numpy arrays its pointers refer to (kept alive)."""
+
+    def __init__(self, job, keep_exit_waves: Optional[bool] = None):
+        self.species_Z = np.ascontiguousarray(job.species_Z, dtype=np.int32)
+        self.gauss_a = np.ascontiguousarray(job.gauss_a, dtype=np.float64)
+        self.gauss_b = np.ascontiguousarray(job.gauss_b, dtype=np.float64)
+        self.probe_xy = np.ascontiguousarray(job.probe_xy, dtype=np.float64).reshape(-1, 2)
+        if self.probe_xy.size == 0:
+            self.probe_xy = np.zeros((1, 2))
+        d = JobDesc()
+        d.cell[:] = [float(v) for v in job.cell]
+        d.nx, d.ny, d.n_slices = int(job.nx), int(job.ny), int(job.n_slices)
+        d.voltage_V = float(job.voltage_V)
+        d.aperture_mrad = float(job.aperture_mrad)
+        d.n_probes = int(job.probe_xy.shape[0]) if job.aperture_mrad > 0 else 1
+        d.probe_xy = _ptr(self.probe_xy, ctypes.c_double)
+        d.pot_nx, d.pot_ny = int(job.pot_nx), int(job.pot_ny)
+        d.dt_fs = float(job.dt_fs)
+        d.n_frames = int(job.positions.shape[0])
+        d.n_atoms = int(job.positions.shape[1])
+        d.n_species = int(len(self.species_Z))
+        d.species_Z = _ptr(self.species_Z, ctypes.c_int32)
+        d.gauss_a = _ptr(self.gauss_a, ctypes.c_double)
+        d.gauss_b = _ptr(self.gauss_b, ctypes.c_double)
+        keep = job.keep_exit_waves if keep_exit_waves is None else keep_exit_waves
+        d.flags = (TWO_SIDED if job.two_sided else 0) | (KEEP_EXIT_WAVES if keep else 0)
+        self.desc = d
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)      # torch.cuda.Stream
+
+
+class Context:
+    """tacaw_ctx: a device, a memory budget, timing and the serving loop."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        h = ctypes.c_void_p()
+        _check(lib().tacaw_ctx_create(int(device), int(hbm_budget_bytes), ctypes.byref(h)))
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            _check(lib().tacaw_ctx_destroy(self.handle))
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def timing_enable(self, on: bool = True):
+        _check(lib().tacaw_timing_enable(self.handle, 1 if on else 0))
+
+    def timing_get(self, kernel_class) -> tuple:
+        cls = KERNEL_CLASSES[kernel_class] if isinstance(kernel_class, str) else int(kernel_class)
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        _check(lib().tacaw_timing_get(self.handle, cls, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    def submit(self, job: "TacawJob"):
+        _check(lib().tacaw_submit(self.handle, job.handle))
+
+
+class TacawJob:
+    """tacaw_job created from a workloads.Job (inputs copied by the library)."""
+
+    def __init__(self, ctx: Context, job, keep_exit_waves: Optional[bool] = None):
+        self.ctx = ctx
+        self.job = job
+        self._d = _DescHolder(job, keep_exit_waves)
+        sp = np.ascontiguousarray(job.atom_species, dtype=np.int32)
+        pos = np.ascontiguousarray(job.positions, dtype=np.float64)
+        h = ctypes.c_void_p()
+        _check(lib().tacaw_job_create(ctx.handle, ctypes.byref(self._d.desc), _ptr(sp, ctypes.c_int32),
+                                      _ptr(pos, ctypes.c_double), ctypes.byref(h)))
+        self.handle = h
+        self.n_probes = self._d.desc.n_probes
+        self.n_frames = self._d.desc.n_frames
+        self.n_bins = self.n_frames if job.two_sided else self.n_frames // 2
+        self.nx, self.ny = job.nx, job.ny
+
+    # plain per-job form
+    def run(self, stream=None):
+        _check(lib().tacaw_run(self.handle, _stream_handle(stream)))
+
+    # serving form
+    def poll(self) -> bool:
+        d = ctypes.c_int()
+        _check(lib().tacaw_poll(self.handle, ctypes.byref(d)))
+        return bool(d.value)
+
+    def wait(self):
+        _check(lib().tacaw_wait(self.handle))
+
+    def cancel(self):
+        _check(lib().tacaw_cancel(self.handle))
+
+    @property
+    def spectrum_shape(self):
+        return (self.n_probes, self.n_bins, self.ny, self.nx)
+
+    @property
+    def exit_shape(self):
+        return (self.n_probes, self.n_frames, self.ny, self.nx)
+
+    def spectrum(self, out=None):
+        """I[p][m][ky][kx] float32 into a new numpy array, or into `out` (numpy or
+        a CUDA torch tensor)."""
+        n = int(np.prod(self.spectrum_shape))
+        if out is None:
+            out = np.empty(self.spectrum_shape, dtype=np.float32)
+        if isinstance(out, np.ndarray):
+            assert out.dtype == np.float32 and out.flags.c_contiguous and out.size == n
+            _check(lib().tacaw_get_spectrum(self.handle, out.ctypes.data, n, 0))
+        else:
+            assert out.is_cuda and out.is_contiguous() and out.numel() == n
+            _check(lib().tacaw_get_spectrum(self.handle, out.data_ptr(), n, 1))
+        return out
+
+    def exit_waves(self, out=None):
+        """psi[p][f][ky][kx] complex64 into a new numpy array or into `out`."""
+        n = int(np.prod(self.exit_shape))
+        if out is None:
+            out = np.empty(self.exit_shape, dtype=np.complex64)
+        if isinstance(out, np.ndarray):
+            assert out.dtype == np.complex64 and out.flags.c_contiguous and out.size == n
+            _check(lib().tacaw_get_exit_waves(self.handle, out.ctypes.data, n, 0))
+        else:
+            assert out.is_cuda and out.is_contiguous() and out.numel() == n
+            _check(lib().tacaw_get_exit_waves(self.handle, out.data_ptr(), n, 1))
+        return out
+
+    def slices(self) -> np.ndarray:
+        n = int(self._d.desc.n_atoms)
+        out = np.empty(n, dtype=np.int32)
+        _check(lib().tacaw_job_slices(self.handle, _ptr(out, ctypes.c_int32), n))
+        return out
+
+    def destroy(self):
+        if self.handle:
+            _check(lib().tacaw_job_destroy(self.handle))
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.destroy()
+
+
+def footprint(job) -> int:
+    d = _DescHolder(job)
+    b = ctypes.c_size_t()
+    _check(lib().tacaw_job_footprint(ctypes.byref(d.desc), ctypes.byref(b)))
+    return b.value
+
+
+def axes(job):
+    """(kx[nx], ky[ny], f_THz[M]) as the library reports them."""
+    d = _DescHolder(job)
+    m = job.n_frames if job.two_sided else job.n_frames // 2
+    kx = np.empty(job.nx)
+    ky = np.empty(job.ny)
+    f = np.empty(m)
+    _check(lib().tacaw_axes(ctypes.byref(d.desc), _ptr(kx, ctypes.c_double), _ptr(ky, ctypes.c_double),
+                            _ptr(f, ctypes.c_double)))
+    return kx, ky, f
+
+
+def version() -> str:
+    return lib().tacaw_version().decode()

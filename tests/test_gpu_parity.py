@@ -1,0 +1,147 @@
+"""HIP path vs the FP64 oracle, through the C ABI (needs an MI355X).
+
+Tolerances (complex64 GPU path vs FP64 oracle): relative L2 error <= 1e-4 on
+exit waves psi(k, t) and <= 1e-3 on I(k, w), over the whole compared array.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2602_10064_amd import workloads as w
+from tests.oracle_pool import exit_waves_parallel
+
+pytestmark = pytest.mark.gpu
+
+EXIT_TOL = 1e-4
+SPEC_TOL = 1e-3
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+@pytest.fixture(scope="module")
+def tacaw():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2602_10064_amd import tacaw as t
+    t.lib()
+    return t
+
+
+@pytest.fixture(scope="module")
+def ctx(tacaw):
+    c = tacaw.Context(0)
+    yield c
+    c.close()
+
+
+def run_gpu(tacaw, ctx, job):
+    print(f"[gpu] {job.name}: grid {job.nx}x{job.ny} pot {job.pot_nx}x{job.pot_ny} slices "
+          f"{job.n_slices} frames {job.n_frames} probes {job.n_probes} atoms {job.n_atoms}", flush=True)
+    with tacaw.TacawJob(ctx, job) as j:
+        j.run()
+        return j.exit_waves(), j.spectrum(), j.slices()
+
+
+def check_job(tacaw, ctx, oracle, job, exit_tol=EXIT_TOL, spec_tol=SPEC_TOL):
+    ex, spec, sl = run_gpu(tacaw, ctx, job)
+    ref_sl = oracle.slice_index(job.positions, job.cell[2], job.n_slices)
+    assert np.array_equal(sl, ref_sl)
+    ref_ex = exit_waves_parallel(job)
+    ref_spec = oracle.tacaw_spectrum(ref_ex, two_sided=job.two_sided)
+    e1 = rel_l2(ex, ref_ex)
+    e2 = rel_l2(spec, ref_spec)
+    print(f"[gpu] {job.name}: exit relL2 {e1:.3e}  spectrum relL2 {e2:.3e}", flush=True)
+    assert e1 <= exit_tol
+    assert e2 <= spec_tol
+    return ex, spec, ref_ex, ref_spec
+
+
+def test_c1_tiny_full(tacaw, ctx, oracle):
+    job = w.c1_tiny()
+    ex, spec, _, _ = check_job(tacaw, ctx, oracle, job)
+    # FP64 mean subtraction: the DC bin holds rounding only
+    assert spec[:, 0].max() <= 1e-6 * spec.max()
+    # unitary propagation in FP32
+    norms = np.sum(np.abs(ex.astype(np.complex128)) ** 2, axis=(2, 3))
+    assert np.max(np.abs(norms - 1.0)) < 1e-5
+
+
+SMALL = [
+    dict(seed=11, nx=16, ny=16, n_slices=3, n_frames=8, cell=(3.2, 3.2, 3.0)),
+    dict(seed=12, nx=32, ny=48, n_slices=4, n_frames=12, cell=(5.0, 7.5, 4.0)),
+    dict(seed=13, nx=96, ny=64, n_slices=5, n_frames=10, cell=(12.0, 8.0, 6.0), n_atoms=12),
+    dict(seed=14, nx=160, ny=128, n_slices=2, n_frames=6, cell=(18.0, 15.0, 3.0), n_atoms=10),
+    dict(seed=15, nx=384, ny=192, n_slices=2, n_frames=4, cell=(40.0, 22.0, 3.0), n_atoms=20),
+    dict(seed=16, nx=64, ny=64, n_slices=3, n_frames=8, cell=(8.0, 8.0, 4.0), aperture_mrad=30.0,
+         n_probes=3, voltage_V=60e3),
+    dict(seed=17, nx=32, ny=32, n_slices=3, n_frames=8, cell=(10.0, 9.0, 4.0), aperture_mrad=25.0,
+         n_probes=4, voltage_V=100e3, pot_grid=(100, 90)),
+    dict(seed=18, nx=48, ny=32, n_slices=2, n_frames=15, cell=(9.5, 8.1, 4.0), aperture_mrad=30.0,
+         n_probes=2, voltage_V=200e3, pot_grid=(95, 81), two_sided=True),
+    dict(seed=19, nx=640, ny=16, n_slices=2, n_frames=4, cell=(64.0, 2.0, 3.0), n_atoms=8),
+]
+
+
+@pytest.mark.parametrize("kw", SMALL, ids=[f"s{k['seed']}_{k['nx']}x{k['ny']}" for k in SMALL])
+def test_small_jobs(tacaw, ctx, oracle, kw):
+    job = w.random_small_job(**kw)
+    check_job(tacaw, ctx, oracle, job)
+
+
+def test_c2_shape_reduced_frames_ragged_batches(tacaw, ctx, oracle, monkeypatch):
+    # full 512^2 grid, 32 slices, 9216 atoms; 16 frames in batches of 5 (5+5+5+1)
+    monkeypatch.setenv("TACAW_V_BUDGET_MB", str(5 * 32))
+    job = w.c2_plain(n_frames=16)
+    check_job(tacaw, ctx, oracle, job)
+
+
+def test_determinism_bitwise(tacaw, ctx):
+    job = w.c1_tiny(n_frames=32)
+    ex1, sp1, _ = run_gpu(tacaw, ctx, job)
+    ex2, sp2, _ = run_gpu(tacaw, ctx, job)
+    assert np.array_equal(ex1.view(np.uint32), ex2.view(np.uint32))
+    assert np.array_equal(sp1.view(np.uint32), sp2.view(np.uint32))
+
+
+def test_static_trajectory_gives_zero_spectrum(tacaw, ctx):
+    job = w.random_small_job(21, nx=32, ny=32, n_frames=8, cell=(5.0, 5.0, 3.0))
+    job.positions[:] = job.positions[0:1]
+    _, spec, _ = run_gpu(tacaw, ctx, job)
+    assert spec.max() < 1e-20
+
+
+def test_circular_frame_shift_invariance(tacaw, ctx):
+    job = w.c1_tiny(n_frames=32)
+    _, a, _ = run_gpu(tacaw, ctx, job)
+    _, b, _ = run_gpu(tacaw, ctx, job.replace(positions=np.roll(job.positions, 5, axis=0)))
+    assert rel_l2(b, a) < 1e-4
+
+
+def test_device_destination_and_stream(tacaw, ctx):
+    import torch
+    job = w.c1_tiny(n_frames=16)
+    with tacaw.TacawJob(ctx, job) as j:
+        s = torch.cuda.Stream()
+        j.run(stream=s)
+        host = j.spectrum()
+        dev = torch.empty(j.spectrum_shape, dtype=torch.float32, device="cuda")
+        j.spectrum(out=dev)
+        assert np.array_equal(dev.cpu().numpy(), host)
+        exd = torch.empty(j.exit_shape, dtype=torch.complex64, device="cuda")
+        j.exit_waves(out=exd)
+        assert np.array_equal(exd.cpu().numpy(), j.exit_waves())
+
+
+def test_errors_do_not_poison_context(tacaw, ctx):
+    job = w.random_small_job(22, nx=16, ny=16, n_frames=8)
+    with pytest.raises(tacaw.TacawError):
+        tacaw.TacawJob(ctx, job.replace(atom_species=np.full(job.n_atoms, 7, np.int32)))
+    with tacaw.TacawJob(ctx, job) as j:
+        with pytest.raises(tacaw.TacawError) as e:
+            j.spectrum()
+        assert e.value.status == 5          # not run yet
+        j.run()
+        assert np.isfinite(j.spectrum()).all()
