@@ -51,6 +51,8 @@ typedef enum {
 /* tacaw_job_desc.flags */
 #define TACAW_TWO_SIDED 1u        /* keep all F frequency bins instead of F/2      */
 #define TACAW_KEEP_EXIT_WAVES 2u  /* keep psi(k, t) readable after the time stage  */
+#define TACAW_DEFER_ALLOC 4u      /* allocate device memory only when the job is run
+                                     or admitted by the serving loop                 */
 
 typedef struct tacaw_ctx tacaw_ctx;
 typedef struct tacaw_job tacaw_job;
@@ -111,7 +113,7 @@ typedef struct {
   const int32_t* species_Z;    /* n_species atomic numbers (labels only)                 */
   const double* gauss_a;       /* n_species x 5 form-factor amplitudes [A], > 0          */
   const double* gauss_b;       /* n_species x 5 form-factor widths [A^2], > 0            */
-  uint32_t flags;              /* TACAW_TWO_SIDED | TACAW_KEEP_EXIT_WAVES                */
+  uint32_t flags;              /* TACAW_TWO_SIDED | TACAW_KEEP_EXIT_WAVES | TACAW_DEFER_ALLOC */
 } tacaw_job_desc;
 
 /* ---- context ------------------------------------------------------------ */
@@ -164,6 +166,11 @@ tacaw_status tacaw_wait(tacaw_job* job);
 /* Cancel a submitted job.  Jobs not yet admitted are dropped; a running job
  * stops at its next frame batch.  Other jobs are unaffected. */
 tacaw_status tacaw_cancel(tacaw_job* job);
+
+/* Latency of a job that finished in the serving loop: time from submit to
+ * admission (queued_ms) and from submit to the spectrum being ready on the
+ * device (total_ms), in milliseconds.  ENOTREADY before it finishes. */
+tacaw_status tacaw_job_latency(const tacaw_job* job, double* queued_ms, double* total_ms);
 
 /* Copy the spectrum I[p][m][ky][kx] (float32, n = n_probes * M * ny * nx,
  * M = F/2 or F) into dst, a host pointer or (dst_on_device != 0) a device

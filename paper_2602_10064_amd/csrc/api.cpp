@@ -12,6 +12,8 @@ const char* last_error_text();
 void encode_positions(const HostPlan& hp, const double* pos, int f0, int f1, AtomPos* out);
 tacaw_status run_batch_range(tacaw_job* job, hipStream_t s, int f_begin, int f_end);
 tacaw_status run_time_stage(tacaw_job* job, hipStream_t s);
+tacaw_status materialize(tacaw_job* j, hipStream_t s = nullptr);
+void release_working(tacaw_job* j);
 }  // namespace tacaw
 
 using namespace tacaw;
@@ -138,7 +140,7 @@ static PassArgs pass_args(tacaw_job* j) {
   return a;
 }
 
-// Splat + all slices for frames [f_begin, f_end) (one or more frame batches).
+// Potentials + all slices for frames [f_begin, f_end) (one or more frame batches).
 tacaw_status run_batch_range(tacaw_job* job, hipStream_t s, int f_begin, int f_end) {
   const HostPlan& hp = job->hp;
   for (int f0 = f_begin; f0 < f_end; f0 += hp.fb) {
@@ -154,6 +156,7 @@ tacaw_status run_batch_range(tacaw_job* job, hipStream_t s, int f_begin, int f_e
     sa.f0 = f0;
     sa.fb = fb;
     sa.n_slices = hp.ns;
+    sa.slice0 = 0;
     sa.pnx = hp.pnx;
     sa.pny = hp.pny;
     sa.tiles_x = hp.tiles_x;
@@ -162,13 +165,24 @@ tacaw_status run_batch_range(tacaw_job* job, hipStream_t s, int f_begin, int f_e
     sa.rcy = hp.rcy;
     sa.img_x = hp.img_x;
     sa.img_y = hp.img_y;
-    tacaw_status st = timed(job, TACAW_K_SPLAT, s, [&] { return launch_splat(sa, s); });
-    if (st != TACAW_OK) return st;
+    tacaw_status st = TACAW_OK;
+    if (!hp.splat_per_slice) {
+      st = timed(job, TACAW_K_SPLAT, s, [&] { return launch_splat(sa, hp.ns, s); });
+      if (st != TACAW_OK) return st;
+    }
     PassArgs a = pass_args(job);
     a.f0 = f0;
     a.fb = fb;
+    a.v_slices = hp.splat_per_slice ? 1 : hp.ns;
+    a.v_slice0 = 0;
     for (int sl = 0; sl < hp.ns; ++sl) {
       a.slice = sl;
+      if (hp.splat_per_slice) {
+        sa.slice0 = sl;
+        a.v_slice0 = sl;
+        st = timed(job, TACAW_K_SPLAT, s, [&] { return launch_splat(sa, 1, s); });
+        if (st != TACAW_OK) return st;
+      }
       const int rmode = sl == 0 ? ROW_FIRST : ROW_REGULAR;
       st = timed(job, TACAW_K_ROW, s, [&] { return launch_row_pass(a, rmode, s); });
       if (st != TACAW_OK) return st;
@@ -198,6 +212,117 @@ tacaw_status run_time_stage(tacaw_job* job, hipStream_t s) {
   t.kt = time_stage_kt(hp.F, t.n_k);
   t.inv_f2 = (float)(1.0 / ((double)hp.F * hp.F));
   return timed(job, TACAW_K_TIME, s, [&] { return launch_time_stage(t, s); });
+}
+
+
+// Allocate the job's device buffers, upload its inputs and build its tables
+// and incident probes.  Synchronous.
+tacaw_status materialize(tacaw_job* j, hipStream_t s0) {
+  if (j->materialized) return TACAW_OK;
+  HIP_TRY(hipSetDevice(j->ctx->device));
+  HostPlan& hp = j->hp;
+  auto fail = [&](const char* what, hipError_t e) {
+    set_error("%s: %s", what, hipGetErrorString(e));
+    free_job_buffers(j);
+    return e == hipErrorOutOfMemory ? TACAW_ENOMEM : TACAW_EDEVICE;
+  };
+  hipError_t e;
+  const size_t nk = (size_t)hp.nx * hp.ny;
+#define ALLOC(ptr, count) \
+  if ((e = dalloc(&(ptr), (count))) != hipSuccess) return fail("hipMalloc " #ptr, e);
+  if (!j->d_exit) ALLOC(j->d_exit, (size_t)hp.P * hp.F * nk);
+  if (!j->d_spec) ALLOC(j->d_spec, (size_t)hp.P * hp.M * nk);
+  ALLOC(j->d_V, (size_t)hp.fb * (hp.splat_per_slice ? 1 : hp.ns) * hp.pnx * hp.pny);
+  ALLOC(j->d_pos, (size_t)hp.F * hp.A);
+  ALLOC(j->d_species, (size_t)hp.A);
+  ALLOC(j->d_tile_start, hp.tile_start.size());
+  ALLOC(j->d_tile_atoms, hp.tile_atoms.size());
+  ALLOC(j->d_coef, hp.coef.size());
+  ALLOC(j->d_tw_x, (size_t)hp.nx);
+  ALLOC(j->d_tw_y, (size_t)hp.ny);
+  ALLOC(j->d_tw_t, (size_t)hp.F);
+  ALLOC(j->d_px, (size_t)hp.nx);
+  ALLOC(j->d_py, (size_t)hp.ny);
+  ALLOC(j->d_px_last, (size_t)hp.nx);
+  ALLOC(j->d_py_last, (size_t)hp.ny);
+  ALLOC(j->d_origin, (size_t)hp.P * 2);
+  ALLOC(j->d_rloc, (size_t)hp.P * 2);
+  ALLOC(j->d_count, 1);
+  if (!hp.plane) ALLOC(j->d_probe0, (size_t)hp.P * nk);
+#undef ALLOC
+
+  if (hp.A > 0) {
+    if ((e = hipMemcpyAsync(j->d_pos, j->enc.data(), j->enc.size() * sizeof(AtomPos), hipMemcpyHostToDevice, s0)) !=
+        hipSuccess)
+      return fail("upload positions", e);
+    if ((e = hipMemcpyAsync(j->d_species, hp.sorted_species.data(), hp.A * sizeof(int32_t), hipMemcpyHostToDevice, s0)) !=
+        hipSuccess)
+      return fail("upload species", e);
+  }
+  if ((e = hipMemcpyAsync(j->d_tile_start, hp.tile_start.data(), hp.tile_start.size() * sizeof(int32_t),
+                     hipMemcpyHostToDevice, s0)) != hipSuccess)
+    return fail("upload tiles", e);
+  if (!hp.tile_atoms.empty() &&
+      (e = hipMemcpyAsync(j->d_tile_atoms, hp.tile_atoms.data(), hp.tile_atoms.size() * sizeof(int32_t),
+                     hipMemcpyHostToDevice, s0)) != hipSuccess)
+    return fail("upload tile atoms", e);
+  if ((e = hipMemcpyAsync(j->d_coef, hp.coef.data(), hp.coef.size() * sizeof(float), hipMemcpyHostToDevice, s0)) !=
+      hipSuccess)
+    return fail("upload coefficients", e);
+  if ((e = hipMemcpyAsync(j->d_origin, hp.origin.data(), hp.origin.size() * sizeof(int32_t), hipMemcpyHostToDevice, s0)) !=
+      hipSuccess)
+    return fail("upload origins", e);
+  if ((e = hipMemcpyAsync(j->d_rloc, hp.rloc.data(), hp.rloc.size() * sizeof(double), hipMemcpyHostToDevice, s0)) !=
+      hipSuccess)
+    return fail("upload probe positions", e);
+
+  // tables and incident probes on the device, then synchronise the stream
+  const double sx = 1.0 / hp.nx, sy = 1.0 / hp.ny;
+  const double lx = 1.0 / sqrt((double)hp.nx), ly = 1.0 / sqrt((double)hp.ny);
+  if ((e = launch_twiddles(j->d_tw_x, hp.nx, s0)) != hipSuccess) return fail("twiddles", e);
+  if ((e = launch_twiddles(j->d_tw_y, hp.ny, s0)) != hipSuccess) return fail("twiddles", e);
+  if ((e = launch_twiddles(j->d_tw_t, hp.F, s0)) != hipSuccess) return fail("twiddles", e);
+  if ((e = launch_prop_factor(j->d_px, hp.nx, hp.dx, hp.lam, hp.dz, sx, s0)) != hipSuccess) return fail("prop", e);
+  if ((e = launch_prop_factor(j->d_py, hp.ny, hp.dy, hp.lam, hp.dz, sy, s0)) != hipSuccess) return fail("prop", e);
+  if ((e = launch_prop_factor(j->d_px_last, hp.nx, hp.dx, hp.lam, hp.dz, lx, s0)) != hipSuccess)
+    return fail("prop", e);
+  if ((e = launch_prop_factor(j->d_py_last, hp.ny, hp.dy, hp.lam, hp.dz, ly, s0)) != hipSuccess)
+    return fail("prop", e);
+  if (!hp.plane) {
+    if ((e = hipMemsetAsync(j->d_count, 0, sizeof(int), s0)) != hipSuccess) return fail("memset", e);
+    if ((e = launch_aperture_count(j->d_count, hp.nx, hp.ny, hp.dx, hp.dy, hp.lam, hp.alpha, s0)) != hipSuccess)
+      return fail("aperture", e);
+    if ((e = launch_probe_fill(j->d_probe0, j->d_rloc, j->d_count, hp.P, hp.nx, hp.ny, hp.dx, hp.dy, hp.lam,
+                               hp.alpha, s0)) != hipSuccess)
+      return fail("probe fill", e);
+    PassArgs a = pass_args(j);
+    a.exit = j->d_probe0;
+    a.n_frames = 1;
+    a.f0 = 0;
+    a.fb = 1;
+    if ((e = launch_col_pass(a, COL_INVERSE_ONLY, s0)) != hipSuccess) return fail("probe iFFT_y", e);
+    if ((e = launch_row_pass(a, ROW_INVERSE_ONLY, s0)) != hipSuccess) return fail("probe iFFT_x", e);
+  }
+  if ((e = hipStreamSynchronize(s0)) != hipSuccess) return fail("job setup", e);
+  j->materialized = true;
+  return TACAW_OK;
+}
+
+// Free every device buffer except the spectrum and (when kept) the exit waves.
+void release_working(tacaw_job* j) {
+  float2* keep_exit = (j->desc.flags & TACAW_KEEP_EXIT_WAVES) ? j->d_exit : nullptr;
+  float* keep_spec = j->d_spec;
+  if (!keep_exit && j->d_exit) (void)hipFree(j->d_exit);
+  j->d_exit = nullptr;
+  j->d_spec = nullptr;
+  free_job_buffers(j);
+  j->d_exit = keep_exit;
+  j->d_spec = keep_spec;
+  j->materialized = false;
+}
+
+size_t resident_bytes_after_done(const tacaw_job* j) {
+  return j->fp.spec + ((j->desc.flags & TACAW_KEEP_EXIT_WAVES) ? j->fp.exit : 0);
 }
 
 }  // namespace tacaw
@@ -274,7 +399,6 @@ tacaw_status tacaw_job_create(tacaw_ctx* ctx, const tacaw_job_desc* d, const int
     set_error("atom_species and positions must not be NULL when n_atoms > 0");
     return TACAW_EINVAL;
   }
-  HIP_TRY(hipSetDevice(ctx->device));
   tacaw_job* j = new tacaw_job();
   j->ctx = ctx;
   j->desc = *d;
@@ -296,101 +420,25 @@ tacaw_status tacaw_job_create(tacaw_ctx* ctx, const tacaw_job_desc* d, const int
     delete j;
     return st;
   }
-  HostPlan& hp = j->hp;
-  j->fp = footprint_of(&j->desc, hp.fb, hp.tile_atoms.size());
-  if (j->fp.total() > ctx->budget) {
+  j->fp = footprint_of(&j->desc, j->hp.fb, j->hp.tile_atoms.size());
+  // deferred jobs are checked against the budget when submitted
+  if (!(d->flags & TACAW_DEFER_ALLOC) && j->fp.total() > ctx->budget) {
     set_error("job needs %.3f GiB of device memory, above the context budget of %.3f GiB",
               j->fp.total() / 1073741824.0, ctx->budget / 1073741824.0);
     delete j;
     return TACAW_ENOMEM;
   }
-
-  auto fail = [&](const char* what, hipError_t e) {
-    set_error("%s: %s", what, hipGetErrorString(e));
-    free_job_buffers(j);
-    delete j;
-    return e == hipErrorOutOfMemory ? TACAW_ENOMEM : TACAW_EDEVICE;
-  };
-  hipError_t e;
-  const size_t nk = (size_t)hp.nx * hp.ny;
-#define ALLOC(ptr, count) \
-  if ((e = dalloc(&(ptr), (count))) != hipSuccess) return fail("hipMalloc " #ptr, e);
-  ALLOC(j->d_exit, (size_t)hp.P * hp.F * nk);
-  ALLOC(j->d_spec, (size_t)hp.P * hp.M * nk);
-  ALLOC(j->d_V, (size_t)hp.fb * hp.ns * hp.pnx * hp.pny);
-  ALLOC(j->d_pos, (size_t)hp.F * hp.A);
-  ALLOC(j->d_species, (size_t)hp.A);
-  ALLOC(j->d_tile_start, hp.tile_start.size());
-  ALLOC(j->d_tile_atoms, hp.tile_atoms.size());
-  ALLOC(j->d_coef, hp.coef.size());
-  ALLOC(j->d_tw_x, (size_t)hp.nx);
-  ALLOC(j->d_tw_y, (size_t)hp.ny);
-  ALLOC(j->d_tw_t, (size_t)hp.F);
-  ALLOC(j->d_px, (size_t)hp.nx);
-  ALLOC(j->d_py, (size_t)hp.ny);
-  ALLOC(j->d_px_last, (size_t)hp.nx);
-  ALLOC(j->d_py_last, (size_t)hp.ny);
-  ALLOC(j->d_origin, (size_t)hp.P * 2);
-  ALLOC(j->d_rloc, (size_t)hp.P * 2);
-  ALLOC(j->d_count, 1);
-  if (!hp.plane) ALLOC(j->d_probe0, (size_t)hp.P * nk);
-#undef ALLOC
-
-  // uploads (synchronous; inputs are copied so the caller keeps its arrays)
-  if (hp.A > 0) {
-    std::vector<AtomPos> enc((size_t)hp.F * hp.A);
-    encode_positions(hp, positions, 0, hp.F, enc.data());
-    if ((e = hipMemcpy(j->d_pos, enc.data(), enc.size() * sizeof(AtomPos), hipMemcpyHostToDevice)) != hipSuccess)
-      return fail("upload positions", e);
-    if ((e = hipMemcpy(j->d_species, hp.sorted_species.data(), hp.A * sizeof(int32_t), hipMemcpyHostToDevice)) !=
-        hipSuccess)
-      return fail("upload species", e);
+  if (j->hp.A > 0) {
+    j->enc.resize((size_t)j->hp.F * j->hp.A);
+    encode_positions(j->hp, positions, 0, j->hp.F, j->enc.data());
   }
-  if ((e = hipMemcpy(j->d_tile_start, hp.tile_start.data(), hp.tile_start.size() * sizeof(int32_t),
-                     hipMemcpyHostToDevice)) != hipSuccess)
-    return fail("upload tiles", e);
-  if (!hp.tile_atoms.empty() &&
-      (e = hipMemcpy(j->d_tile_atoms, hp.tile_atoms.data(), hp.tile_atoms.size() * sizeof(int32_t),
-                     hipMemcpyHostToDevice)) != hipSuccess)
-    return fail("upload tile atoms", e);
-  if ((e = hipMemcpy(j->d_coef, hp.coef.data(), hp.coef.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess)
-    return fail("upload coefficients", e);
-  if ((e = hipMemcpy(j->d_origin, hp.origin.data(), hp.origin.size() * sizeof(int32_t), hipMemcpyHostToDevice)) !=
-      hipSuccess)
-    return fail("upload origins", e);
-  if ((e = hipMemcpy(j->d_rloc, hp.rloc.data(), hp.rloc.size() * sizeof(double), hipMemcpyHostToDevice)) !=
-      hipSuccess)
-    return fail("upload probe positions", e);
-
-  // tables and incident probes on the device (null stream, then synchronise)
-  hipStream_t s0 = nullptr;
-  const double sx = 1.0 / hp.nx, sy = 1.0 / hp.ny;
-  const double lx = 1.0 / sqrt((double)hp.nx), ly = 1.0 / sqrt((double)hp.ny);
-  if ((e = launch_twiddles(j->d_tw_x, hp.nx, s0)) != hipSuccess) return fail("twiddles", e);
-  if ((e = launch_twiddles(j->d_tw_y, hp.ny, s0)) != hipSuccess) return fail("twiddles", e);
-  if ((e = launch_twiddles(j->d_tw_t, hp.F, s0)) != hipSuccess) return fail("twiddles", e);
-  if ((e = launch_prop_factor(j->d_px, hp.nx, hp.dx, hp.lam, hp.dz, sx, s0)) != hipSuccess) return fail("prop", e);
-  if ((e = launch_prop_factor(j->d_py, hp.ny, hp.dy, hp.lam, hp.dz, sy, s0)) != hipSuccess) return fail("prop", e);
-  if ((e = launch_prop_factor(j->d_px_last, hp.nx, hp.dx, hp.lam, hp.dz, lx, s0)) != hipSuccess)
-    return fail("prop", e);
-  if ((e = launch_prop_factor(j->d_py_last, hp.ny, hp.dy, hp.lam, hp.dz, ly, s0)) != hipSuccess)
-    return fail("prop", e);
-  if (!hp.plane) {
-    if ((e = hipMemset(j->d_count, 0, sizeof(int))) != hipSuccess) return fail("memset", e);
-    if ((e = launch_aperture_count(j->d_count, hp.nx, hp.ny, hp.dx, hp.dy, hp.lam, hp.alpha, s0)) != hipSuccess)
-      return fail("aperture", e);
-    if ((e = launch_probe_fill(j->d_probe0, j->d_rloc, j->d_count, hp.P, hp.nx, hp.ny, hp.dx, hp.dy, hp.lam,
-                               hp.alpha, s0)) != hipSuccess)
-      return fail("probe fill", e);
-    PassArgs a = pass_args(j);
-    a.exit = j->d_probe0;
-    a.n_frames = 1;
-    a.f0 = 0;
-    a.fb = 1;
-    if ((e = launch_col_pass(a, COL_INVERSE_ONLY, s0)) != hipSuccess) return fail("probe iFFT_y", e);
-    if ((e = launch_row_pass(a, ROW_INVERSE_ONLY, s0)) != hipSuccess) return fail("probe iFFT_x", e);
+  if (!(d->flags & TACAW_DEFER_ALLOC)) {
+    st = materialize(j);
+    if (st != TACAW_OK) {
+      delete j;
+      return st;
+    }
   }
-  if ((e = hipDeviceSynchronize()) != hipSuccess) return fail("job setup", e);
   *out = j;
   return TACAW_OK;
 }
@@ -407,9 +455,11 @@ tacaw_status tacaw_run(tacaw_job* job, void* hip_stream) {
     return TACAW_EBUSY;
   }
   HIP_TRY(hipSetDevice(job->ctx->device));
+  tacaw_status st = materialize(job);
+  if (st != TACAW_OK) return st;
   hipStream_t s = (hipStream_t)hip_stream;
   job->last_stream = s;
-  tacaw_status st = run_batch_range(job, s, 0, job->hp.F);
+  st = run_batch_range(job, s, 0, job->hp.F);
   if (st != TACAW_OK) return st;
   st = run_time_stage(job, s);
   if (st != TACAW_OK) return st;
@@ -533,6 +583,10 @@ tacaw_status tacaw_job_destroy(tacaw_job* job) {
   }
   (void)hipSetDevice(job->ctx->device);
   (void)hipDeviceSynchronize();
+  if (job->retained) {
+    std::lock_guard<std::mutex> lk(job->ctx->mu);
+    job->ctx->resident -= job->retained;
+  }
   free_job_buffers(job);
   delete job;
   return TACAW_OK;

@@ -118,7 +118,7 @@ __global__ void __launch_bounds__(256) k_splat(SplatArgs a) {
   const int tid = threadIdx.x;
   const int n_tiles = a.tiles_x * a.tiles_y;
   const int tile = blockIdx.x;
-  const int s = blockIdx.y;
+  const int s = a.slice0 + blockIdx.y;
   const int fl = blockIdx.z;
   const int f = a.f0 + fl;
   const int tx0 = (tile % a.tiles_x) * SPLAT_TX;
@@ -168,7 +168,7 @@ __global__ void __launch_bounds__(256) k_splat(SplatArgs a) {
   }
   const int y = ty0 + ry;
   if (y < a.pny) {
-    float* out = a.V + (((size_t)fl * a.n_slices + s) * a.pny + y) * a.pnx;
+    float* out = a.V + (((size_t)fl * gridDim.y + blockIdx.y) * a.pny + y) * a.pnx;
 #pragma unroll
     for (int j = 0; j < 4; ++j)
       if (tx0 + cx + j < a.pnx) out[tx0 + cx + j] = acc[j];
@@ -240,7 +240,8 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS) k_row(PassArgs a) {
     const int oy = a.plane ? 0 : a.origin[2 * p + 1];
     int yy = oy + y;
     if (yy >= a.pny) yy -= a.pny;
-    const float* vrow = a.V + (((size_t)fl * a.n_slices + a.slice) * a.pny + yy) * (size_t)a.pnx;
+    const float* vrow =
+        a.V + (((size_t)fl * a.v_slices + (a.slice - a.v_slice0)) * a.pny + yy) * (size_t)a.pnx;
     for (int x = t; x < N; x += G) {
       int xx = ox + x;
       if (xx >= a.pnx) xx -= a.pnx;
@@ -261,7 +262,7 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS) k_row(PassArgs a) {
 template <int N>
 struct ColCfg {
   static constexpr int G = Plan<N>::G;
-  static constexpr int CT = N <= 512 ? COL_CT : 4;
+  static constexpr int CT = N <= 512 ? COL_CT : COL_CT / 2;
   static constexpr int LD = N + 1;  // padded column stride in LDS
   static constexpr int THREADS = G * CT;
 };
@@ -434,8 +435,8 @@ hipError_t launch_col_pass(const PassArgs& a, int mode, hipStream_t s) {
   }
 }
 
-hipError_t launch_splat(const SplatArgs& a, hipStream_t s) {
-  dim3 grid(a.tiles_x * a.tiles_y, a.n_slices, a.fb), block(256);
+hipError_t launch_splat(const SplatArgs& a, int n_slices_launch, hipStream_t s) {
+  dim3 grid(a.tiles_x * a.tiles_y, n_slices_launch, a.fb), block(256);
   hipLaunchKernelGGL(k_splat, grid, block, 0, s, a);
   return hipGetLastError();
 }

@@ -148,14 +148,31 @@ tacaw_status validate_desc(const tacaw_job_desc* d) {
   return TACAW_OK;
 }
 
-// Frames whose potentials are materialised at once: up to ~4 GiB of V.
+// Potentials of one slice are built right before that slice's row pass
+// (per-slice mode) unless TACAW_SPLAT_ALL=1 asks for all slices of a frame
+// batch at once.
+bool splat_per_slice() {
+  const char* e = getenv("TACAW_SPLAT_ALL");
+  return !(e && atoi(e) != 0);
+}
+
+// Frames per batch: the waves and potentials of one batch should stay within
+// ~192 MiB, so that between the row and column passes of a slice they can
+// live in the 256 MiB last-level cache.  TACAW_FB overrides the choice and
+// TACAW_BATCH_MB the target.
 int choose_frame_batch(const tacaw_job_desc* d) {
+  if (const char* e = getenv("TACAW_FB")) {
+    const int fb = atoi(e);
+    if (fb > 0) return std::min(fb, d->n_frames);
+  }
   const int pnx = d->pot_nx > 0 ? d->pot_nx : d->nx;
   const int pny = d->pot_ny > 0 ? d->pot_ny : d->ny;
-  const double per_frame = (double)d->n_slices * pnx * pny * sizeof(float);
-  double budget = 4.0 * (1ull << 30);
-  if (const char* e = getenv("TACAW_V_BUDGET_MB")) budget = atof(e) * (1 << 20);
-  int fb = (int)std::max(1.0, floor(budget / per_frame));
+  const double P = d->aperture_mrad == 0.0 ? 1.0 : (double)d->n_probes;
+  const double v_slices = splat_per_slice() ? 1.0 : (double)d->n_slices;
+  const double per_frame = P * d->nx * d->ny * 8.0 + v_slices * pnx * pny * 4.0;
+  double target = 192.0 * (1 << 20);
+  if (const char* e = getenv("TACAW_BATCH_MB")) target = atof(e) * (1 << 20);
+  const int fb = (int)std::max(1.0, floor(target / per_frame));
   return std::min(fb, d->n_frames);
 }
 
@@ -169,7 +186,7 @@ Footprint footprint_of(const tacaw_job_desc* d, int fb, size_t n_tile_atoms) {
   const size_t M = (d->flags & TACAW_TWO_SIDED) ? d->n_frames : d->n_frames / 2;
   f.exit = P * d->n_frames * nk * sizeof(float2);
   f.spec = P * M * nk * sizeof(float);
-  f.V = (size_t)fb * d->n_slices * pnx * pny * sizeof(float);
+  f.V = (size_t)fb * (splat_per_slice() ? 1 : d->n_slices) * pnx * pny * sizeof(float);
   f.pos = (size_t)d->n_frames * d->n_atoms * sizeof(AtomPos) + (size_t)d->n_atoms * sizeof(int32_t);
   f.tiles = n_tile_atoms * sizeof(int32_t);
   f.probes = plane ? 0 : P * nk * sizeof(float2) + P * (2 * sizeof(int32_t) + 2 * sizeof(double));
@@ -205,6 +222,7 @@ tacaw_status plan_job(const tacaw_job_desc* d, const int32_t* atom_species, cons
   hp.sigma = sigma_rad_per_VA(d->voltage_V);
   hp.alpha = d->aperture_mrad * 1e-3;
   hp.fb = choose_frame_batch(d);
+  hp.splat_per_slice = splat_per_slice();
 
   for (int j = 0; j < hp.A; ++j)
     if (atom_species[j] < 0 || atom_species[j] >= hp.S) {

@@ -28,6 +28,7 @@ struct HostPlan {
   float rcx = 0, rcy = 0;
   int img_x = 0, img_y = 0, tiles_x = 0, tiles_y = 0;
   int fb = 1;                          // frames per batch
+  bool splat_per_slice = true;         // potentials built slice by slice
   std::vector<int32_t> slice_of;       // per input atom
   std::vector<int32_t> order;          // sorted position -> input atom
   std::vector<int32_t> tile_start;     // [ns * tiles + 1]
@@ -46,6 +47,7 @@ struct Footprint {
 
 tacaw_status validate_desc(const tacaw_job_desc* d);
 int choose_frame_batch(const tacaw_job_desc* d);
+bool splat_per_slice();
 Footprint footprint_of(const tacaw_job_desc* d, int fb, size_t n_tile_atoms_estimate);
 double wavelength_A(double volt);
 double sigma_rad_per_VA(double volt);
@@ -112,6 +114,8 @@ struct tacaw_job {
   int32_t* d_origin = nullptr;
   double* d_rloc = nullptr;
   int* d_count = nullptr;
+  std::vector<tacaw::AtomPos> enc;   // encoded positions, kept until the device copy exists
+  bool materialized = false;
   hipStream_t last_stream = nullptr;
   bool has_result = false;
   // serving state
@@ -119,5 +123,7 @@ struct tacaw_job {
   std::atomic<bool> cancel_req{false};
   int next_frame = 0;                // serving: next frame batch start
   int next_slice = 0;
-  double t_submit = 0, t_done = 0;
+  double t_submit = 0, t_admit = 0, t_done = 0;
+  size_t retained = 0;               // bytes counted in ctx->resident after a served job ends
+  bool served = false;
 };

@@ -18,7 +18,7 @@ constexpr int N_GAUSS = 5;
 constexpr int SPLAT_TX = 64;   // splat tile: columns
 constexpr int SPLAT_TY = 16;   // splat tile: rows
 constexpr int SPLAT_MC = 16;   // candidate atoms staged in LDS per round
-constexpr int COL_CT = 8;      // columns per column-pass workgroup
+constexpr int COL_CT = 16;     // columns per column-pass workgroup (128-byte rows)
 
 // Projected potentials of a batch of frames.
 struct SplatArgs {
@@ -27,8 +27,8 @@ struct SplatArgs {
   const int32_t* tile_start;   // [n_slices * tiles + 1] CSR offsets
   const int32_t* tile_atoms;   // sorted-atom indices
   const float* coef;           // [S][5][3]: amplitude (V A), exp2 factor x, exp2 factor y
-  float* V;                    // [fb][n_slices][pny][pnx]
-  int n_atoms, f0, fb, n_slices, pnx, pny, tiles_x, tiles_y;
+  float* V;                    // [fb][gridDim.y][pny][pnx]: slices slice0 .. slice0+gridDim.y-1
+  int n_atoms, f0, fb, n_slices, slice0, pnx, pny, tiles_x, tiles_y;
   float rcx, rcy;              // truncation radius in pixels along x and y
   int img_x, img_y;            // periodic images -img..img searched per axis
 };
@@ -36,7 +36,7 @@ struct SplatArgs {
 // One row or column pass over a batch of (probe, frame) waves.
 struct PassArgs {
   float2* exit;                // [P][F][ny][nx] exit store, also the in-flight waves
-  const float* V;              // [fb][n_slices][pny][pnx]
+  const float* V;              // [fb][v_slices][pny][pnx], holding slices v_slice0 ..
   const float2* probe0;        // [P][ny][nx] incident probes (real space)
   const int32_t* origin;       // [P][2] window origin on the potential grid
   const float2* tw_x;          // [nx] exp(-2 pi i m / nx)
@@ -44,6 +44,7 @@ struct PassArgs {
   const float2* px;            // [nx] propagator factor along kx (scaled)
   const float2* py;            // [ny]
   int nx, ny, pnx, pny, n_frames, f0, fb, n_probes, n_slices, slice;
+  int v_slices, v_slice0;      // slices per frame held in V and the first of them
   float sigma;                 // interaction parameter [rad / (V A)]
   float plane_amp;             // 1 / sqrt(nx ny)
   int plane;                   // 1: plane-wave incident wave
@@ -62,7 +63,7 @@ enum ColMode { COL_REGULAR = 0, COL_LAST = 1, COL_INVERSE_ONLY = 2 };
 
 // Kernel launchers (kernels.hip).  Each returns hipSuccess or the launch error.
 bool grid_supported(int n);
-hipError_t launch_splat(const SplatArgs& a, hipStream_t s);
+hipError_t launch_splat(const SplatArgs& a, int n_slices_launch, hipStream_t s);
 hipError_t launch_row_pass(const PassArgs& a, int mode, hipStream_t s);
 hipError_t launch_col_pass(const PassArgs& a, int mode, hipStream_t s);
 hipError_t launch_time_stage(const TimeArgs& a, hipStream_t s);

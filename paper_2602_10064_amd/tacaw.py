@@ -20,6 +20,7 @@ STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "EBUSY", 5: 
                 6: "ECANCELLED", 7: "EUNSUPPORTED"}
 TWO_SIDED = 1
 KEEP_EXIT_WAVES = 2
+DEFER_ALLOC = 4
 
 K_SPLAT, K_ROW, K_COL, K_TIME, K_OTHER, K_FUSED = range(6)
 KERNEL_CLASSES = {"splat": K_SPLAT, "row": K_ROW, "col": K_COL, "time": K_TIME, "other": K_OTHER,
@@ -59,7 +60,7 @@ EXPORTED = [
     "tacaw_ctx_create", "tacaw_ctx_destroy", "tacaw_job_footprint", "tacaw_job_create", "tacaw_run",
     "tacaw_submit", "tacaw_poll", "tacaw_wait", "tacaw_cancel", "tacaw_get_spectrum",
     "tacaw_get_exit_waves", "tacaw_axes", "tacaw_job_slices", "tacaw_job_destroy", "tacaw_last_error",
-    "tacaw_timing_enable", "tacaw_timing_get", "tacaw_version",
+    "tacaw_timing_enable", "tacaw_timing_get", "tacaw_version", "tacaw_job_latency",
 ]
 
 
@@ -91,6 +92,7 @@ def lib() -> ctypes.CDLL:
         "tacaw_job_destroy": [vp],
         "tacaw_timing_enable": [vp, ctypes.c_int],
         "tacaw_timing_get": [vp, ctypes.c_int, P(dp), P(ctypes.c_int64)],
+        "tacaw_job_latency": [vp, P(dp), P(dp)],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -188,10 +190,13 @@ class Context:
 class TacawJob:
     """tacaw_job created from a workloads.Job (inputs copied by the library)."""
 
-    def __init__(self, ctx: Context, job, keep_exit_waves: Optional[bool] = None):
+    def __init__(self, ctx: Context, job, keep_exit_waves: Optional[bool] = None,
+                 defer_alloc: bool = False):
         self.ctx = ctx
         self.job = job
         self._d = _DescHolder(job, keep_exit_waves)
+        if defer_alloc:
+            self._d.desc.flags |= DEFER_ALLOC
         sp = np.ascontiguousarray(job.atom_species, dtype=np.int32)
         pos = np.ascontiguousarray(job.positions, dtype=np.float64)
         h = ctypes.c_void_p()
@@ -218,6 +223,16 @@ class TacawJob:
 
     def cancel(self):
         _check(lib().tacaw_cancel(self.handle))
+
+    def submit(self):
+        _check(lib().tacaw_submit(self.ctx.handle, self.handle))
+
+    def latency_ms(self) -> tuple:
+        """(queued_ms, total_ms) of a job that finished in the serving loop."""
+        q = ctypes.c_double()
+        t = ctypes.c_double()
+        _check(lib().tacaw_job_latency(self.handle, ctypes.byref(q), ctypes.byref(t)))
+        return q.value, t.value
 
     @property
     def spectrum_shape(self):

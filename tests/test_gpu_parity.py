@@ -93,9 +93,19 @@ def test_small_jobs(tacaw, ctx, oracle, kw):
 
 def test_c2_shape_reduced_frames_ragged_batches(tacaw, ctx, oracle, monkeypatch):
     # full 512^2 grid, 32 slices, 9216 atoms; 16 frames in batches of 5 (5+5+5+1)
-    monkeypatch.setenv("TACAW_V_BUDGET_MB", str(5 * 32))
+    monkeypatch.setenv("TACAW_FB", "5")
     job = w.c2_plain(n_frames=16)
     check_job(tacaw, ctx, oracle, job)
+
+
+def test_splat_all_slices_mode_matches(tacaw, ctx, monkeypatch):
+    # potentials of all slices of a batch at once give bitwise the same result
+    job = w.c1_tiny(n_frames=16)
+    _, a, _ = run_gpu(tacaw, ctx, job)
+    monkeypatch.setenv("TACAW_SPLAT_ALL", "1")
+    monkeypatch.setenv("TACAW_FB", "3")
+    _, b, _ = run_gpu(tacaw, ctx, job)
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
 
 
 def test_determinism_bitwise(tacaw, ctx):

@@ -1,0 +1,115 @@
+"""Serving loop through the C ABI (needs an MI355X): admission by footprint,
+continuous batching across requests, cancellation, and bitwise equality of
+every result alone and in the mix."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_2602_10064_amd import workloads as w
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tacaw():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2602_10064_amd import tacaw as t
+    t.lib()
+    return t
+
+
+def mix():
+    jobs = [
+        w.c1_tiny(n_frames=32),
+        w.random_small_job(31, nx=96, ny=64, n_slices=5, n_frames=10, cell=(12.0, 8.0, 6.0), n_atoms=12),
+        w.random_small_job(32, nx=64, ny=64, n_slices=3, n_frames=8, cell=(8.0, 8.0, 4.0),
+                           aperture_mrad=30.0, n_probes=3, voltage_V=60e3),
+        w.random_small_job(33, nx=32, ny=32, n_slices=3, n_frames=12, cell=(10.0, 9.0, 4.0),
+                           aperture_mrad=25.0, n_probes=4, pot_grid=(100, 90)),
+        w.c2_plain(n_frames=6, grid=256, n_slices=8, reps=(6, 6, 2)),
+        w.random_small_job(34, nx=128, ny=128, n_slices=4, n_frames=16, cell=(16.0, 16.0, 5.0),
+                           n_atoms=30, two_sided=True),
+    ]
+    return jobs
+
+
+def alone(tacaw, ctx, job):
+    with tacaw.TacawJob(ctx, job) as j:
+        j.run()
+        return j.spectrum()
+
+
+def test_alone_vs_mix_bitwise(tacaw):
+    jobs = mix()
+    with tacaw.Context(0) as ctx:
+        ref = [alone(tacaw, ctx, j) for j in jobs]
+    # a budget that holds about two of these jobs at once forces queueing
+    fps = sorted(tacaw.footprint(j) for j in jobs)
+    budget = fps[-1] + fps[-2] + (64 << 20)
+    with tacaw.Context(0, hbm_budget_bytes=budget) as ctx:
+        handles = [tacaw.TacawJob(ctx, j, defer_alloc=True) for j in jobs]
+        for h in handles:
+            h.submit()
+        for h in handles:
+            h.wait()
+            assert h.poll()
+        for h, r in zip(handles, ref):
+            got = h.spectrum()
+            assert np.array_equal(got.view(np.uint32), r.view(np.uint32)), h.job.name
+            q, t = h.latency_ms()
+            assert 0 <= q <= t
+        for h in handles:
+            h.destroy()
+
+
+def test_cancel_and_reject(tacaw):
+    jobs = mix()
+    with tacaw.Context(0) as ctx:
+        ref = [alone(tacaw, ctx, j) for j in jobs[:3]]
+    big = w.c2_plain(n_frames=128)           # 256 MiB of exit waves alone
+    with tacaw.Context(0, hbm_budget_bytes=200 << 20) as ctx:
+        hb = tacaw.TacawJob(ctx, big, defer_alloc=True)
+        with pytest.raises(tacaw.TacawError) as e:
+            hb.submit()                       # can never fit 200 MiB: rejected
+        assert e.value.status == 2
+        hb.destroy()
+        hs = [tacaw.TacawJob(ctx, j, defer_alloc=True) for j in jobs[:3]]
+        victim = tacaw.TacawJob(ctx, w.c1_tiny(n_frames=64), defer_alloc=True)
+        for h in hs[:2]:
+            h.submit()
+        victim.submit()
+        victim.cancel()
+        hs[2].submit()
+        with pytest.raises(tacaw.TacawError) as e:
+            victim.wait()
+        assert e.value.status == 6
+        for h, r in zip(hs, ref):
+            h.wait()
+            assert np.array_equal(h.spectrum().view(np.uint32), r.view(np.uint32))
+        # a cancelled job can be submitted again and completes
+        victim.submit()
+        victim.wait()
+        assert np.isfinite(victim.spectrum()).all()
+        for h in hs + [victim]:
+            h.destroy()
+
+
+def test_streamed_arrivals_overlap(tacaw):
+    # requests arrive while others run; all complete with latency recorded
+    rng = np.random.default_rng(5)
+    jobs = [w.c1_tiny(n_frames=32, seed=s) for s in range(1, 9)]
+    with tacaw.Context(0) as ctx:
+        hs = []
+        for j in jobs:
+            h = tacaw.TacawJob(ctx, j, defer_alloc=True)
+            h.submit()
+            hs.append(h)
+            time.sleep(float(rng.exponential(0.002)))
+        for h in hs:
+            h.wait()
+        lat = np.array([h.latency_ms()[1] for h in hs])
+        assert np.all(lat > 0)
+        for h in hs:
+            h.destroy()
