@@ -53,6 +53,8 @@ typedef enum {
 #define TACAW_KEEP_EXIT_WAVES 2u  /* keep psi(k, t) readable after the time stage  */
 #define TACAW_DEFER_ALLOC 4u      /* allocate device memory only when the job is run
                                      or admitted by the serving loop                 */
+#define TACAW_USE_GRAPH 8u        /* tacaw_run captures the job's whole launch
+                                     sequence into a HIP graph once and replays it   */
 
 typedef struct tacaw_ctx tacaw_ctx;
 typedef struct tacaw_job tacaw_job;
@@ -67,8 +69,8 @@ typedef struct tacaw_job tacaw_job;
  * projected potential v_s(r) = C sum_i a_i (pi/b_i) exp(-pi^2 r^2 / b_i) (V A)
  * is point-sampled at grid nodes r_p = (p_x Lx/Nx, p_y Ly/Ny) and summed over
  * the atoms of a slice and their periodic images.  The library truncates each
- * atom at r_c = sqrt(b_max ln 1e8)/pi, which changes V by at most 1e-8 of an
- * atom's peak.
+ * Gaussian term of an atom (box cutoff per axis) at r_i = sqrt(b_i ln 1e8)/pi,
+ * where it has fallen below 1e-8 of its peak.
  *
  * Slices (Methods 2.2, "atoms within the slice z-bounds"): atom j belongs to
  * slice floor((zbar_j mod Lz)/dz), clamped to [0, n_slices), where zbar_j is
@@ -113,7 +115,8 @@ typedef struct {
   const int32_t* species_Z;    /* n_species atomic numbers (labels only)                 */
   const double* gauss_a;       /* n_species x 5 form-factor amplitudes [A], > 0          */
   const double* gauss_b;       /* n_species x 5 form-factor widths [A^2], > 0            */
-  uint32_t flags;              /* TACAW_TWO_SIDED | TACAW_KEEP_EXIT_WAVES | TACAW_DEFER_ALLOC */
+  uint32_t flags;              /* TACAW_TWO_SIDED, TACAW_KEEP_EXIT_WAVES, TACAW_DEFER_ALLOC,
+                                  TACAW_USE_GRAPH                                        */
 } tacaw_job_desc;
 
 /* ---- context ------------------------------------------------------------ */
@@ -151,6 +154,23 @@ tacaw_status tacaw_job_create(tacaw_ctx* ctx, const tacaw_job_desc* desc,
  * return without waiting.  May be called again to recompute.  EBUSY while the
  * job is in the serving loop. */
 tacaw_status tacaw_run(tacaw_job* job, void* hip_stream);
+
+/* Batched form for uneven jobs (several grids, slice and frame counts): run
+ * n_jobs jobs of one context together, ordered on `hip_stream`.  Jobs with
+ * the same grid share launches: each launch advances up to 8 frame batches
+ * of different jobs by one pass, each at its own slice, and a finished frame
+ * batch is replaced by the next one at once.  Groups of different grid sizes
+ * run on the context's own streams and are joined back to `hip_stream`.
+ * Every result equals the job's tacaw_run result bit for bit. */
+tacaw_status tacaw_run_batch(tacaw_job* const* jobs, int n_jobs, void* hip_stream);
+
+/* Autotuner: time the row-pass and column-pass tile variants (rows per
+ * workgroup, columns per workgroup) on one frame batch of `job` and keep the
+ * faster of each for the job's grid size in the context (appended to the
+ * JSON-lines file named by $TACAW_TUNE_CACHE, read back by later contexts).
+ * Writes the chosen variants (0 or 1) when the pointers are not NULL.  Resets
+ * the context's timing totals. */
+tacaw_status tacaw_autotune(tacaw_job* job, void* hip_stream, int* row_variant, int* col_variant);
 
 /* Serving form: hand the job to the context's continuous-batching loop.
  * The loop admits it once its footprint fits the budget next to the jobs

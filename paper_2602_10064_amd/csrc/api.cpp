@@ -3,6 +3,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <functional>
 #include <vector>
 
 #include "runtime.h"
@@ -36,7 +37,15 @@ hipError_t dalloc(T** p, size_t count) {
   return hipMalloc((void**)p, count * sizeof(T));
 }
 
+void drop_graph(tacaw_job* j) {
+  if (j->graph_exec) (void)hipGraphExecDestroy(j->graph_exec);
+  if (j->graph) (void)hipGraphDestroy(j->graph);
+  j->graph_exec = nullptr;
+  j->graph = nullptr;
+}
+
 void free_job_buffers(tacaw_job* j) {
+  drop_graph(j);
   void* bufs[] = {j->d_exit,    j->d_spec,   j->d_V,      j->d_pos,     j->d_species,   j->d_tile_start,
                   j->d_tile_atoms, j->d_coef, j->d_tw_x,  j->d_tw_y,    j->d_tw_t,      j->d_px,
                   j->d_py,      j->d_px_last, j->d_py_last, j->d_probe0, j->d_origin,   j->d_rloc,
@@ -87,10 +96,17 @@ void drain_records(tacaw_ctx* c) {
 
 namespace tacaw {
 
+int row_variant_for(tacaw_ctx* c, int n) {
+  const int v = (n > 0 && n < 2048) ? c->row_variant[n] : 0;
+  return v ? v - 1 : 1;
+}
+int col_variant_for(tacaw_ctx* c, int n) {
+  const int v = (n > 0 && n < 2048) ? c->col_variant[n] : 0;
+  return v ? v - 1 : 1;
+}
+
 // Launch wrapper: brackets the launch with events on its stream when timing.
-template <typename F>
-static tacaw_status timed(tacaw_job* job, int cls, hipStream_t s, F&& launch) {
-  tacaw_ctx* c = job->ctx;
+tacaw_status timed_launch(tacaw_ctx* c, int cls, hipStream_t s, const std::function<hipError_t()>& launch) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   bool tm = false;
   {
@@ -116,7 +132,12 @@ static tacaw_status timed(tacaw_job* job, int cls, hipStream_t s, F&& launch) {
   return TACAW_OK;
 }
 
-static PassArgs pass_args(tacaw_job* j) {
+template <typename F>
+static tacaw_status timed(tacaw_job* job, int cls, hipStream_t s, F&& launch) {
+  return timed_launch(job->ctx, cls, s, std::function<hipError_t()>(launch));
+}
+
+PassArgs pass_args(tacaw_job* j) {
   const HostPlan& hp = j->hp;
   PassArgs a{};
   a.exit = j->d_exit;
@@ -183,16 +204,22 @@ tacaw_status run_batch_range(tacaw_job* job, hipStream_t s, int f_begin, int f_e
         st = timed(job, TACAW_K_SPLAT, s, [&] { return launch_splat(sa, 1, s); });
         if (st != TACAW_OK) return st;
       }
-      const int rmode = sl == 0 ? ROW_FIRST : ROW_REGULAR;
-      st = timed(job, TACAW_K_ROW, s, [&] { return launch_row_pass(a, rmode, s); });
+      PassLane rl{};
+      rl.a = a;
+      rl.mode = sl == 0 ? ROW_FIRST : ROW_REGULAR;
+      const int rv = row_variant_for(job->ctx, hp.nx);
+      st = timed(job, TACAW_K_ROW, s, [&] { return launch_row_lanes(&rl, 1, rv, s); });
       if (st != TACAW_OK) return st;
       const bool last = sl == hp.ns - 1;
-      PassArgs ca = a;
+      PassLane cl{};
+      cl.a = a;
       if (last) {
-        ca.px = job->d_px_last;
-        ca.py = job->d_py_last;
+        cl.a.px = job->d_px_last;
+        cl.a.py = job->d_py_last;
       }
-      st = timed(job, TACAW_K_COL, s, [&] { return launch_col_pass(ca, last ? COL_LAST : COL_REGULAR, s); });
+      cl.mode = last ? COL_LAST : COL_REGULAR;
+      const int cv = col_variant_for(job->ctx, hp.ny);
+      st = timed(job, TACAW_K_COL, s, [&] { return launch_col_lanes(&cl, 1, cv, s); });
       if (st != TACAW_OK) return st;
     }
   }
@@ -459,6 +486,35 @@ tacaw_status tacaw_run(tacaw_job* job, void* hip_stream) {
   if (st != TACAW_OK) return st;
   hipStream_t s = (hipStream_t)hip_stream;
   job->last_stream = s;
+  bool timing = false;
+  {
+    std::lock_guard<std::mutex> lk(job->ctx->mu);
+    timing = job->ctx->timing;
+  }
+  if ((job->desc.flags & TACAW_USE_GRAPH) && !timing) {
+    if (!job->graph_exec) {
+      // capture on the job's own stream, replay on any stream
+      if (!job->capture_stream) HIP_TRY(hipStreamCreateWithFlags(&job->capture_stream, hipStreamNonBlocking));
+      HIP_TRY(hipStreamBeginCapture(job->capture_stream, hipStreamCaptureModeThreadLocal));
+      st = run_batch_range(job, job->capture_stream, 0, job->hp.F);
+      if (st == TACAW_OK) st = run_time_stage(job, job->capture_stream);
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamEndCapture(job->capture_stream, &g);
+      if (st != TACAW_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+      }
+      if (e != hipSuccess) {
+        set_error("graph capture failed: %s", hipGetErrorString(e));
+        return TACAW_EDEVICE;
+      }
+      job->graph = g;
+      HIP_TRY(hipGraphInstantiate(&job->graph_exec, job->graph, nullptr, nullptr, 0));
+    }
+    HIP_TRY(hipGraphLaunch(job->graph_exec, s));
+    job->has_result = true;
+    return TACAW_OK;
+  }
   st = run_batch_range(job, s, 0, job->hp.F);
   if (st != TACAW_OK) return st;
   st = run_time_stage(job, s);
@@ -588,6 +644,7 @@ tacaw_status tacaw_job_destroy(tacaw_job* job) {
     job->ctx->resident -= job->retained;
   }
   free_job_buffers(job);
+  if (job->capture_stream) (void)hipStreamDestroy(job->capture_stream);
   delete job;
   return TACAW_OK;
 }

@@ -1,0 +1,304 @@
+// Batched execution of uneven jobs, the autotuner, and HIP-graph replay of a
+// job's launch sequence.
+//
+// Batched form: jobs are grouped by grid size; inside a group a launch
+// advances up to MAX_LANES lanes by one pass, a lane being one frame batch of
+// one job at its own slice (each lane has its own potentials, exit store,
+// tables and mode).  When a lane finishes its last slice the next frame batch
+// (of the same or another job) takes its place, so slice steps of different
+// jobs are batched continuously.  A job has at most one lane in flight (its
+// potential buffer holds one slice of one frame batch).  Groups run on their
+// own streams, joined back to the caller's stream.  Every wave is computed by
+// the same per-row and per-column arithmetic as in tacaw_run, so results are
+// bitwise those of the plain form.
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <deque>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <vector>
+
+#include "runtime.h"
+
+using namespace tacaw;
+
+namespace {
+
+struct BLane {
+  tacaw_job* job;
+  int f0, fb, slice;
+};
+
+tacaw_status ensure_streams(tacaw_ctx* c) {
+  for (auto& st : c->batch_streams)
+    if (!st && hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+      set_error("hipStreamCreate failed");
+      return TACAW_EDEVICE;
+    }
+  return TACAW_OK;
+}
+
+SplatArgs splat_args(tacaw_job* j, int f0, int fb, int slice) {
+  const HostPlan& hp = j->hp;
+  SplatArgs sa{};
+  sa.pos = j->d_pos;
+  sa.species = j->d_species;
+  sa.tile_start = j->d_tile_start;
+  sa.tile_atoms = j->d_tile_atoms;
+  sa.coef = j->d_coef;
+  sa.V = j->d_V;
+  sa.n_atoms = hp.A;
+  sa.f0 = f0;
+  sa.fb = fb;
+  sa.n_slices = hp.ns;
+  sa.slice0 = slice;
+  sa.pnx = hp.pnx;
+  sa.pny = hp.pny;
+  sa.tiles_x = hp.tiles_x;
+  sa.tiles_y = hp.tiles_y;
+  sa.rcx = hp.rcx;
+  sa.rcy = hp.rcy;
+  sa.img_x = hp.img_x;
+  sa.img_y = hp.img_y;
+  return sa;
+}
+
+// One group of same-grid jobs on one stream.
+tacaw_status run_group(tacaw_ctx* c, std::vector<tacaw_job*>& jobs, hipStream_t s) {
+  std::deque<BLane> pending;
+  for (tacaw_job* j : jobs)
+    for (int f0 = 0; f0 < j->hp.F; f0 += j->hp.fb) pending.push_back({j, f0, std::min(j->hp.fb, j->hp.F - f0), 0});
+  std::vector<BLane> active;
+  std::map<tacaw_job*, int> left;  // frame batches not finished per job
+  for (tacaw_job* j : jobs) left[j] = (j->hp.F + j->hp.fb - 1) / j->hp.fb;
+  const int nx = jobs[0]->hp.nx, ny = jobs[0]->hp.ny;
+  const int rv = row_variant_for(c, nx), cv = col_variant_for(c, ny);
+  while (!pending.empty() || !active.empty()) {
+    // fill free lanes, at most one lane per job
+    for (auto it = pending.begin(); it != pending.end() && (int)active.size() < MAX_LANES;) {
+      bool busy = false;
+      for (auto& l : active) busy |= l.job == it->job;
+      if (busy) {
+        ++it;
+        continue;
+      }
+      active.push_back(*it);
+      it = pending.erase(it);
+    }
+    const int n = (int)active.size();
+    SplatLane sl[MAX_LANES];
+    PassLane rl[MAX_LANES], cl[MAX_LANES];
+    for (int i = 0; i < n; ++i) {
+      BLane& L = active[i];
+      tacaw_job* j = L.job;
+      sl[i] = SplatLane{};
+      sl[i].a = splat_args(j, L.f0, L.fb, L.slice);
+      sl[i].n_slices_launch = 1;
+      PassArgs a = pass_args(j);
+      a.f0 = L.f0;
+      a.fb = L.fb;
+      a.slice = L.slice;
+      a.v_slices = 1;
+      a.v_slice0 = L.slice;
+      rl[i] = PassLane{};
+      rl[i].a = a;
+      rl[i].mode = L.slice == 0 ? ROW_FIRST : ROW_REGULAR;
+      const bool last = L.slice == j->hp.ns - 1;
+      cl[i] = PassLane{};
+      cl[i].a = a;
+      if (last) {
+        cl[i].a.px = j->d_px_last;
+        cl[i].a.py = j->d_py_last;
+      }
+      cl[i].mode = last ? COL_LAST : COL_REGULAR;
+    }
+    tacaw_status st = timed_launch(c, TACAW_K_SPLAT, s, [&] { return launch_splat_lanes(sl, n, s); });
+    if (st != TACAW_OK) return st;
+    st = timed_launch(c, TACAW_K_ROW, s, [&] { return launch_row_lanes(rl, n, rv, s); });
+    if (st != TACAW_OK) return st;
+    st = timed_launch(c, TACAW_K_COL, s, [&] { return launch_col_lanes(cl, n, cv, s); });
+    if (st != TACAW_OK) return st;
+    std::vector<BLane> still;
+    for (auto& L : active) {
+      L.slice += 1;
+      if (L.slice < L.job->hp.ns) {
+        still.push_back(L);
+      } else if (--left[L.job] == 0) {
+        st = run_time_stage(L.job, s);
+        if (st != TACAW_OK) return st;
+        L.job->has_result = true;
+        L.job->last_stream = s;
+      }
+    }
+    active.swap(still);
+  }
+  return TACAW_OK;
+}
+
+void load_tune_cache(tacaw_ctx* c) {
+  if (c->tune_loaded) return;
+  c->tune_loaded = true;
+  const char* path = getenv("TACAW_TUNE_CACHE");
+  if (!path) return;
+  c->tune_cache = path;
+  std::ifstream in(path);
+  std::string line;
+  while (std::getline(in, line)) {
+    int nx = 0, ny = 0, r = 0, cc = 0;
+    if (sscanf(line.c_str(), "{\"nx\": %d, \"ny\": %d, \"row_variant\": %d, \"col_variant\": %d}", &nx, &ny, &r,
+               &cc) == 4 &&
+        nx > 0 && nx < 2048 && ny > 0 && ny < 2048 && (r == 0 || r == 1) && (cc == 0 || cc == 1)) {
+      c->row_variant[nx] = r + 1;
+      c->col_variant[ny] = cc + 1;
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+tacaw_status tacaw_run_batch(tacaw_job* const* jobs, int n_jobs, void* hip_stream) {
+  clear_error();
+  if (!jobs || n_jobs < 1) {
+    set_error("need at least one job");
+    return TACAW_EINVAL;
+  }
+  tacaw_ctx* c = jobs[0]->ctx;
+  for (int i = 0; i < n_jobs; ++i) {
+    if (!jobs[i] || jobs[i]->ctx != c) {
+      set_error("job %d is NULL or belongs to another context", i);
+      return TACAW_EINVAL;
+    }
+    const int ss = jobs[i]->serve_state.load();
+    if (ss == 1 || ss == 2) {
+      set_error("job %d is in the serving loop", i);
+      return TACAW_EBUSY;
+    }
+    for (int k = 0; k < i; ++k)
+      if (jobs[k] == jobs[i]) {
+        set_error("job %d appears twice", i);
+        return TACAW_EINVAL;
+      }
+  }
+  if (hipSetDevice(c->device) != hipSuccess) {
+    set_error("hipSetDevice failed");
+    return TACAW_EDEVICE;
+  }
+  load_tune_cache(c);
+  tacaw_status st = ensure_streams(c);
+  if (st != TACAW_OK) return st;
+  hipStream_t user = (hipStream_t)hip_stream;
+  std::map<std::pair<int, int>, std::vector<tacaw_job*>> groups;
+  std::vector<tacaw_job*> plain;   // jobs planned with all-slice potentials run one by one
+  for (int i = 0; i < n_jobs; ++i) {
+    st = materialize(jobs[i], nullptr);
+    if (st != TACAW_OK) return st;
+    if (jobs[i]->hp.splat_per_slice)
+      groups[{jobs[i]->hp.nx, jobs[i]->hp.ny}].push_back(jobs[i]);
+    else
+      plain.push_back(jobs[i]);
+  }
+  hipEvent_t start;
+  if (hipEventCreateWithFlags(&start, hipEventDisableTiming) != hipSuccess) {
+    set_error("hipEventCreate failed");
+    return TACAW_EDEVICE;
+  }
+  (void)hipEventRecord(start, user);
+  int k = 0;
+  bool used[4] = {false, false, false, false};
+  for (auto& g : groups) {
+    hipStream_t s = c->batch_streams[k % 4];
+    if (!used[k % 4]) (void)hipStreamWaitEvent(s, start, 0);
+    used[k % 4] = true;
+    st = run_group(c, g.second, s);
+    if (st != TACAW_OK) break;
+    ++k;
+  }
+  for (int i = 0; i < 4 && st == TACAW_OK; ++i) {
+    if (!used[i]) continue;
+    hipEvent_t done;
+    if (hipEventCreateWithFlags(&done, hipEventDisableTiming) != hipSuccess) continue;
+    (void)hipEventRecord(done, c->batch_streams[i]);
+    (void)hipStreamWaitEvent(user, done, 0);
+    (void)hipEventDestroy(done);
+  }
+  (void)hipEventDestroy(start);
+  if (st != TACAW_OK) return st;
+  for (tacaw_job* j : plain) {
+    st = run_batch_range(j, user, 0, j->hp.F);
+    if (st != TACAW_OK) return st;
+    st = run_time_stage(j, user);
+    if (st != TACAW_OK) return st;
+    j->has_result = true;
+  }
+  for (int i = 0; i < n_jobs; ++i) jobs[i]->last_stream = user;
+  return TACAW_OK;
+}
+
+tacaw_status tacaw_autotune(tacaw_job* job, void* hip_stream, int* row_variant, int* col_variant) {
+  clear_error();
+  if (!job) {
+    set_error("job is NULL");
+    return TACAW_EINVAL;
+  }
+  tacaw_ctx* c = job->ctx;
+  if (hipSetDevice(c->device) != hipSuccess) {
+    set_error("hipSetDevice failed");
+    return TACAW_EDEVICE;
+  }
+  load_tune_cache(c);
+  tacaw_status st = materialize(job, nullptr);
+  if (st != TACAW_OK) return st;
+  hipStream_t s = (hipStream_t)hip_stream;
+  const HostPlan& hp = job->hp;
+  const int fb = std::min(hp.fb, hp.F);
+  double best_row[2] = {0, 0}, best_col[2] = {0, 0};
+  const bool was_timing = c->timing;
+  for (int v = 0; v < 2; ++v) {
+    c->row_variant[hp.nx] = v + 1;
+    c->col_variant[hp.ny] = v + 1;
+    for (int rep = 0; rep < 2; ++rep) {   // first repetition warms up
+      {
+        std::lock_guard<std::mutex> lk(c->mu);
+        c->timing = true;
+        for (int i = 0; i < TACAW_K_COUNT; ++i) {
+          c->total_ms[i] = 0;
+          c->launches[i] = 0;
+        }
+      }
+      st = run_batch_range(job, s, 0, fb);
+      if (st != TACAW_OK) break;
+      double row_ms = 0, col_ms = 0;
+      int64_t n = 0;
+      tacaw_timing_get(c, TACAW_K_ROW, &row_ms, &n);
+      tacaw_timing_get(c, TACAW_K_COL, &col_ms, &n);
+      best_row[v] = row_ms;
+      best_col[v] = col_ms;
+    }
+    if (st != TACAW_OK) break;
+  }
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    c->timing = was_timing;
+  }
+  if (st != TACAW_OK) return st;
+  const int rv = best_row[1] <= best_row[0] ? 1 : 0;
+  const int cv = best_col[1] <= best_col[0] ? 1 : 0;
+  c->row_variant[hp.nx] = rv + 1;
+  c->col_variant[hp.ny] = cv + 1;
+  if (row_variant) *row_variant = rv;
+  if (col_variant) *col_variant = cv;
+  if (!c->tune_cache.empty()) {
+    std::ofstream out(c->tune_cache, std::ios::app);
+    out << "{\"nx\": " << hp.nx << ", \"ny\": " << hp.ny << ", \"row_variant\": " << rv
+        << ", \"col_variant\": " << cv << "}\n";
+  }
+  return TACAW_OK;
+}
+
+}  // extern "C"

@@ -91,6 +91,19 @@ __global__ void k_probe_fill(float2* out, const double* rloc, const int* count, 
 }
 
 // ---------------------------------------------------------------------------
+// Lane tables: one launch advances up to MAX_LANES (job, frame batch) lanes of
+// the same grid size by one pass; each lane has its own slice and mode.  The
+// table is a by-value kernel argument (read with scalar loads).
+// ---------------------------------------------------------------------------
+template <typename Table>
+__device__ __forceinline__ int find_lane(const Table& t, int b) {
+  int L = 0;
+  for (int i = 1; i < t.n; ++i)
+    if (b >= t.l[i].block_start) L = i;
+  return L;
+}
+
+// ---------------------------------------------------------------------------
 // Projected potential
 // ---------------------------------------------------------------------------
 // sum over periodic images of exp2(-e2 d^2) for |d| <= rc, where d is the
@@ -109,94 +122,143 @@ __device__ __forceinline__ float profile(int node, int ipos, float fpos, int n, 
   return g;
 }
 
-__global__ void __launch_bounds__(256) k_splat(SplatArgs a) {
+// Periodic distance in pixels from position u to the node interval [lo, hi].
+__device__ __forceinline__ float interval_distance(float u, int lo, int hi, int n) {
+  const float c = 0.5f * (float)(lo + hi), h = 0.5f * (float)(hi - lo);
+  float d = u - c;
+  d -= (float)n * rintf(d / (float)n);
+  return fmaxf(0.f, fabsf(d) - h);
+}
+
+// One workgroup computes a 32 x 64 tile of V for one (frame, slice).  Each
+// candidate atom contributes, per Gaussian term, an outer product of a column
+// profile and a row profile (the 2D Gaussian and its periodic images factor
+// into x and y parts); the profiles of up to SPLAT_MC atoms are staged in LDS
+// and every thread accumulates a 2 x 4 block of pixels.  Terms whose own
+// cutoff box misses the tile are skipped by a per-atom bit mask.  The
+// summation order is fixed, so the result is deterministic.
+__global__ void __launch_bounds__(256) k_splat(SplatTable tab) {
   __shared__ float gx[SPLAT_MC][N_GAUSS][SPLAT_TX];
   __shared__ float gy[SPLAT_MC][N_GAUSS][SPLAT_TY];
   __shared__ AtomPos sp_pos[SPLAT_MC];
   __shared__ int sp_spc[SPLAT_MC];
+  __shared__ int sp_mask[SPLAT_MC];
 
+  const int L = find_lane(tab, blockIdx.x);
+  const SplatArgs& a = tab.l[L].a;
+  const int nsl = tab.l[L].n_slices_launch;
+  const int lb = blockIdx.x - tab.l[L].block_start;
   const int tid = threadIdx.x;
   const int n_tiles = a.tiles_x * a.tiles_y;
-  const int tile = blockIdx.x;
-  const int s = a.slice0 + blockIdx.y;
-  const int fl = blockIdx.z;
+  const int tile = lb % n_tiles;
+  const int sl = (lb / n_tiles) % nsl;
+  const int fl = lb / (n_tiles * nsl);
+  const int s = a.slice0 + sl;
   const int f = a.f0 + fl;
   const int tx0 = (tile % a.tiles_x) * SPLAT_TX;
   const int ty0 = (tile / a.tiles_x) * SPLAT_TY;
   const int cs = a.tile_start[s * n_tiles + tile];
   const int ce = a.tile_start[s * n_tiles + tile + 1];
 
-  const int ry = tid / (SPLAT_TX / 4);        // 0..15
-  const int cx = (tid % (SPLAT_TX / 4)) * 4;  // 0..60
-  float acc[4] = {0.f, 0.f, 0.f, 0.f};
+  const int ry = (tid / (SPLAT_TX / 4)) * 2;  // 0, 2, .., 30
+  const int cx = (tid % (SPLAT_TX / 4)) * 4;  // 0, 4, .., 60
+  float acc0[4] = {0.f, 0.f, 0.f, 0.f};
+  float acc1[4] = {0.f, 0.f, 0.f, 0.f};
 
   for (int c0 = cs; c0 < ce; c0 += SPLAT_MC) {
     const int mc = min(SPLAT_MC, ce - c0);
     __syncthreads();
     if (tid < mc) {
       const int atom = a.tile_atoms[c0 + tid];
-      sp_pos[tid] = a.pos[(size_t)f * a.n_atoms + atom];
-      sp_spc[tid] = a.species[atom];
+      const AtomPos p = a.pos[(size_t)f * a.n_atoms + atom];
+      const int spc = a.species[atom];
+      sp_pos[tid] = p;
+      sp_spc[tid] = spc;
+      const float dxs = interval_distance((float)p.ix + p.fx, tx0, tx0 + SPLAT_TX - 1, a.pnx);
+      const float dys = interval_distance((float)p.iy + p.fy, ty0, ty0 + SPLAT_TY - 1, a.pny);
+      int mask = 0;
+      for (int i = 0; i < N_GAUSS; ++i) {
+        const float* c = a.coef + (spc * N_GAUSS + i) * COEF_STRIDE;
+        if (dxs <= c[3] && dys <= c[4]) mask |= 1 << i;
+      }
+      sp_mask[tid] = mask;
     }
     __syncthreads();
     for (int e = tid; e < mc * N_GAUSS * SPLAT_TX; e += 256) {
       const int m = e / (N_GAUSS * SPLAT_TX);
       const int i = (e / SPLAT_TX) % N_GAUSS;
       const int x = e % SPLAT_TX;
-      const float e2 = a.coef[(sp_spc[m] * N_GAUSS + i) * 3 + 1];
-      gx[m][i][x] = profile(tx0 + x, sp_pos[m].ix, sp_pos[m].fx, a.pnx, e2, a.rcx, a.img_x);
+      const float* c = a.coef + (sp_spc[m] * N_GAUSS + i) * COEF_STRIDE;
+      gx[m][i][x] = profile(tx0 + x, sp_pos[m].ix, sp_pos[m].fx, a.pnx, c[1], c[3], a.img_x);
     }
     for (int e = tid; e < mc * N_GAUSS * SPLAT_TY; e += 256) {
       const int m = e / (N_GAUSS * SPLAT_TY);
       const int i = (e / SPLAT_TY) % N_GAUSS;
       const int y = e % SPLAT_TY;
-      const float* c = a.coef + (sp_spc[m] * N_GAUSS + i) * 3;
-      gy[m][i][y] = c[0] * profile(ty0 + y, sp_pos[m].iy, sp_pos[m].fy, a.pny, c[2], a.rcy, a.img_y);
+      const float* c = a.coef + (sp_spc[m] * N_GAUSS + i) * COEF_STRIDE;
+      gy[m][i][y] = c[0] * profile(ty0 + y, sp_pos[m].iy, sp_pos[m].fy, a.pny, c[2], c[4], a.img_y);
     }
     __syncthreads();
     for (int m = 0; m < mc; ++m) {
+      const int mask = sp_mask[m];
 #pragma unroll
       for (int i = 0; i < N_GAUSS; ++i) {
-        const float g = gy[m][i][ry];
+        if (!(mask & (1 << i))) continue;
+        const float2 g = *reinterpret_cast<const float2*>(&gy[m][i][ry]);
         const float4 h = *reinterpret_cast<const float4*>(&gx[m][i][cx]);
-        acc[0] += g * h.x;
-        acc[1] += g * h.y;
-        acc[2] += g * h.z;
-        acc[3] += g * h.w;
+        acc0[0] += g.x * h.x;
+        acc0[1] += g.x * h.y;
+        acc0[2] += g.x * h.z;
+        acc0[3] += g.x * h.w;
+        acc1[0] += g.y * h.x;
+        acc1[1] += g.y * h.y;
+        acc1[2] += g.y * h.z;
+        acc1[3] += g.y * h.w;
       }
     }
   }
-  const int y = ty0 + ry;
-  if (y < a.pny) {
-    float* out = a.V + (((size_t)fl * gridDim.y + blockIdx.y) * a.pny + y) * a.pnx;
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-      if (tx0 + cx + j < a.pnx) out[tx0 + cx + j] = acc[j];
+  for (int r = 0; r < 2; ++r) {
+    const int y = ty0 + ry + r;
+    if (y < a.pny) {
+      float* out = a.V + (((size_t)fl * nsl + sl) * a.pny + y) * a.pnx;
+      const float* acc = r == 0 ? acc0 : acc1;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (tx0 + cx + j < a.pnx) out[tx0 + cx + j] = acc[j];
+    }
   }
 }
 
 // ---------------------------------------------------------------------------
-// Row pass
+// Row pass: [iFFT_x] -> * exp(i sigma V) -> FFT_x for RPI rows per block
 // ---------------------------------------------------------------------------
-template <int N>
+template <int N, int VAR>
 struct RowCfg {
   static constexpr int G = Plan<N>::G;
   static constexpr int cap_thr = 256 / G;
   static constexpr int cap_lds = 4096 / N > 0 ? 4096 / N : 1;
   static constexpr int RPI0 = cap_thr < cap_lds ? cap_thr : cap_lds;
   // largest power of two not above RPI0
-  static constexpr int RPI = RPI0 >= 64 ? 64 : RPI0 >= 32 ? 32 : RPI0 >= 16 ? 16 : RPI0 >= 8 ? 8
-                           : RPI0 >= 4 ? 4 : RPI0 >= 2 ? 2 : 1;
+  static constexpr int RPIB = RPI0 >= 64 ? 64 : RPI0 >= 32 ? 32 : RPI0 >= 16 ? 16 : RPI0 >= 8 ? 8
+                            : RPI0 >= 4 ? 4 : RPI0 >= 2 ? 2 : 1;
+  // variant 1 doubles the rows per block where threads and LDS allow
+  static constexpr int RPI = (VAR == 1 && 2 * RPIB * G <= 1024 && 2 * RPIB * N <= 8192) ? 2 * RPIB : RPIB;
   static constexpr int THREADS = RPI * G;
 };
 
-template <int N, int MODE>
-__global__ void __launch_bounds__(RowCfg<N>::THREADS) k_row(PassArgs a) {
+template <int N, int VAR>
+__global__ void __launch_bounds__((RowCfg<N, VAR>::THREADS)) k_row(PassTable tab) {
   using PL = Plan<N>;
   constexpr int G = PL::G;
-  constexpr int RPI = RowCfg<N>::RPI;
+  constexpr int RPI = RowCfg<N, VAR>::RPI;
   __shared__ float2 tw[N];
   __shared__ float2 rows[RPI][N];
+
+  const int L = find_lane(tab, blockIdx.x);
+  const PassArgs& a = tab.l[L].a;
+  const int mode = tab.l[L].mode;
+  const int lb = blockIdx.x - tab.l[L].block_start;
 
   for (int i = threadIdx.x; i < N; i += blockDim.x) tw[i] = a.tw_x[i];
   const int g = threadIdx.x / G;
@@ -204,7 +266,7 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS) k_row(PassArgs a) {
   float2* buf = rows[g];
 
   const long total = (long)a.n_probes * a.fb * a.ny;
-  const long rid = (long)blockIdx.x * RPI + g;
+  const long rid = (long)lb * RPI + g;
   const bool active = rid < total;
   int p = 0, fl = 0, y = 0;
   float2* row = nullptr;
@@ -217,7 +279,7 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS) k_row(PassArgs a) {
   }
 
   if (active) {
-    if (MODE == ROW_FIRST) {
+    if (mode == ROW_FIRST) {
       if (a.plane) {
         for (int x = t; x < N; x += G) buf[x] = make_float2(a.plane_amp, 0.f);
       } else {
@@ -229,8 +291,8 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS) k_row(PassArgs a) {
     }
   }
   __syncthreads();
-  if (MODE != ROW_FIRST) StagesIP<N, G, true, 1, typename PL::R>::run(buf, tw, t);
-  if (MODE == ROW_INVERSE_ONLY) {
+  if (mode != ROW_FIRST) StagesIP<N, G, true, 1, typename PL::R>::run(buf, tw, t);
+  if (mode == ROW_INVERSE_ONLY) {
     if (active)
       for (int x = t; x < N; x += G) row[x] = buf[x];
     return;
@@ -257,28 +319,34 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS) k_row(PassArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Column pass
+// Column pass: FFT_y -> * P -> [iFFT_y] on CT adjacent columns per block
 // ---------------------------------------------------------------------------
-template <int N>
+template <int N, int VAR>
 struct ColCfg {
   static constexpr int G = Plan<N>::G;
-  static constexpr int CT = N <= 512 ? COL_CT : COL_CT / 2;
+  static constexpr int CTB = N <= 512 ? COL_CT : COL_CT / 2;
+  static constexpr int CT = VAR == 1 ? CTB : CTB / 2;
   static constexpr int LD = N + 1;  // padded column stride in LDS
   static constexpr int THREADS = G * CT;
 };
 
-template <int N, int MODE>
-__global__ void __launch_bounds__(ColCfg<N>::THREADS) k_col(PassArgs a) {
+template <int N, int VAR>
+__global__ void __launch_bounds__((ColCfg<N, VAR>::THREADS)) k_col(PassTable tab) {
   using PL = Plan<N>;
   constexpr int G = PL::G;
-  constexpr int CT = ColCfg<N>::CT;
-  constexpr int LD = ColCfg<N>::LD;
+  constexpr int CT = ColCfg<N, VAR>::CT;
+  constexpr int LD = ColCfg<N, VAR>::LD;
   __shared__ float2 tw[N];
   __shared__ float2 cols[CT * LD];
 
+  const int tile_g = xcd_remap(blockIdx.x, gridDim.x);
+  const int L = find_lane(tab, tile_g);
+  const PassArgs& a = tab.l[L].a;
+  const int mode = tab.l[L].mode;
+  const int tile = tile_g - tab.l[L].block_start;
+
   for (int i = threadIdx.x; i < N; i += blockDim.x) tw[i] = a.tw_y[i];
   const int tiles_per_wave = a.nx / CT;
-  const int tile = xcd_remap(blockIdx.x, gridDim.x);
   const int w = tile / tiles_per_wave;
   const int x0 = (tile % tiles_per_wave) * CT;
   const int p = w / a.fb;
@@ -293,14 +361,14 @@ __global__ void __launch_bounds__(ColCfg<N>::THREADS) k_col(PassArgs a) {
   const int c = threadIdx.x / G;
   const int t = threadIdx.x % G;
   float2* buf = cols + c * LD;
-  if (MODE == COL_INVERSE_ONLY) {
+  if (mode == COL_INVERSE_ONLY) {
     StagesIP<N, G, true, 1, typename PL::R>::run(buf, tw, t);
   } else {
     StagesIP<N, G, false, 1, typename PL::R>::run(buf, tw, t);
     const float2 pxv = a.px[x0 + c];
     for (int yy = t; yy < N; yy += G) buf[yy] = cmul(buf[yy], cmul(pxv, a.py[yy]));
     __syncthreads();
-    if (MODE == COL_REGULAR) StagesIP<N, G, true, 1, typename PL::R>::run(buf, tw, t);
+    if (mode == COL_REGULAR) StagesIP<N, G, true, 1, typename PL::R>::run(buf, tw, t);
   }
   for (int e = threadIdx.x; e < CT * N; e += blockDim.x) {
     const int cc = e % CT, yy = e / CT;
@@ -389,56 +457,104 @@ bool grid_supported(int n) {
   }
 }
 
-template <int N>
-static hipError_t row_launch(const PassArgs& a, int mode, hipStream_t s) {
-  constexpr int RPI = RowCfg<N>::RPI;
-  const long total = (long)a.n_probes * a.fb * a.ny;
-  const unsigned blocks = (unsigned)((total + RPI - 1) / RPI);
-  dim3 grid(blocks), block(RowCfg<N>::THREADS);
-  if (mode == ROW_FIRST) hipLaunchKernelGGL((k_row<N, ROW_FIRST>), grid, block, 0, s, a);
-  else if (mode == ROW_REGULAR) hipLaunchKernelGGL((k_row<N, ROW_REGULAR>), grid, block, 0, s, a);
-  else hipLaunchKernelGGL((k_row<N, ROW_INVERSE_ONLY>), grid, block, 0, s, a);
+template <int N, int VAR>
+static hipError_t row_launch(PassTable& t, hipStream_t s) {
+  constexpr int RPI = RowCfg<N, VAR>::RPI;
+  int blocks = 0;
+  for (int i = 0; i < t.n; ++i) {
+    const PassArgs& a = t.l[i].a;
+    const long total = (long)a.n_probes * a.fb * a.ny;
+    t.l[i].block_start = blocks;
+    blocks += (int)((total + RPI - 1) / RPI);
+  }
+  hipLaunchKernelGGL((k_row<N, VAR>), dim3(blocks), dim3(RowCfg<N, VAR>::THREADS), 0, s, t);
   return hipGetLastError();
 }
 
-template <int N>
-static hipError_t col_launch(const PassArgs& a, int mode, hipStream_t s) {
-  constexpr int CT = ColCfg<N>::CT;
-  if (a.nx % CT != 0) return hipErrorInvalidValue;
-  const long blocks = (long)a.n_probes * a.fb * (a.nx / CT);
-  dim3 grid((unsigned)blocks), block(ColCfg<N>::THREADS);
-  if (mode == COL_REGULAR) hipLaunchKernelGGL((k_col<N, COL_REGULAR>), grid, block, 0, s, a);
-  else if (mode == COL_LAST) hipLaunchKernelGGL((k_col<N, COL_LAST>), grid, block, 0, s, a);
-  else hipLaunchKernelGGL((k_col<N, COL_INVERSE_ONLY>), grid, block, 0, s, a);
+template <int N, int VAR>
+static hipError_t col_launch(PassTable& t, hipStream_t s) {
+  constexpr int CT = ColCfg<N, VAR>::CT;
+  int blocks = 0;
+  for (int i = 0; i < t.n; ++i) {
+    const PassArgs& a = t.l[i].a;
+    if (a.nx % CT != 0) return hipErrorInvalidValue;
+    t.l[i].block_start = blocks;
+    blocks += a.n_probes * a.fb * (a.nx / CT);
+  }
+  hipLaunchKernelGGL((k_col<N, VAR>), dim3(blocks), dim3(ColCfg<N, VAR>::THREADS), 0, s, t);
   return hipGetLastError();
+}
+
+static bool same_grid(const PassLane* lanes, int n) {
+  for (int i = 1; i < n; ++i)
+    if (lanes[i].a.nx != lanes[0].a.nx || lanes[i].a.ny != lanes[0].a.ny) return false;
+  return true;
+}
+
+hipError_t launch_row_lanes(const PassLane* lanes, int n, int variant, hipStream_t s) {
+  if (n < 1 || n > MAX_LANES || !same_grid(lanes, n)) return hipErrorInvalidValue;
+  PassTable t{};
+  t.n = n;
+  for (int i = 0; i < n; ++i) t.l[i] = lanes[i];
+  switch (lanes[0].a.nx) {
+#define CASE(NN) \
+  case NN: return variant ? row_launch<NN, 1>(t, s) : row_launch<NN, 0>(t, s);
+    TACAW_SIZES(CASE)
+#undef CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_col_lanes(const PassLane* lanes, int n, int variant, hipStream_t s) {
+  if (n < 1 || n > MAX_LANES || !same_grid(lanes, n)) return hipErrorInvalidValue;
+  PassTable t{};
+  t.n = n;
+  for (int i = 0; i < n; ++i) t.l[i] = lanes[i];
+  switch (lanes[0].a.ny) {
+#define CASE(NN) \
+  case NN: return variant ? col_launch<NN, 1>(t, s) : col_launch<NN, 0>(t, s);
+    TACAW_SIZES(CASE)
+#undef CASE
+    default:
+      return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_row_pass(const PassArgs& a, int mode, hipStream_t s) {
-  switch (a.nx) {
-#define CASE(NN) \
-  case NN: return row_launch<NN>(a, mode, s);
-    TACAW_SIZES(CASE)
-#undef CASE
-    default:
-      return hipErrorInvalidValue;
-  }
+  PassLane l{};
+  l.a = a;
+  l.mode = mode;
+  return launch_row_lanes(&l, 1, 1, s);
 }
 
 hipError_t launch_col_pass(const PassArgs& a, int mode, hipStream_t s) {
-  switch (a.ny) {
-#define CASE(NN) \
-  case NN: return col_launch<NN>(a, mode, s);
-    TACAW_SIZES(CASE)
-#undef CASE
-    default:
-      return hipErrorInvalidValue;
+  PassLane l{};
+  l.a = a;
+  l.mode = mode;
+  return launch_col_lanes(&l, 1, 1, s);
+}
+
+hipError_t launch_splat_lanes(const SplatLane* lanes, int n, hipStream_t s) {
+  if (n < 1 || n > MAX_LANES) return hipErrorInvalidValue;
+  SplatTable t{};
+  t.n = n;
+  int blocks = 0;
+  for (int i = 0; i < n; ++i) {
+    t.l[i] = lanes[i];
+    t.l[i].block_start = blocks;
+    const SplatArgs& a = lanes[i].a;
+    blocks += a.tiles_x * a.tiles_y * lanes[i].n_slices_launch * a.fb;
   }
+  hipLaunchKernelGGL(k_splat, dim3(blocks), dim3(256), 0, s, t);
+  return hipGetLastError();
 }
 
 hipError_t launch_splat(const SplatArgs& a, int n_slices_launch, hipStream_t s) {
-  dim3 grid(a.tiles_x * a.tiles_y, n_slices_launch, a.fb), block(256);
-  hipLaunchKernelGGL(k_splat, grid, block, 0, s, a);
-  return hipGetLastError();
+  SplatLane l{};
+  l.a = a;
+  l.n_slices_launch = n_slices_launch;
+  return launch_splat_lanes(&l, 1, s);
 }
 
 int time_stage_kt(int n_frames, int n_k) {

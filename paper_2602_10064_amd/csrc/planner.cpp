@@ -191,7 +191,7 @@ Footprint footprint_of(const tacaw_job_desc* d, int fb, size_t n_tile_atoms) {
   f.tiles = n_tile_atoms * sizeof(int32_t);
   f.probes = plane ? 0 : P * nk * sizeof(float2) + P * (2 * sizeof(int32_t) + 2 * sizeof(double));
   f.tables = (size_t)(2 * d->nx + 2 * d->ny + d->nx + d->ny + d->n_frames) * sizeof(float2) +
-             (size_t)d->n_species * N_GAUSS * 3 * sizeof(float) + 64;
+             (size_t)d->n_species * N_GAUSS * COEF_STRIDE * sizeof(float) + 64;
   return f;
 }
 
@@ -273,17 +273,21 @@ tacaw_status plan_job(const tacaw_job_desc* d, const int32_t* atom_species, cons
   hp.img_y = images(hp.rcy, hp.pny);
 
   // Per-species coefficients: amplitude C a pi / b (V A), exp2 factors per
-  // pixel^2 along x and y.
+  // pixel^2 along x and y, and each term's own truncation radius
+  // sqrt(b ln 1e8)/pi in pixels (narrow terms reach far less than rc).
   const double cpref = 2.0 * M_PI * kBohrA * kCoulombEVA;
-  hp.coef.resize((size_t)hp.S * N_GAUSS * 3);
+  hp.coef.resize((size_t)hp.S * N_GAUSS * COEF_STRIDE);
   for (int s = 0; s < hp.S; ++s)
     for (int i = 0; i < N_GAUSS; ++i) {
       const double a = d->gauss_a[s * N_GAUSS + i], b = d->gauss_b[s * N_GAUSS + i];
       const double c = M_PI * M_PI / b;
-      float* o = &hp.coef[((size_t)s * N_GAUSS + i) * 3];
+      const double rci = sqrt(b * log(1e8)) / M_PI;
+      float* o = &hp.coef[((size_t)s * N_GAUSS + i) * COEF_STRIDE];
       o[0] = (float)(cpref * a * M_PI / b);
       o[1] = (float)(c * hp.dx * hp.dx / M_LN2);
       o[2] = (float)(c * hp.dy * hp.dy / M_LN2);
+      o[3] = (float)(rci / hp.dx);
+      o[4] = (float)(rci / hp.dy);
     }
 
   // Candidate atoms per (slice, tile): every atom whose mean position, widened

@@ -6,6 +6,7 @@
 #include <atomic>
 #include <condition_variable>
 #include <deque>
+#include <functional>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -13,6 +14,9 @@
 
 #include "tacaw.h"
 #include "tacaw_internal.h"
+
+struct tacaw_ctx;
+struct tacaw_job;
 
 namespace tacaw {
 
@@ -61,6 +65,16 @@ struct TimingRecord {
 
 struct JobState;
 
+// Launch through the timing wrapper (HIP events around the launch when the
+// context's timing is on).
+tacaw_status timed_launch(tacaw_ctx* c, int cls, hipStream_t s, const std::function<hipError_t()>& launch);
+PassArgs pass_args(tacaw_job* j);
+int row_variant_for(tacaw_ctx* c, int n);
+int col_variant_for(tacaw_ctx* c, int n);
+tacaw_status materialize(tacaw_job* j, hipStream_t s);
+tacaw_status run_batch_range(tacaw_job* job, hipStream_t s, int f_begin, int f_end);
+tacaw_status run_time_stage(tacaw_job* job, hipStream_t s);
+
 struct tacaw_ctx_impl;
 
 }  // namespace tacaw
@@ -84,6 +98,12 @@ struct tacaw_ctx {
   bool stop = false;
   bool server_started = false;
   hipStream_t serve_stream = nullptr;
+  // batched executor and autotuner
+  hipStream_t batch_streams[4] = {nullptr, nullptr, nullptr, nullptr};
+  int row_variant[2048] = {0};   // by grid size: 0 untuned (use 1), else variant + 1
+  int col_variant[2048] = {0};
+  std::string tune_cache;        // JSON-lines file of tuned variants ("" -> none)
+  bool tune_loaded = false;
 };
 
 struct tacaw_job {
@@ -118,6 +138,10 @@ struct tacaw_job {
   bool materialized = false;
   hipStream_t last_stream = nullptr;
   bool has_result = false;
+  // HIP-graph replay of the whole launch sequence (TACAW_USE_GRAPH)
+  hipStream_t capture_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
   // serving state
   std::atomic<int> serve_state{0};   // 0 idle, 1 queued, 2 running, 3 done, 4 cancelled, 5 failed
   std::atomic<bool> cancel_req{false};

@@ -16,7 +16,8 @@ struct AtomPos {
 
 constexpr int N_GAUSS = 5;
 constexpr int SPLAT_TX = 64;   // splat tile: columns
-constexpr int SPLAT_TY = 16;   // splat tile: rows
+constexpr int SPLAT_TY = 32;   // splat tile: rows
+constexpr int COEF_STRIDE = 5; // per (species, term): amplitude, exp2 x, exp2 y, cutoff x, cutoff y
 constexpr int SPLAT_MC = 16;   // candidate atoms staged in LDS per round
 constexpr int COL_CT = 16;     // columns per column-pass workgroup (128-byte rows)
 
@@ -26,7 +27,8 @@ struct SplatArgs {
   const int32_t* species;      // [A] species index, sorted order
   const int32_t* tile_start;   // [n_slices * tiles + 1] CSR offsets
   const int32_t* tile_atoms;   // sorted-atom indices
-  const float* coef;           // [S][5][3]: amplitude (V A), exp2 factor x, exp2 factor y
+  const float* coef;           // [S][5][COEF_STRIDE]: amplitude (V A), exp2 factor per pixel^2
+                               // along x and y, truncation radius in pixels along x and y
   float* V;                    // [fb][gridDim.y][pny][pnx]: slices slice0 .. slice0+gridDim.y-1
   int n_atoms, f0, fb, n_slices, slice0, pnx, pny, tiles_x, tiles_y;
   float rcx, rcy;              // truncation radius in pixels along x and y
@@ -58,6 +60,26 @@ struct TimeArgs {
   float inv_f2;                // 1 / F^2
 };
 
+constexpr int MAX_LANES = 8;
+struct PassLane {
+  PassArgs a;
+  int mode;          // RowMode or ColMode
+  int block_start;   // set by the launcher
+};
+struct PassTable {
+  int n;
+  PassLane l[MAX_LANES];
+};
+struct SplatLane {
+  SplatArgs a;
+  int n_slices_launch;  // slices slice0 .. slice0 + n - 1 of frames f0 .. f0 + fb - 1
+  int block_start;      // set by the launcher
+};
+struct SplatTable {
+  int n;
+  SplatLane l[MAX_LANES];
+};
+
 enum RowMode { ROW_FIRST = 0, ROW_REGULAR = 1, ROW_INVERSE_ONLY = 2 };
 enum ColMode { COL_REGULAR = 0, COL_LAST = 1, COL_INVERSE_ONLY = 2 };
 
@@ -65,6 +87,9 @@ enum ColMode { COL_REGULAR = 0, COL_LAST = 1, COL_INVERSE_ONLY = 2 };
 bool grid_supported(int n);
 hipError_t launch_splat(const SplatArgs& a, int n_slices_launch, hipStream_t s);
 hipError_t launch_row_pass(const PassArgs& a, int mode, hipStream_t s);
+hipError_t launch_row_lanes(const PassLane* lanes, int n, int variant, hipStream_t s);
+hipError_t launch_col_lanes(const PassLane* lanes, int n, int variant, hipStream_t s);
+hipError_t launch_splat_lanes(const SplatLane* lanes, int n, hipStream_t s);
 hipError_t launch_col_pass(const PassArgs& a, int mode, hipStream_t s);
 hipError_t launch_time_stage(const TimeArgs& a, hipStream_t s);
 int time_stage_kt(int n_frames, int n_k);

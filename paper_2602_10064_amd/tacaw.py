@@ -21,6 +21,7 @@ STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "EBUSY", 5: 
 TWO_SIDED = 1
 KEEP_EXIT_WAVES = 2
 DEFER_ALLOC = 4
+USE_GRAPH = 8
 
 K_SPLAT, K_ROW, K_COL, K_TIME, K_OTHER, K_FUSED = range(6)
 KERNEL_CLASSES = {"splat": K_SPLAT, "row": K_ROW, "col": K_COL, "time": K_TIME, "other": K_OTHER,
@@ -61,6 +62,7 @@ EXPORTED = [
     "tacaw_submit", "tacaw_poll", "tacaw_wait", "tacaw_cancel", "tacaw_get_spectrum",
     "tacaw_get_exit_waves", "tacaw_axes", "tacaw_job_slices", "tacaw_job_destroy", "tacaw_last_error",
     "tacaw_timing_enable", "tacaw_timing_get", "tacaw_version", "tacaw_job_latency",
+    "tacaw_run_batch", "tacaw_autotune",
 ]
 
 
@@ -93,6 +95,8 @@ def lib() -> ctypes.CDLL:
         "tacaw_timing_enable": [vp, ctypes.c_int],
         "tacaw_timing_get": [vp, ctypes.c_int, P(dp), P(ctypes.c_int64)],
         "tacaw_job_latency": [vp, P(dp), P(dp)],
+        "tacaw_run_batch": [P(vp), ctypes.c_int, vp],
+        "tacaw_autotune": [vp, vp, P(ctypes.c_int), P(ctypes.c_int)],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -191,12 +195,14 @@ class TacawJob:
     """tacaw_job created from a workloads.Job (inputs copied by the library)."""
 
     def __init__(self, ctx: Context, job, keep_exit_waves: Optional[bool] = None,
-                 defer_alloc: bool = False):
+                 defer_alloc: bool = False, use_graph: bool = False):
         self.ctx = ctx
         self.job = job
         self._d = _DescHolder(job, keep_exit_waves)
         if defer_alloc:
             self._d.desc.flags |= DEFER_ALLOC
+        if use_graph:
+            self._d.desc.flags |= USE_GRAPH
         sp = np.ascontiguousarray(job.atom_species, dtype=np.int32)
         pos = np.ascontiguousarray(job.positions, dtype=np.float64)
         h = ctypes.c_void_p()
@@ -226,6 +232,13 @@ class TacawJob:
 
     def submit(self):
         _check(lib().tacaw_submit(self.ctx.handle, self.handle))
+
+    def autotune(self, stream=None) -> tuple:
+        """Pick the faster row/column tile variants for this grid size."""
+        r = ctypes.c_int()
+        c = ctypes.c_int()
+        _check(lib().tacaw_autotune(self.handle, _stream_handle(stream), ctypes.byref(r), ctypes.byref(c)))
+        return r.value, c.value
 
     def latency_ms(self) -> tuple:
         """(queued_ms, total_ms) of a job that finished in the serving loop."""
@@ -285,6 +298,12 @@ class TacawJob:
 
     def __exit__(self, *exc):
         self.destroy()
+
+
+def run_batch(jobs, stream=None):
+    """tacaw_run_batch over a list of TacawJob of one context."""
+    arr = (ctypes.c_void_p * len(jobs))(*[j.handle.value for j in jobs])
+    _check(lib().tacaw_run_batch(arr, len(jobs), _stream_handle(stream)))
 
 
 def footprint(job) -> int:

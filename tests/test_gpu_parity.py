@@ -155,3 +155,10 @@ def test_errors_do_not_poison_context(tacaw, ctx):
         assert e.value.status == 5          # not run yet
         j.run()
         assert np.isfinite(j.spectrum()).all()
+
+
+def test_c3_shape_reduced_probes_frames(tacaw, ctx, oracle):
+    # full c3 geometry (38400 atoms, 1000x866 potential grid, 256^2 windows,
+    # 20 slices, 30 mrad at 60 kV) with a 3x3 scan and 4 frames
+    job = w.c3_probe(n_frames=4, n_scan=3)
+    check_job(tacaw, ctx, oracle, job)
