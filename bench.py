@@ -61,8 +61,141 @@ def cpu_baseline(job, sample_frames: int):
                       f"spectrum of the sample), FP64 numpy, one frame per process, {dt:.1f} s"}
 
 
+def bench_c4(args):
+    """64 seeded uneven jobs: plain per-job launches vs the batched executor."""
+    import torch
+    from paper_2602_10064_amd import tacaw, workloads
+    ctx = tacaw.Context(0)
+    handles, steps_total = [], 0
+    t0 = time.perf_counter()
+    for j in range(args.jobs):
+        job = workloads.c4_job(j)
+        steps_total += job.slice_steps()
+        handles.append(tacaw.TacawJob(ctx, job, keep_exit_waves=False))
+        del job
+    print(f"[bench] {args.jobs} jobs generated and created in {time.perf_counter() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+    stream = torch.cuda.current_stream()
+    if args.autotune:
+        seen = set()
+        for h in handles:
+            if h.nx not in seen:
+                seen.add(h.nx)
+                print(f"[bench] autotune {h.nx}: {h.autotune(stream)}", file=sys.stderr, flush=True)
+    # warm-up: one batched pass (materialises every job)
+    tacaw.run_batch(handles, stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for h in handles:
+        h.run(stream=stream)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    print(f"[bench] plain per-job launches: {t_plain:.3f} s", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    tacaw.run_batch(handles, stream)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    print(f"[bench] batched: {t_batch:.3f} s", file=sys.stderr, flush=True)
+    for h in handles:
+        h.destroy()
+    ctx.close()
+    return {
+        "metric": "slice-steps/sec (grid-pts*slices*frames/s), batched uneven jobs",
+        "value": steps_total / t_batch, "unit": "slice-steps/s", "n_gpus": 1,
+        "plain_value": steps_total / t_plain, "speedup_vs_plain": t_plain / t_batch,
+        "ms_batched": t_batch * 1e3, "ms_plain": t_plain * 1e3, "higher_is_better": True,
+        "dtype": "fp32", "data": "synthetic",
+        "config": {"workload": f"{args.jobs} seeded uneven jobs (grids 128-512, 8-48 slices, "
+                               f"128-1024 frames, plane wave or probe)", "slice_steps": steps_total},
+    }
+
+
+def bench_c5(args):
+    """Serving loop: Poisson arrivals (4 req/s) of uneven jobs plus 10% 1024^2 x 2048-frame jobs."""
+    import threading
+    from paper_2602_10064_amd import tacaw, workloads
+    times, big = workloads.c5_arrivals(args.requests, rate_per_s=args.rate)
+    ctx = tacaw.Context(0)
+    n_reg = min(args.requests, 24)
+    t0 = time.perf_counter()
+    reg_pool = []
+    for i in range(n_reg):
+        job = workloads.c4_job(i, seed_base=5000)
+        reg_pool.append((tacaw.TacawJob(ctx, job, keep_exit_waves=False, defer_alloc=True), job.slice_steps()))
+        del job
+    big_pool = []
+    if big.any():
+        bj = workloads.c4_job(0, seed_base=5500, big=True)
+        for _ in range(2):
+            big_pool.append((tacaw.TacawJob(ctx, bj, keep_exit_waves=False, defer_alloc=True), bj.slice_steps()))
+        del bj
+    print(f"[bench] serving pools ready in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    lat, done_steps, finished_at = [], [0], []
+    lock = threading.Lock()
+    busy = {}
+
+    def waiter(h, steps):
+        h.wait()
+        q, tot = h.latency_ms()
+        with lock:
+            lat.append(tot)
+            done_steps[0] += steps
+            finished_at.append(time.perf_counter())
+            busy[id(h)] = False
+
+    threads = []
+    start = time.perf_counter()
+    ri = bi = 0
+    for k in range(args.requests):
+        now = time.perf_counter() - start
+        if times[k] > now:
+            time.sleep(times[k] - now)
+        pool = big_pool if big[k] and big_pool else reg_pool
+        idx = (bi if pool is big_pool else ri) % len(pool)
+        if pool is big_pool:
+            bi += 1
+        else:
+            ri += 1
+        h, steps = pool[idx]
+        while True:
+            with lock:
+                if not busy.get(id(h), False):
+                    busy[id(h)] = True
+                    break
+            time.sleep(0.001)
+        h.submit()
+        th = threading.Thread(target=waiter, args=(h, steps))
+        th.start()
+        threads.append(th)
+        if k % 20 == 0:
+            print(f"[bench] submitted {k + 1}/{args.requests}", file=sys.stderr, flush=True)
+    for th in threads:
+        th.join()
+    elapsed = max(finished_at) - start
+    lat = np.array(lat)
+    for h, _ in reg_pool + big_pool:
+        h.destroy()
+    ctx.close()
+    return {
+        "metric": "slice-steps/sec (grid-pts*slices*frames/s) + p50/p99 request latency",
+        "value": done_steps[0] / elapsed, "unit": "slice-steps/s", "n_gpus": 1,
+        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+        "requests": int(args.requests), "rate_per_s": args.rate, "elapsed_s": elapsed,
+        "big_requests": int(big.sum()), "higher_is_better": True, "dtype": "fp32", "data": "synthetic",
+        "config": {"workload": "Poisson arrivals of seeded uneven jobs (90%) and 1024^2 x 2048-frame "
+                               "jobs (10%), admission by device-memory footprint, continuous batching"},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="c2", choices=["c2", "c4", "c5"],
+                    help="c2: the 512^2 x 32 x 1024 plane-wave workload (default); c4: uneven-job "
+                         "batch; c5: serving")
+    ap.add_argument("--jobs", type=int, default=64)
+    ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--requests", type=int, default=120)
+    ap.add_argument("--rate", type=float, default=4.0)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
@@ -81,6 +214,12 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.workload == "c4":
+        print(json.dumps(bench_c4(args)), flush=True)
+        return
+    if args.workload == "c5":
+        print(json.dumps(bench_c5(args)), flush=True)
+        return
     t_gen = time.perf_counter()
     job = workloads.c2_plain(n_frames=args.frames)
     t_gen = time.perf_counter() - t_gen

@@ -164,11 +164,13 @@ tacaw_status tacaw_run(tacaw_job* job, void* hip_stream);
  * Every result equals the job's tacaw_run result bit for bit. */
 tacaw_status tacaw_run_batch(tacaw_job* const* jobs, int n_jobs, void* hip_stream);
 
-/* Autotuner: time the row-pass and column-pass tile variants (rows per
- * workgroup, columns per workgroup) on one frame batch of `job` and keep the
+/* Autotuner: time the row-pass variants (rows per workgroup, and for grids
+ * of 64 and 512 a register-resident radix-8 kernel) and the column-pass tile
+ * widths on one frame batch of `job` and keep the
  * faster of each for the job's grid size in the context (appended to the
  * JSON-lines file named by $TACAW_TUNE_CACHE, read back by later contexts).
- * Writes the chosen variants (0 or 1) when the pointers are not NULL.  Resets
+ * Writes the chosen variants (row 0-2, column 0-1) when the pointers are not
+ * NULL.  Resets
  * the context's timing totals. */
 tacaw_status tacaw_autotune(tacaw_job* job, void* hip_stream, int* row_variant, int* col_variant);
 

@@ -1,5 +1,6 @@
 // C ABI of libtacaw: contexts, jobs, the plain per-job run, results, timing.
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -96,13 +97,21 @@ void drain_records(tacaw_ctx* c) {
 
 namespace tacaw {
 
+// Tile variant of the row pass (0: base rows per block, 1: doubled, 2: the
+// register radix-8 kernel for 64 and 512) and of the column pass (0: half
+// width, 1: full width).  Tuned choices win; $TACAW_ROW_VARIANT and
+// $TACAW_COL_VARIANT override untuned defaults.
 int row_variant_for(tacaw_ctx* c, int n) {
   const int v = (n > 0 && n < 2048) ? c->row_variant[n] : 0;
-  return v ? v - 1 : 1;
+  if (v) return v - 1;
+  if (const char* e = getenv("TACAW_ROW_VARIANT")) return atoi(e);
+  return (n == 512 || n == 64) ? 2 : 1;
 }
 int col_variant_for(tacaw_ctx* c, int n) {
   const int v = (n > 0 && n < 2048) ? c->col_variant[n] : 0;
-  return v ? v - 1 : 1;
+  if (v) return v - 1;
+  if (const char* e = getenv("TACAW_COL_VARIANT")) return atoi(e);
+  return (n == 512 || n == 64) ? 2 : 0;
 }
 
 // Launch wrapper: brackets the launch with events on its stream when timing.
@@ -174,6 +183,8 @@ tacaw_status run_batch_range(tacaw_job* job, hipStream_t s, int f_begin, int f_e
     sa.coef = job->d_coef;
     sa.V = job->d_V;
     sa.n_atoms = hp.A;
+  sa.n_species = hp.S;
+    sa.n_species = hp.S;
     sa.f0 = f0;
     sa.fb = fb;
     sa.n_slices = hp.ns;
@@ -407,8 +418,8 @@ tacaw_status tacaw_job_footprint(const tacaw_job_desc* d, size_t* bytes) {
     set_error("bytes is NULL");
     return TACAW_EINVAL;
   }
-  // tile lists are not known before planning: bound them by 32 entries per atom
-  *bytes = footprint_of(d, choose_frame_batch(d), (size_t)d->n_atoms * 32 + 1).total();
+  // candidate lists are not known before planning: bound them by 5 terms x 16 tiles per atom
+  *bytes = footprint_of(d, choose_frame_batch(d), (size_t)d->n_atoms * 80 + 1).total();
   return TACAW_OK;
 }
 

@@ -52,6 +52,7 @@ SplatArgs splat_args(tacaw_job* j, int f0, int fb, int slice) {
   sa.coef = j->d_coef;
   sa.V = j->d_V;
   sa.n_atoms = hp.A;
+  sa.n_species = hp.S;
   sa.f0 = f0;
   sa.fb = fb;
   sa.n_slices = hp.ns;
@@ -151,7 +152,7 @@ void load_tune_cache(tacaw_ctx* c) {
     int nx = 0, ny = 0, r = 0, cc = 0;
     if (sscanf(line.c_str(), "{\"nx\": %d, \"ny\": %d, \"row_variant\": %d, \"col_variant\": %d}", &nx, &ny, &r,
                &cc) == 4 &&
-        nx > 0 && nx < 2048 && ny > 0 && ny < 2048 && (r == 0 || r == 1) && (cc == 0 || cc == 1)) {
+        nx > 0 && nx < 2048 && ny > 0 && ny < 2048 && r >= 0 && r <= 2 && (cc == 0 || cc == 1)) {
       c->row_variant[nx] = r + 1;
       c->col_variant[ny] = cc + 1;
     }
@@ -257,11 +258,12 @@ tacaw_status tacaw_autotune(tacaw_job* job, void* hip_stream, int* row_variant, 
   hipStream_t s = (hipStream_t)hip_stream;
   const HostPlan& hp = job->hp;
   const int fb = std::min(hp.fb, hp.F);
-  double best_row[2] = {0, 0}, best_col[2] = {0, 0};
+  const int n_row_var = (hp.nx == 512 || hp.nx == 64) ? 3 : 2;
+  double best_row[3] = {1e30, 1e30, 1e30}, best_col[3] = {1e30, 1e30, 1e30};
   const bool was_timing = c->timing;
-  for (int v = 0; v < 2; ++v) {
+  for (int v = 0; v < n_row_var; ++v) {
     c->row_variant[hp.nx] = v + 1;
-    c->col_variant[hp.ny] = v + 1;
+    c->col_variant[hp.ny] = std::min(v, 1) + 1;
     for (int rep = 0; rep < 2; ++rep) {   // first repetition warms up
       {
         std::lock_guard<std::mutex> lk(c->mu);
@@ -287,7 +289,9 @@ tacaw_status tacaw_autotune(tacaw_job* job, void* hip_stream, int* row_variant, 
     c->timing = was_timing;
   }
   if (st != TACAW_OK) return st;
-  const int rv = best_row[1] <= best_row[0] ? 1 : 0;
+  int rv = 0;
+  for (int v = 1; v < n_row_var; ++v)
+    if (best_row[v] < best_row[rv]) rv = v;
   const int cv = best_col[1] <= best_col[0] ? 1 : 0;
   c->row_variant[hp.nx] = rv + 1;
   c->col_variant[hp.ny] = cv + 1;

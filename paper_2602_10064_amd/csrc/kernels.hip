@@ -12,6 +12,8 @@
 //   setup        twiddles, propagator factors, probe aperture fill
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "fft_engine.h"
 #include "tacaw_internal.h"
 
@@ -90,6 +92,15 @@ __global__ void k_probe_fill(float2* out, const double* rloc, const int* count, 
   out[i] = v;
 }
 
+// exp(i phi) for the transmission function: the argument is reduced to
+// [-1/2, 1/2) revolutions exactly (subtracting an integer), then the hardware
+// sine and cosine (absolute error ~1.6e-7 there) are used.
+__device__ __forceinline__ float2 phase_factor(float phi) {
+  float rev = phi * 0.15915494309189535f;
+  rev -= rintf(rev);
+  return make_float2(__builtin_amdgcn_cosf(rev), __builtin_amdgcn_sinf(rev));
+}
+
 // ---------------------------------------------------------------------------
 // Lane tables: one launch advances up to MAX_LANES (job, frame batch) lanes of
 // the same grid size by one pass; each lane has its own slice and mode.  The
@@ -107,17 +118,22 @@ __device__ __forceinline__ int find_lane(const Table& t, int b) {
 // Projected potential
 // ---------------------------------------------------------------------------
 // sum over periodic images of exp2(-e2 d^2) for |d| <= rc, where d is the
-// pixel distance from grid node `node` to an atom at pixel ipos + fpos.
+// pixel distance from grid node `node` (0 <= node < n + tile) to an atom at
+// pixel ipos + fpos (0 <= ipos < n).  No integer division: node - ipos lies in
+// (-n, 2n).  exp2 of an argument below -26.6 (the 1e-8 cutoff) is never
+// evaluated, so the raw hardware exp2 is accurate here.
 __device__ __forceinline__ float profile(int node, int ipos, float fpos, int n, float e2, float rc,
                                          int img) {
-  int di = (node - ipos) % n;
+  int di = node - ipos;
+  if (di >= n) di -= n;
   if (di < 0) di += n;
   if (di >= n - n / 2) di -= n;  // di in [-(n/2), n - n/2)
   const float d0 = (float)di - fpos;
+  if (img == 0) return fabsf(d0) <= rc ? __builtin_amdgcn_exp2f(-e2 * d0 * d0) : 0.f;
   float g = 0.f;
   for (int k = -img; k <= img; ++k) {
     const float d = d0 + (float)(k * n);
-    if (fabsf(d) <= rc) g += exp2f(-e2 * d * d);
+    if (fabsf(d) <= rc) g += __builtin_amdgcn_exp2f(-e2 * d * d);
   }
   return g;
 }
@@ -137,95 +153,159 @@ __device__ __forceinline__ float interval_distance(float u, int lo, int hi, int 
 // and every thread accumulates a 2 x 4 block of pixels.  Terms whose own
 // cutoff box misses the tile are skipped by a per-atom bit mask.  The
 // summation order is fixed, so the result is deterministic.
+// Per active (atom, term) pair of a tile: what the profile fill needs.
+struct PairData {
+  int ix, iy;     // atom pixel (for the general periodic-image path)
+  int ox, oy;     // minimal-image pixel offset of the tile's first node from the atom
+  float fx, fy;
+  float e2x, e2y, rcx, rcy, amp;
+};
+
+// Profile value at tile node `j` for a pair whose tile-origin offset is `o`:
+// d = (o + j) - f pixels.  Valid when no second periodic image can reach the
+// tile (then the minimal image of the origin stays minimal across the tile
+// for every node within the cutoff).
+__device__ __forceinline__ float profile_tile(int o, int j, float f, float e2, float rc) {
+  const float d = (float)(o + j) - f;
+  return fabsf(d) <= rc ? __builtin_amdgcn_exp2f(-e2 * d * d) : 0.f;
+}
+
+// One workgroup (4 wavefronts) computes a 32 x 32 tile of V for one (frame,
+// slice).  V_tile = Gy^T Gx, a sum over the tile's active (atom, term) pairs
+// of outer(row profile, column profile): the 2D Gaussian of a term and its
+// periodic images factor into x and y parts.  The profiles of up to 80 pairs
+// are built in LDS (a pair is active when its own cutoff box meets the
+// tile), then each wavefront accumulates one 16 x 16 quarter of the tile with
+// v_mfma_f32_16x16x4f32 (FP32 products and sums), four pairs per instruction.
+// The pair order and the instruction sequence are fixed, so the result is
+// deterministic.
 __global__ void __launch_bounds__(256) k_splat(SplatTable tab) {
-  __shared__ float gx[SPLAT_MC][N_GAUSS][SPLAT_TX];
-  __shared__ float gy[SPLAT_MC][N_GAUSS][SPLAT_TY];
-  __shared__ AtomPos sp_pos[SPLAT_MC];
-  __shared__ int sp_spc[SPLAT_MC];
-  __shared__ int sp_mask[SPLAT_MC];
+  constexpr int MP = SPLAT_MC;   // pairs staged per round (multiple of 4)
+  constexpr int FPB = SPLAT_FPB; // frames per block
+  static_assert(SPLAT_TX == 32 && SPLAT_TY == 32, "MFMA tiling assumes 32 x 32 tiles");
+  static_assert(MP % 4 == 0 && MP <= 256, "pair rounds");
+  __shared__ float gx[MP][SPLAT_TX];
+  __shared__ float gy[MP][SPLAT_TY];
+  __shared__ PairData pd[MP];
+  __shared__ AtomPos fpos[FPB][MP];
+  __shared__ int pcoef[MP];  // offset of the pair's coefficients
+  __shared__ float coef_s[SPLAT_MAX_SPECIES * N_GAUSS * COEF_STRIDE];
 
   const int L = find_lane(tab, blockIdx.x);
   const SplatArgs& a = tab.l[L].a;
   const int nsl = tab.l[L].n_slices_launch;
+  const int n_coef = a.n_species * N_GAUSS * COEF_STRIDE;
+  const bool coef_in_lds = a.n_species <= SPLAT_MAX_SPECIES;
+  if (coef_in_lds)
+    for (int i = threadIdx.x; i < n_coef; i += blockDim.x) coef_s[i] = a.coef[i];
+  const float* coef = coef_in_lds ? coef_s : a.coef;
   const int lb = blockIdx.x - tab.l[L].block_start;
   const int tid = threadIdx.x;
   const int n_tiles = a.tiles_x * a.tiles_y;
   const int tile = lb % n_tiles;
   const int sl = (lb / n_tiles) % nsl;
-  const int fl = lb / (n_tiles * nsl);
+  const int fg = lb / (n_tiles * nsl);
+  const int fl0 = fg * FPB;
+  const int nf = min(FPB, a.fb - fl0);
   const int s = a.slice0 + sl;
-  const int f = a.f0 + fl;
   const int tx0 = (tile % a.tiles_x) * SPLAT_TX;
   const int ty0 = (tile / a.tiles_x) * SPLAT_TY;
   const int cs = a.tile_start[s * n_tiles + tile];
   const int ce = a.tile_start[s * n_tiles + tile + 1];
+  const bool simple_x = a.img_x == 0 && 2 * (a.rcx + SPLAT_TX + 2) < a.pnx;
+  const bool simple_y = a.img_y == 0 && 2 * (a.rcy + SPLAT_TY + 2) < a.pny;
 
-  const int ry = (tid / (SPLAT_TX / 4)) * 2;  // 0, 2, .., 30
-  const int cx = (tid % (SPLAT_TX / 4)) * 4;  // 0, 4, .., 60
-  float acc0[4] = {0.f, 0.f, 0.f, 0.f};
-  float acc1[4] = {0.f, 0.f, 0.f, 0.f};
-
-  for (int c0 = cs; c0 < ce; c0 += SPLAT_MC) {
-    const int mc = min(SPLAT_MC, ce - c0);
-    __syncthreads();
-    if (tid < mc) {
-      const int atom = a.tile_atoms[c0 + tid];
-      const AtomPos p = a.pos[(size_t)f * a.n_atoms + atom];
-      const int spc = a.species[atom];
-      sp_pos[tid] = p;
-      sp_spc[tid] = spc;
-      const float dxs = interval_distance((float)p.ix + p.fx, tx0, tx0 + SPLAT_TX - 1, a.pnx);
-      const float dys = interval_distance((float)p.iy + p.fy, ty0, ty0 + SPLAT_TY - 1, a.pny);
-      int mask = 0;
-      for (int i = 0; i < N_GAUSS; ++i) {
-        const float* c = a.coef + (spc * N_GAUSS + i) * COEF_STRIDE;
-        if (dxs <= c[3] && dys <= c[4]) mask |= 1 << i;
-      }
-      sp_mask[tid] = mask;
-    }
-    __syncthreads();
-    for (int e = tid; e < mc * N_GAUSS * SPLAT_TX; e += 256) {
-      const int m = e / (N_GAUSS * SPLAT_TX);
-      const int i = (e / SPLAT_TX) % N_GAUSS;
-      const int x = e % SPLAT_TX;
-      const float* c = a.coef + (sp_spc[m] * N_GAUSS + i) * COEF_STRIDE;
-      gx[m][i][x] = profile(tx0 + x, sp_pos[m].ix, sp_pos[m].fx, a.pnx, c[1], c[3], a.img_x);
-    }
-    for (int e = tid; e < mc * N_GAUSS * SPLAT_TY; e += 256) {
-      const int m = e / (N_GAUSS * SPLAT_TY);
-      const int i = (e / SPLAT_TY) % N_GAUSS;
-      const int y = e % SPLAT_TY;
-      const float* c = a.coef + (sp_spc[m] * N_GAUSS + i) * COEF_STRIDE;
-      gy[m][i][y] = c[0] * profile(ty0 + y, sp_pos[m].iy, sp_pos[m].fy, a.pny, c[2], c[4], a.img_y);
-    }
-    __syncthreads();
-    for (int m = 0; m < mc; ++m) {
-      const int mask = sp_mask[m];
+  const int wave = tid / 64, lane = tid % 64;
+  const int row0 = 16 * (wave & 1), col0 = 16 * (wave >> 1);
+  typedef float v4f __attribute__((ext_vector_type(4)));
+  v4f acc[FPB];
 #pragma unroll
-      for (int i = 0; i < N_GAUSS; ++i) {
-        if (!(mask & (1 << i))) continue;
-        const float2 g = *reinterpret_cast<const float2*>(&gy[m][i][ry]);
-        const float4 h = *reinterpret_cast<const float4*>(&gx[m][i][cx]);
-        acc0[0] += g.x * h.x;
-        acc0[1] += g.x * h.y;
-        acc0[2] += g.x * h.z;
-        acc0[3] += g.x * h.w;
-        acc1[0] += g.y * h.x;
-        acc1[1] += g.y * h.y;
-        acc1[2] += g.y * h.z;
-        acc1[3] += g.y * h.w;
+  for (int k = 0; k < FPB; ++k) acc[k] = v4f{0.f, 0.f, 0.f, 0.f};
+
+  for (int c0 = cs; c0 < ce; c0 += MP) {
+    const int mp = min(MP, ce - c0);
+    const int mp4 = (mp + 3) & ~3;  // zero-padded to whole MFMA steps
+    __syncthreads();
+    // positions of every (frame, pair) of this round in one go
+    for (int e = tid; e < mp * FPB; e += 256) {
+      const int m = e % mp, k = e / mp;
+      const int entry = a.tile_atoms[c0 + m];
+      const int atom = entry >> 3;
+      if (k < nf) fpos[k][m] = a.pos[(size_t)(a.f0 + fl0 + k) * a.n_atoms + atom];
+      if (k == 0) pcoef[m] = (a.species[atom] * N_GAUSS + (entry & 7)) * COEF_STRIDE;
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int k = 0; k < nf; ++k) {
+      if (tid < mp) {
+        const AtomPos p = fpos[k][tid];
+        const float* c = coef + pcoef[tid];
+        PairData q;
+        q.ix = p.ix;
+        q.iy = p.iy;
+        q.ox = tx0 - p.ix;
+        if (q.ox >= a.pnx - a.pnx / 2) q.ox -= a.pnx;
+        if (q.ox < -(a.pnx / 2)) q.ox += a.pnx;
+        q.oy = ty0 - p.iy;
+        if (q.oy >= a.pny - a.pny / 2) q.oy -= a.pny;
+        if (q.oy < -(a.pny / 2)) q.oy += a.pny;
+        q.fx = p.fx;
+        q.fy = p.fy;
+        q.amp = c[0];
+        q.e2x = c[1];
+        q.e2y = c[2];
+        q.rcx = c[3];
+        q.rcy = c[4];
+        pd[tid] = q;
       }
+      __syncthreads();
+      for (int e = tid; e < mp4 * SPLAT_TX; e += 256) {
+        const int kk = e / SPLAT_TX, x = e % SPLAT_TX;
+        float v = 0.f;
+        if (kk < mp) {
+          const PairData& q = pd[kk];
+          v = simple_x ? profile_tile(q.ox, x, q.fx, q.e2x, q.rcx)
+                       : profile(tx0 + x, q.ix, q.fx, a.pnx, q.e2x, q.rcx, a.img_x);
+        }
+        gx[kk][x] = v;
+      }
+      for (int e = tid; e < mp4 * SPLAT_TY; e += 256) {
+        const int kk = e / SPLAT_TY, y = e % SPLAT_TY;
+        float v = 0.f;
+        if (kk < mp) {
+          const PairData& q = pd[kk];
+          v = q.amp * (simple_y ? profile_tile(q.oy, y, q.fy, q.e2y, q.rcy)
+                                : profile(ty0 + y, q.iy, q.fy, a.pny, q.e2y, q.rcy, a.img_y));
+        }
+        gy[kk][y] = v;
+      }
+      __syncthreads();
+      // D[r][c] += sum_k gy[k][row0 + r] * gx[k][col0 + c]; A is 16 x 4 (lane:
+      // row lane % 16, k lane / 16), B is 4 x 16 (k lane / 16, column lane % 16)
+      v4f d = acc[0];
+#pragma unroll
+      for (int q = 1; q < FPB; ++q)
+        if (q == k) d = acc[q];
+      for (int k0 = 0; k0 < mp4; k0 += 4) {
+        const int kk = k0 + lane / 16;
+        d = __builtin_amdgcn_mfma_f32_16x16x4f32(gy[kk][row0 + lane % 16], gx[kk][col0 + lane % 16], d, 0, 0, 0);
+      }
+#pragma unroll
+      for (int q = 0; q < FPB; ++q)
+        if (q == k) acc[q] = d;
+      __syncthreads();  // pd, gx and gy are rewritten for the next frame
     }
   }
+  // D layout: lane holds rows 4 (lane / 16) + j, j < 4, of column lane % 16
+  const int x = tx0 + col0 + lane % 16;
 #pragma unroll
-  for (int r = 0; r < 2; ++r) {
-    const int y = ty0 + ry + r;
-    if (y < a.pny) {
-      float* out = a.V + (((size_t)fl * nsl + sl) * a.pny + y) * a.pnx;
-      const float* acc = r == 0 ? acc0 : acc1;
+  for (int k = 0; k < FPB; ++k) {
+    if (k >= nf) break;
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
-        if (tx0 + cx + j < a.pnx) out[tx0 + cx + j] = acc[j];
+    for (int j = 0; j < 4; ++j) {
+      const int y = ty0 + row0 + 4 * (lane / 16) + j;
+      if (y < a.pny && x < a.pnx)
+        a.V[(((size_t)(fl0 + k) * nsl + sl) * a.pny + y) * a.pnx + x] = acc[k][j];
     }
   }
 }
@@ -307,15 +387,172 @@ __global__ void __launch_bounds__((RowCfg<N, VAR>::THREADS)) k_row(PassTable tab
     for (int x = t; x < N; x += G) {
       int xx = ox + x;
       if (xx >= a.pnx) xx -= a.pnx;
-      float sn, cs;
-      sincosf(a.sigma * vrow[xx], &sn, &cs);
-      buf[x] = cmul(buf[x], make_float2(cs, sn));
+      buf[x] = cmul(buf[x], phase_factor(a.sigma * vrow[xx]));
     }
   }
   __syncthreads();
   StagesIP<N, G, false, 1, typename PL::R>::run(buf, tw, t);
   if (active)
     for (int x = t; x < N; x += G) row[x] = buf[x];
+}
+
+// ---------------------------------------------------------------------------
+// Row pass, uniform radix 8 (N = 8^S): one row per G = N/8 lanes inside one
+// wavefront; lane t keeps the row values at x = t + G r (r < 8) in registers,
+// which is both the first Stockham stage's input layout and the last stage's
+// output layout, so global loads and stores are coalesced and only S-1 LDS
+// exchanges per FFT remain, synchronised within the wavefront only.  Each
+// wavefront walks over rows with a grid stride; stage twiddles stay in
+// registers for all its rows.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int N>
+struct R8 {
+  static constexpr int S = N == 8 ? 1 : N == 64 ? 2 : N == 512 ? 3 : N == 4096 ? 4 : 0;
+  static constexpr int G = N / 8;            // lanes per row
+  static constexpr int RPW = 64 / G;         // rows per wavefront
+  static_assert(S > 0 && G <= 64, "uniform radix-8 row pass");
+};
+
+// One FFT on registers: x[r] at positions t + G r in and out.  lds: this
+// row's N-value scratch.  tw[j][r-1]: stage-j twiddles for this lane.
+template <int N, bool INV>
+__device__ __forceinline__ void fft_r8(float2 (&x)[8], float2* lds, const float2 (&tw)[R8<N>::S][7], int t) {
+  constexpr int S = R8<N>::S;
+  constexpr int G = R8<N>::G;
+  int P = 1;
+#pragma unroll
+  for (int j = 0; j < S; ++j) {
+    if (j > 0) {
+#pragma unroll
+      for (int r = 1; r < 8; ++r) x[r] = INV ? cmulc(x[r], tw[j][r - 1]) : cmul(x[r], tw[j][r - 1]);
+    }
+    dft8<INV>(x);
+    if (j < S - 1) {
+      const int k = t % P;
+      const int base = (t - k) * 8 + k;
+      wave_lds_sync();  // earlier reads of lds by this wavefront are done
+#pragma unroll
+      for (int r = 0; r < 8; ++r) lds[base + r * P] = x[r];
+      wave_lds_sync();
+#pragma unroll
+      for (int r = 0; r < 8; ++r) x[r] = lds[t + r * G];
+    }
+    P *= 8;
+  }
+}
+
+template <int N>
+__global__ void __launch_bounds__(256) k_row_r8(PassTable tab, int blocks_per_lane) {
+  constexpr int G = R8<N>::G;
+  constexpr int RPW = R8<N>::RPW;
+  constexpr int S = R8<N>::S;
+  __shared__ float2 scratch[4][RPW][N];
+
+  const int L = blockIdx.x / blocks_per_lane;
+  const PassArgs& a = tab.l[L].a;
+  const int mode = tab.l[L].mode;
+  const int lb = blockIdx.x % blocks_per_lane;
+  const int wave = threadIdx.x / 64;
+  const int lane = threadIdx.x % 64;
+  const int sub = lane / G;   // row within the wavefront
+  const int t = lane % G;
+  float2* lds = scratch[wave][sub];
+
+  // stage twiddles W_{8P}^{r (t mod P)} = tw[r (t mod P) N / (8P)]
+  float2 tw[S][7];
+  {
+    int P = 1;
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+      const int k = t % P;
+      const int step = N / (8 * P);
+#pragma unroll
+      for (int r = 1; r < 8; ++r) tw[j][r - 1] = a.tw_x[(r * k * step) % N];
+      P *= 8;
+    }
+  }
+  const long total = (long)a.n_probes * a.fb * a.ny;
+  const long stride = (long)blocks_per_lane * 4 * RPW;
+  const bool transmit = mode != ROW_INVERSE_ONLY;
+
+  // global reads of one row: the wave values and the potential row values
+  auto fetch = [&](long rid, float2 (&xv)[8], float (&vv)[8]) {
+    if (rid >= total) return;
+    const long w = rid / a.ny;
+    const int y = (int)(rid % a.ny);
+    const int p = (int)(w / a.fb);
+    const int fl = (int)(w % a.fb);
+    if (mode == ROW_FIRST) {
+      if (a.plane) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) xv[r] = make_float2(a.plane_amp, 0.f);
+      } else {
+        const float2* src = a.probe0 + ((size_t)p * a.ny + y) * (size_t)N;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) xv[r] = src[t + r * G];
+      }
+    } else {
+      const float2* row = a.exit + (((size_t)p * a.n_frames + a.f0 + fl) * a.ny + y) * (size_t)N;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) xv[r] = row[t + r * G];
+    }
+    if (transmit) {
+      const int ox = a.plane ? 0 : a.origin[2 * p];
+      const int oy = a.plane ? 0 : a.origin[2 * p + 1];
+      int yy = oy + y;
+      if (yy >= a.pny) yy -= a.pny;
+      const float* vrow =
+          a.V + (((size_t)fl * a.v_slices + (a.slice - a.v_slice0)) * a.pny + yy) * (size_t)a.pnx;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        int xx = ox + t + r * G;
+        if (xx >= a.pnx) xx -= a.pnx;
+        vv[r] = vrow[xx];
+      }
+    }
+  };
+
+  float2 xn[8];
+  float vn[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    xn[r] = make_float2(0.f, 0.f);
+    vn[r] = 0.f;
+  }
+  long rid0 = ((long)lb * 4 + wave) * RPW;
+  fetch(rid0 + sub, xn, vn);
+  for (; rid0 < total; rid0 += stride) {
+    const long rid = rid0 + sub;
+    float2 x[8];
+    float v[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      x[r] = xn[r];
+      v[r] = vn[r];
+    }
+    fetch(rid0 + stride + sub, xn, vn);  // next row's reads overlap this row's arithmetic
+    if (mode != ROW_FIRST) fft_r8<N, true>(x, lds, tw, t);
+    if (transmit) {
+#pragma unroll
+      for (int r = 0; r < 8; ++r) x[r] = cmul(x[r], phase_factor(a.sigma * v[r]));
+      fft_r8<N, false>(x, lds, tw, t);
+    }
+    if (rid < total) {
+      const long w = rid / a.ny;
+      const int y = (int)(rid % a.ny);
+      const int p = (int)(w / a.fb);
+      const int fl = (int)(w % a.fb);
+      float2* row = a.exit + (((size_t)p * a.n_frames + a.f0 + fl) * a.ny + y) * (size_t)N;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) row[t + r * G] = x[r];
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -373,6 +610,129 @@ __global__ void __launch_bounds__((ColCfg<N, VAR>::THREADS)) k_col(PassTable tab
   for (int e = threadIdx.x; e < CT * N; e += blockDim.x) {
     const int cc = e % CT, yy = e / CT;
     wave[(size_t)yy * a.nx + x0 + cc] = cols[cc * LD + yy];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Column pass, uniform radix 8 (N = 64 or 512).  A block owns CT adjacent
+// columns of one wave: it loads them coalesced into LDS (column stride
+// N + 2 keeps the transposing writes and the column reads conflict-free),
+// then each column is transformed by G = N/8 lanes of one wavefront on
+// registers (FFT_y, * P, iFFT_y) with wavefront-local LDS exchanges, written
+// back to its LDS column and stored coalesced.  Blocks walk over tiles with a
+// grid stride (XCD-contiguous order), keeping their stage twiddles in
+// registers.
+// ---------------------------------------------------------------------------
+template <int N>
+struct C8 {
+  static constexpr int G = N / 8;               // lanes per column
+  static constexpr int CPW = 64 / G;            // columns per wavefront
+  static constexpr int WAVES = N == 512 ? 8 : 4;
+  static constexpr int CT = WAVES * CPW;        // columns per block
+  static constexpr int LD = N + 2;
+  static constexpr int THREADS = WAVES * 64;
+};
+
+template <int N>
+__global__ void __launch_bounds__((C8<N>::THREADS)) k_col_r8(PassTable tab, int total_tiles) {
+  constexpr int G = C8<N>::G;
+  constexpr int CPW = C8<N>::CPW;
+  constexpr int CT = C8<N>::CT;
+  constexpr int LD = C8<N>::LD;
+  constexpr int S = R8<N>::S;
+  constexpr int THREADS = C8<N>::THREADS;
+  constexpr int PER = CT * N / THREADS;  // tile values each thread moves
+  __shared__ float2 cols[CT * LD];
+  const int wave = threadIdx.x / 64;
+  const int lane = threadIdx.x % 64;
+  const int cl = wave * CPW + lane / G;  // this lane's column in the tile
+  const int t = lane % G;
+  float2* lds = cols + cl * LD;
+
+  // stage twiddles of the y transform (every lane of the table has this ny)
+  float2 tw[S][7];
+  {
+    const float2* twy = tab.l[0].a.tw_y;
+    int P = 1;
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+      const int k = t % P;
+      const int step = N / (8 * P);
+#pragma unroll
+      for (int r = 1; r < 8; ++r) tw[j][r - 1] = twy[(r * k * step) % N];
+      P *= 8;
+    }
+  }
+  // tile geometry of a logical tile index
+  auto locate = [&](int it, int& L, int& x0, float2*& wp) {
+    const int tile_g = xcd_remap(it, total_tiles);
+    L = find_lane(tab, tile_g);
+    const PassArgs& a = tab.l[L].a;
+    const int tile = tile_g - tab.l[L].block_start;
+    const int tiles_per_wave = a.nx / CT;
+    const int w = tile / tiles_per_wave;
+    x0 = (tile % tiles_per_wave) * CT;
+    const int p = w / a.fb;
+    const int fl = w % a.fb;
+    wp = a.exit + ((size_t)p * a.n_frames + a.f0 + fl) * (size_t)N * a.nx;
+  };
+  float2 pre[PER];
+  int L = 0, x0 = 0;
+  float2* wp = nullptr;
+  int it = blockIdx.x;
+  if (it < total_tiles) {
+    locate(it, L, x0, wp);
+    const int nx = tab.l[L].a.nx;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = threadIdx.x + q * THREADS;
+      pre[q] = wp[(size_t)(e / CT) * nx + x0 + e % CT];
+    }
+  }
+  for (; it < total_tiles; it += gridDim.x) {
+    const PassArgs& a = tab.l[L].a;
+    const int mode = tab.l[L].mode;
+    const int cur_x0 = x0;
+    float2* cur_wp = wp;
+    __syncthreads();  // the previous tile's stores from LDS are done
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = threadIdx.x + q * THREADS;
+      cols[(e % CT) * LD + e / CT] = pre[q];
+    }
+    // issue the next tile's loads; they complete during this tile's arithmetic
+    const int nit = it + gridDim.x;
+    if (nit < total_tiles) {
+      locate(nit, L, x0, wp);
+      const int nx = tab.l[L].a.nx;
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int e = threadIdx.x + q * THREADS;
+        pre[q] = wp[(size_t)(e / CT) * nx + x0 + e % CT];
+      }
+    }
+    __syncthreads();
+    float2 x[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) x[r] = lds[t + r * G];
+    if (mode == COL_INVERSE_ONLY) {
+      fft_r8<N, true>(x, lds, tw, t);
+    } else {
+      fft_r8<N, false>(x, lds, tw, t);
+      const float2 pxv = a.px[cur_x0 + cl];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) x[r] = cmul(x[r], cmul(pxv, a.py[t + r * G]));
+      if (mode == COL_REGULAR) fft_r8<N, true>(x, lds, tw, t);
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int r = 0; r < 8; ++r) lds[t + r * G] = x[r];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = threadIdx.x + q * THREADS;
+      cur_wp[(size_t)(e / CT) * a.nx + cur_x0 + e % CT] = cols[(e % CT) * LD + e / CT];
+    }
   }
 }
 
@@ -491,11 +851,31 @@ static bool same_grid(const PassLane* lanes, int n) {
   return true;
 }
 
+template <int N>
+static hipError_t row_r8_launch(PassTable& t, hipStream_t s) {
+  // blocks per lane: enough waves for the lane's rows, at most 2048 blocks in all
+  long most = 0;
+  for (int i = 0; i < t.n; ++i) {
+    const PassArgs& a = t.l[i].a;
+    most = std::max(most, (long)a.n_probes * a.fb * a.ny);
+  }
+  constexpr int rows_per_block = 4 * R8<N>::RPW;
+  long bpl = (most + rows_per_block - 1) / rows_per_block;
+  bpl = std::min<long>(bpl, std::max<long>(1, 2048 / t.n));
+  hipLaunchKernelGGL((k_row_r8<N>), dim3((unsigned)(bpl * t.n)), dim3(256), 0, s, t, (int)bpl);
+  return hipGetLastError();
+}
+
 hipError_t launch_row_lanes(const PassLane* lanes, int n, int variant, hipStream_t s) {
   if (n < 1 || n > MAX_LANES || !same_grid(lanes, n)) return hipErrorInvalidValue;
   PassTable t{};
   t.n = n;
   for (int i = 0; i < n; ++i) t.l[i] = lanes[i];
+  if (variant == 2) {
+    if (lanes[0].a.nx == 512) return row_r8_launch<512>(t, s);
+    if (lanes[0].a.nx == 64) return row_r8_launch<64>(t, s);
+    variant = 1;
+  }
   switch (lanes[0].a.nx) {
 #define CASE(NN) \
   case NN: return variant ? row_launch<NN, 1>(t, s) : row_launch<NN, 0>(t, s);
@@ -506,11 +886,31 @@ hipError_t launch_row_lanes(const PassLane* lanes, int n, int variant, hipStream
   }
 }
 
+template <int N>
+static hipError_t col_r8_launch(PassTable& t, hipStream_t s) {
+  constexpr int CT = C8<N>::CT;
+  int tiles = 0;
+  for (int i = 0; i < t.n; ++i) {
+    const PassArgs& a = t.l[i].a;
+    if (a.nx % CT != 0) return hipErrorInvalidValue;
+    t.l[i].block_start = tiles;
+    tiles += a.n_probes * a.fb * (a.nx / CT);
+  }
+  const int grid = std::min(tiles, 2048);
+  hipLaunchKernelGGL((k_col_r8<N>), dim3(grid), dim3(C8<N>::THREADS), 0, s, t, tiles);
+  return hipGetLastError();
+}
+
 hipError_t launch_col_lanes(const PassLane* lanes, int n, int variant, hipStream_t s) {
   if (n < 1 || n > MAX_LANES || !same_grid(lanes, n)) return hipErrorInvalidValue;
   PassTable t{};
   t.n = n;
   for (int i = 0; i < n; ++i) t.l[i] = lanes[i];
+  if (variant == 2) {
+    if (lanes[0].a.ny == 512 && lanes[0].a.nx % C8<512>::CT == 0) return col_r8_launch<512>(t, s);
+    if (lanes[0].a.ny == 64 && lanes[0].a.nx % C8<64>::CT == 0) return col_r8_launch<64>(t, s);
+    variant = 0;
+  }
   switch (lanes[0].a.ny) {
 #define CASE(NN) \
   case NN: return variant ? col_launch<NN, 1>(t, s) : col_launch<NN, 0>(t, s);
@@ -544,7 +944,7 @@ hipError_t launch_splat_lanes(const SplatLane* lanes, int n, hipStream_t s) {
     t.l[i] = lanes[i];
     t.l[i].block_start = blocks;
     const SplatArgs& a = lanes[i].a;
-    blocks += a.tiles_x * a.tiles_y * lanes[i].n_slices_launch * a.fb;
+    blocks += a.tiles_x * a.tiles_y * lanes[i].n_slices_launch * ((a.fb + SPLAT_FPB - 1) / SPLAT_FPB);
   }
   hipLaunchKernelGGL(k_splat, dim3(blocks), dim3(256), 0, s, t);
   return hipGetLastError();

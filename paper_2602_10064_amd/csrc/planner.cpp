@@ -139,6 +139,10 @@ tacaw_status validate_desc(const tacaw_job_desc* d) {
       return TACAW_EINVAL;
     }
   }
+  if (d->n_atoms >= (1 << 27)) {
+    set_error("n_atoms %d above the 2^27 the pair lists encode", d->n_atoms);
+    return TACAW_EUNSUPPORTED;
+  }
   if (!grid_supported(d->nx) || !grid_supported(d->ny)) {
     set_error("grid %dx%d: this build has kernels for 16, 32, 48, 64, 96, 128, 160, 192, 256, 320, "
               "384, 512, 640, 768, 1024",
@@ -290,9 +294,11 @@ tacaw_status plan_job(const tacaw_job_desc* d, const int32_t* atom_species, cons
       o[4] = (float)(rci / hp.dy);
     }
 
-  // Candidate atoms per (slice, tile): every atom whose mean position, widened
-  // by the truncation radius and the largest displacement from that mean, can
-  // reach the tile (box test per axis, periodic).
+  // Candidate (atom, term) pairs per (slice, tile): a term of an atom is listed
+  // for a tile when its own truncation box, widened by the largest
+  // displacement of any atom from its mean position (and two pixels), can
+  // reach the tile along both axes (periodic).  Entries are sorted-atom * 8 +
+  // term, in atom order then term order.
   std::vector<double> xbar(hp.A), ybar(hp.A);
   double dmx = 0.0, dmy = 0.0;
   for (int j = 0; j < hp.A; ++j) {
@@ -313,35 +319,33 @@ tacaw_status plan_job(const tacaw_job_desc* d, const int32_t* atom_species, cons
   hp.tiles_x = (hp.pnx + SPLAT_TX - 1) / SPLAT_TX;
   hp.tiles_y = (hp.pny + SPLAT_TY - 1) / SPLAT_TY;
   const int nt = hp.tiles_x * hp.tiles_y;
-  const double reach_x = hp.rc + dmx + 2.0 * hp.dx;
-  const double reach_y = hp.rc + dmy + 2.0 * hp.dy;
   hp.tile_start.assign((size_t)hp.ns * nt + 1, 0);
   hp.tile_atoms.clear();
-  // per-axis lists: which tiles along x (resp. y) each atom reaches
-  std::vector<std::vector<int>> tx_of(hp.A), ty_of(hp.A);
-  for (int j = 0; j < hp.A; ++j) {
-    const int oj = hp.order[j];
-    for (int tx = 0; tx < hp.tiles_x; ++tx) {
-      const double a0 = tx * SPLAT_TX * hp.dx;
-      const double a1 = (std::min((tx + 1) * SPLAT_TX, hp.pnx) - 1) * hp.dx;
+  auto reached = [](double u, double L, double d, int n, int tile_w, int n_tiles, double reach,
+                    std::vector<int>& out) {
+    out.clear();
+    for (int t = 0; t < n_tiles; ++t) {
+      const double a0 = t * tile_w * d;
+      const double a1 = (std::min((t + 1) * tile_w, n) - 1) * d;
       const double c = 0.5 * (a0 + a1), h = 0.5 * (a1 - a0);
-      const double dist = fabs(wrap_min_image(xbar[oj] - c, hp.lx)) - h;
-      if (dist <= reach_x) tx_of[j].push_back(tx);
+      if (fabs(wrap_min_image(u - c, L)) - h <= reach) out.push_back(t);
     }
-    for (int ty = 0; ty < hp.tiles_y; ++ty) {
-      const double a0 = ty * SPLAT_TY * hp.dy;
-      const double a1 = (std::min((ty + 1) * SPLAT_TY, hp.pny) - 1) * hp.dy;
-      const double c = 0.5 * (a0 + a1), h = 0.5 * (a1 - a0);
-      const double dist = fabs(wrap_min_image(ybar[oj] - c, hp.ly)) - h;
-      if (dist <= reach_y) ty_of[j].push_back(ty);
-    }
-  }
+  };
   std::vector<std::vector<int32_t>> bucket(nt);
+  std::vector<int> txs, tys;
   for (int s = 0; s < hp.ns; ++s) {
     for (auto& b : bucket) b.clear();
-    for (int j = slice_start[s]; j < slice_start[s + 1]; ++j)
-      for (int ty : ty_of[j])
-        for (int tx : tx_of[j]) bucket[ty * hp.tiles_x + tx].push_back(j);
+    for (int j = slice_start[s]; j < slice_start[s + 1]; ++j) {
+      const int oj = hp.order[j];
+      const int sp = hp.sorted_species[j];
+      for (int i = 0; i < N_GAUSS; ++i) {
+        const double rci = sqrt(d->gauss_b[sp * N_GAUSS + i] * log(1e8)) / M_PI;
+        reached(xbar[oj], hp.lx, hp.dx, hp.pnx, SPLAT_TX, hp.tiles_x, rci + dmx + 2.0 * hp.dx, txs);
+        reached(ybar[oj], hp.ly, hp.dy, hp.pny, SPLAT_TY, hp.tiles_y, rci + dmy + 2.0 * hp.dy, tys);
+        for (int ty : tys)
+          for (int tx : txs) bucket[ty * hp.tiles_x + tx].push_back((int32_t)(j * 8 + i));
+      }
+    }
     for (int t = 0; t < nt; ++t) {
       hp.tile_start[(size_t)s * nt + t] = (int32_t)hp.tile_atoms.size();
       hp.tile_atoms.insert(hp.tile_atoms.end(), bucket[t].begin(), bucket[t].end());

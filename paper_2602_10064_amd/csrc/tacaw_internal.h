@@ -15,10 +15,12 @@ struct AtomPos {
 };
 
 constexpr int N_GAUSS = 5;
-constexpr int SPLAT_TX = 64;   // splat tile: columns
+constexpr int SPLAT_TX = 32;   // splat tile: columns
 constexpr int SPLAT_TY = 32;   // splat tile: rows
 constexpr int COEF_STRIDE = 5; // per (species, term): amplitude, exp2 x, exp2 y, cutoff x, cutoff y
-constexpr int SPLAT_MC = 16;   // candidate atoms staged in LDS per round
+constexpr int SPLAT_MC = 64;   // candidate (atom, term) pairs staged in LDS per round
+constexpr int SPLAT_FPB = 8;   // frames per splat workgroup (candidate lists are frame independent)
+constexpr int SPLAT_MAX_SPECIES = 16;  // species whose coefficients are staged in LDS
 constexpr int COL_CT = 16;     // columns per column-pass workgroup (128-byte rows)
 
 // Projected potentials of a batch of frames.
@@ -26,11 +28,11 @@ struct SplatArgs {
   const AtomPos* pos;          // [F][A], atoms sorted by slice
   const int32_t* species;      // [A] species index, sorted order
   const int32_t* tile_start;   // [n_slices * tiles + 1] CSR offsets
-  const int32_t* tile_atoms;   // sorted-atom indices
+  const int32_t* tile_atoms;   // candidate pairs: sorted-atom index * 8 + Gaussian term
   const float* coef;           // [S][5][COEF_STRIDE]: amplitude (V A), exp2 factor per pixel^2
                                // along x and y, truncation radius in pixels along x and y
   float* V;                    // [fb][gridDim.y][pny][pnx]: slices slice0 .. slice0+gridDim.y-1
-  int n_atoms, f0, fb, n_slices, slice0, pnx, pny, tiles_x, tiles_y;
+  int n_atoms, n_species, f0, fb, n_slices, slice0, pnx, pny, tiles_x, tiles_y;
   float rcx, rcy;              // truncation radius in pixels along x and y
   int img_x, img_y;            // periodic images -img..img searched per axis
 };

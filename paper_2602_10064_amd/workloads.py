@@ -165,11 +165,15 @@ def harmonic_trajectory(lattice: np.ndarray, cell: np.ndarray, reps: Sequence[in
     amp = 1.0 / omega
     q = n / cell[None, :]                          # cycles / A
     t = np.arange(n_frames, dtype=np.float64) * dt_fs
-    spatial = 2.0 * math.pi * (lattice @ q.T)      # (A, M)
-    u = np.zeros((n_frames, lattice.shape[0], 3), dtype=np.float64)
-    for m in range(n_modes):
-        c = np.cos(spatial[None, :, m] - omega[m] * t[:, None] + phi[m])  # (F, A)
-        u += (amp[m] * c)[:, :, None] * e[m][None, None, :]
+    spatial = 2.0 * math.pi * (lattice @ q.T) + phi[None, :]      # (A, M)
+    # cos(s - w t) = cos(s) cos(w t) + sin(s) sin(w t): the mode sum becomes
+    # two (F x M) @ (M x A) products per Cartesian component
+    ct, st = np.cos(np.outer(t, omega)), np.sin(np.outer(t, omega))  # (F, M)
+    cs, ss = np.cos(spatial).T, np.sin(spatial).T                    # (M, A)
+    u = np.empty((n_frames, lattice.shape[0], 3), dtype=np.float64)
+    for ax in range(3):
+        wgt = (amp * e[:, ax])[:, None]
+        u[:, :, ax] = ct @ (wgt * cs) + st @ (wgt * ss)
     scale = rms / np.sqrt(np.mean(u * u, axis=(0, 1)))
     u *= scale[None, None, :]
     x = lattice[None, :, :] + u

@@ -162,3 +162,24 @@ def test_c3_shape_reduced_probes_frames(tacaw, ctx, oracle):
     # 20 slices, 30 mrad at 60 kV) with a 3x3 scan and 4 frames
     job = w.c3_probe(n_frames=4, n_scan=3)
     check_job(tacaw, ctx, oracle, job)
+
+
+@pytest.mark.parametrize("variant", ["0", "2"])
+def test_row_variants_bitwise(tacaw, ctx, monkeypatch, variant):
+    # every row-pass variant computes each row with the same arithmetic
+    job = w.c1_tiny(n_frames=16)
+    _, a, _ = run_gpu(tacaw, ctx, job)
+    monkeypatch.setenv("TACAW_ROW_VARIANT", variant)
+    monkeypatch.setenv("TACAW_COL_VARIANT", "0")
+    _, b, _ = run_gpu(tacaw, ctx, job)
+    if variant == "0":
+        assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+    else:
+        assert rel_l2(b, a) < 1e-5
+
+
+def test_c2_shape_register_row_kernel(tacaw, ctx, oracle, monkeypatch):
+    monkeypatch.setenv("TACAW_ROW_VARIANT", "2")
+    monkeypatch.setenv("TACAW_FB", "3")
+    job = w.c2_plain(n_frames=8)
+    check_job(tacaw, ctx, oracle, job)
