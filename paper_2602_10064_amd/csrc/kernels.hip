@@ -92,6 +92,14 @@ __global__ void k_probe_fill(float2* out, const double* rloc, const int* count, 
   out[i] = v;
 }
 
+// Orders LDS writes and reads of the lanes of one wavefront (no workgroup
+// barrier needed when only that wavefront touches the memory).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // exp(i phi) for the transmission function: the argument is reduced to
 // [-1/2, 1/2) revolutions exactly (subtracting an integer), then the hardware
 // sine and cosine (absolute error ~1.6e-7 there) are used.
@@ -180,17 +188,17 @@ __device__ __forceinline__ float profile_tile(int o, int j, float f, float e2, f
 // The pair order and the instruction sequence are fixed, so the result is
 // deterministic.
 __global__ void __launch_bounds__(256) k_splat(SplatTable tab) {
-  constexpr int MP = SPLAT_MC;   // pairs staged per round (multiple of 4)
-  constexpr int FPB = SPLAT_FPB; // frames per block
+  constexpr int MP = 32;          // pairs per round: one row profile and one column profile per lane
+  constexpr int PAD = SPLAT_TX + 1;
+  constexpr int FPW = SPLAT_FPW;  // frames per wavefront
   static_assert(SPLAT_TX == 32 && SPLAT_TY == 32, "MFMA tiling assumes 32 x 32 tiles");
-  static_assert(MP % 4 == 0 && MP <= 256, "pair rounds");
-  __shared__ float gx[MP][SPLAT_TX];
-  __shared__ float gy[MP][SPLAT_TY];
-  __shared__ PairData pd[MP];
-  __shared__ AtomPos fpos[FPB][MP];
-  __shared__ int pcoef[MP];  // offset of the pair's coefficients
+  __shared__ float gxs[4][MP][PAD];
+  __shared__ float gys[4][MP][PAD];
   __shared__ float coef_s[SPLAT_MAX_SPECIES * N_GAUSS * COEF_STRIDE];
 
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  // one work item (tile, slice, group of FPW frames) per wavefront; lanes of
+  // the table start on block boundaries
   const int L = find_lane(tab, blockIdx.x);
   const SplatArgs& a = tab.l[L].a;
   const int nsl = tab.l[L].n_slices_launch;
@@ -198,15 +206,16 @@ __global__ void __launch_bounds__(256) k_splat(SplatTable tab) {
   const bool coef_in_lds = a.n_species <= SPLAT_MAX_SPECIES;
   if (coef_in_lds)
     for (int i = threadIdx.x; i < n_coef; i += blockDim.x) coef_s[i] = a.coef[i];
+  __syncthreads();  // the only workgroup barrier: everything below is per wavefront
   const float* coef = coef_in_lds ? coef_s : a.coef;
-  const int lb = blockIdx.x - tab.l[L].block_start;
-  const int tid = threadIdx.x;
   const int n_tiles = a.tiles_x * a.tiles_y;
-  const int tile = lb % n_tiles;
-  const int sl = (lb / n_tiles) % nsl;
-  const int fg = lb / (n_tiles * nsl);
-  const int fl0 = fg * FPB;
-  const int nf = min(FPB, a.fb - fl0);
+  const int n_fg = (a.fb + FPW - 1) / FPW;
+  const int item = (blockIdx.x - tab.l[L].block_start) * 4 + wave;
+  if (item >= n_tiles * nsl * n_fg) return;
+  const int tile = item % n_tiles;
+  const int sl = (item / n_tiles) % nsl;
+  const int fl0 = (item / (n_tiles * nsl)) * FPW;
+  const int nf = min(FPW, a.fb - fl0);
   const int s = a.slice0 + sl;
   const int tx0 = (tile % a.tiles_x) * SPLAT_TX;
   const int ty0 = (tile / a.tiles_x) * SPLAT_TY;
@@ -214,98 +223,119 @@ __global__ void __launch_bounds__(256) k_splat(SplatTable tab) {
   const int ce = a.tile_start[s * n_tiles + tile + 1];
   const bool simple_x = a.img_x == 0 && 2 * (a.rcx + SPLAT_TX + 2) < a.pnx;
   const bool simple_y = a.img_y == 0 && 2 * (a.rcy + SPLAT_TY + 2) < a.pny;
-
-  const int wave = tid / 64, lane = tid % 64;
-  const int row0 = 16 * (wave & 1), col0 = 16 * (wave >> 1);
+  float (*gx)[PAD] = gxs[wave];
+  float (*gy)[PAD] = gys[wave];
+  const int pr = lane % MP;         // pair of this lane
+  const bool along_y = lane >= MP;  // lanes 0-31 build column profiles, 32-63 row profiles
+  float* dst = along_y ? gy[pr] : gx[pr];
   typedef float v4f __attribute__((ext_vector_type(4)));
-  v4f acc[FPB];
-#pragma unroll
-  for (int k = 0; k < FPB; ++k) acc[k] = v4f{0.f, 0.f, 0.f, 0.f};
 
-  for (int c0 = cs; c0 < ce; c0 += MP) {
-    const int mp = min(MP, ce - c0);
-    const int mp4 = (mp + 3) & ~3;  // zero-padded to whole MFMA steps
-    __syncthreads();
-    // positions of every (frame, pair) of this round in one go
-    for (int e = tid; e < mp * FPB; e += 256) {
-      const int m = e % mp, k = e / mp;
-      const int entry = a.tile_atoms[c0 + m];
-      const int atom = entry >> 3;
-      if (k < nf) fpos[k][m] = a.pos[(size_t)(a.f0 + fl0 + k) * a.n_atoms + atom];
-      if (k == 0) pcoef[m] = (a.species[atom] * N_GAUSS + (entry & 7)) * COEF_STRIDE;
-    }
-    __syncthreads();
-#pragma unroll 1
-    for (int k = 0; k < nf; ++k) {
-      if (tid < mp) {
-        const AtomPos p = fpos[k][tid];
-        const float* c = coef + pcoef[tid];
-        PairData q;
-        q.ix = p.ix;
-        q.iy = p.iy;
-        q.ox = tx0 - p.ix;
-        if (q.ox >= a.pnx - a.pnx / 2) q.ox -= a.pnx;
-        if (q.ox < -(a.pnx / 2)) q.ox += a.pnx;
-        q.oy = ty0 - p.iy;
-        if (q.oy >= a.pny - a.pny / 2) q.oy -= a.pny;
-        if (q.oy < -(a.pny / 2)) q.oy += a.pny;
-        q.fx = p.fx;
-        q.fy = p.fy;
-        q.amp = c[0];
-        q.e2x = c[1];
-        q.e2y = c[2];
-        q.rcx = c[3];
-        q.rcy = c[4];
-        pd[tid] = q;
-      }
-      __syncthreads();
-      for (int e = tid; e < mp4 * SPLAT_TX; e += 256) {
-        const int kk = e / SPLAT_TX, x = e % SPLAT_TX;
-        float v = 0.f;
-        if (kk < mp) {
-          const PairData& q = pd[kk];
-          v = simple_x ? profile_tile(q.ox, x, q.fx, q.e2x, q.rcx)
-                       : profile(tx0 + x, q.ix, q.fx, a.pnx, q.e2x, q.rcx, a.img_x);
-        }
-        gx[kk][x] = v;
-      }
-      for (int e = tid; e < mp4 * SPLAT_TY; e += 256) {
-        const int kk = e / SPLAT_TY, y = e % SPLAT_TY;
-        float v = 0.f;
-        if (kk < mp) {
-          const PairData& q = pd[kk];
-          v = q.amp * (simple_y ? profile_tile(q.oy, y, q.fy, q.e2y, q.rcy)
-                                : profile(ty0 + y, q.iy, q.fy, a.pny, q.e2y, q.rcy, a.img_y));
-        }
-        gy[kk][y] = v;
-      }
-      __syncthreads();
-      // D[r][c] += sum_k gy[k][row0 + r] * gx[k][col0 + c]; A is 16 x 4 (lane:
-      // row lane % 16, k lane / 16), B is 4 x 16 (k lane / 16, column lane % 16)
-      v4f d = acc[0];
+  // per round: this lane's atom and coefficients are the same for every
+  // frame; positions of the first PRE rounds are prefetched one frame ahead
+  constexpr int PRE = 4;
+  int atom_r[PRE];
+  int coef_r[PRE];
+  AtomPos pn[PRE];
 #pragma unroll
-      for (int q = 1; q < FPB; ++q)
-        if (q == k) d = acc[q];
-      for (int k0 = 0; k0 < mp4; k0 += 4) {
-        const int kk = k0 + lane / 16;
-        d = __builtin_amdgcn_mfma_f32_16x16x4f32(gy[kk][row0 + lane % 16], gx[kk][col0 + lane % 16], d, 0, 0, 0);
-      }
-#pragma unroll
-      for (int q = 0; q < FPB; ++q)
-        if (q == k) acc[q] = d;
-      __syncthreads();  // pd, gx and gy are rewritten for the next frame
+  for (int r = 0; r < PRE; ++r) {
+    atom_r[r] = -1;
+    coef_r[r] = 0;
+    const int c0 = cs + r * MP;
+    if (c0 + pr < ce) {
+      const int entry = a.tile_atoms[c0 + pr];
+      atom_r[r] = entry >> 3;
+      coef_r[r] = (a.species[entry >> 3] * N_GAUSS + (entry & 7)) * COEF_STRIDE;
     }
   }
-  // D layout: lane holds rows 4 (lane / 16) + j, j < 4, of column lane % 16
-  const int x = tx0 + col0 + lane % 16;
 #pragma unroll
-  for (int k = 0; k < FPB; ++k) {
-    if (k >= nf) break;
+  for (int r = 0; r < PRE; ++r)
+    if (atom_r[r] >= 0 && nf > 0) pn[r] = a.pos[(size_t)(a.f0 + fl0) * a.n_atoms + atom_r[r]];
+
+  for (int k = 0; k < nf; ++k) {
+    const int fl = fl0 + k;
+    const size_t frame_off = (size_t)(a.f0 + fl) * a.n_atoms;
+    v4f acc[4] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+    int r = 0;
+    for (int c0 = cs; c0 < ce; c0 += MP, ++r) {
+      const int mp = min(MP, ce - c0);
+      const int mp4 = (mp + 3) & ~3;
+      AtomPos p{};
+      const float* c = coef;
+      if (r < PRE) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int y = ty0 + row0 + 4 * (lane / 16) + j;
-      if (y < a.pny && x < a.pnx)
-        a.V[(((size_t)(fl0 + k) * nsl + sl) * a.pny + y) * a.pnx + x] = acc[k][j];
+        for (int q = 0; q < PRE; ++q)
+          if (q == r) {
+            p = pn[q];
+            c = coef + coef_r[q];
+            if (atom_r[q] >= 0 && k + 1 < nf) pn[q] = a.pos[frame_off + a.n_atoms + atom_r[q]];
+          }
+      } else if (pr < mp) {
+        const int entry = a.tile_atoms[c0 + pr];
+        p = a.pos[frame_off + (entry >> 3)];
+        c = coef + (a.species[entry >> 3] * N_GAUSS + (entry & 7)) * COEF_STRIDE;
+      }
+      wave_lds_sync();  // the previous round's MFMA reads are done
+      if (pr < mp) {
+        if (!along_y) {
+          const float e2 = c[1], rc = c[3];
+          int o = tx0 - p.ix;
+          if (o >= a.pnx - a.pnx / 2) o -= a.pnx;
+          if (o < -(a.pnx / 2)) o += a.pnx;
+          if (simple_x) {
+            // node x sits at d = x - u pixels from the atom, u = fx - o
+            const float u = p.fx - (float)o;
+#pragma unroll
+            for (int x = 0; x < SPLAT_TX; ++x) {
+              const float d = (float)x - u;
+              dst[x] = fabsf(d) <= rc ? __builtin_amdgcn_exp2f(-e2 * d * d) : 0.f;
+            }
+          } else {
+            for (int x = 0; x < SPLAT_TX; ++x) dst[x] = profile(tx0 + x, p.ix, p.fx, a.pnx, e2, rc, a.img_x);
+          }
+        } else {
+          const float amp = c[0], e2 = c[2], rc = c[4];
+          int o = ty0 - p.iy;
+          if (o >= a.pny - a.pny / 2) o -= a.pny;
+          if (o < -(a.pny / 2)) o += a.pny;
+          if (simple_y) {
+            const float u = p.fy - (float)o;
+#pragma unroll
+            for (int y = 0; y < SPLAT_TY; ++y) {
+              const float d = (float)y - u;
+              dst[y] = fabsf(d) <= rc ? amp * __builtin_amdgcn_exp2f(-e2 * d * d) : 0.f;
+            }
+          } else {
+            for (int y = 0; y < SPLAT_TY; ++y)
+              dst[y] = amp * profile(ty0 + y, p.iy, p.fy, a.pny, e2, rc, a.img_y);
+          }
+        }
+      } else if (pr < mp4) {
+#pragma unroll
+        for (int x = 0; x < SPLAT_TX; ++x) dst[x] = 0.f;
+      }
+      wave_lds_sync();
+      // V[r][c] += sum_k gy[k][r] gx[k][c] over four 16 x 16 quarters; A is 16 x 4
+      // (row lane % 16, k lane / 16), B is 4 x 16 (k lane / 16, column lane % 16)
+      for (int k0 = 0; k0 < mp4; k0 += 4) {
+        const int kk = k0 + lane / 16;
+        const float a0 = gy[kk][lane % 16], a1 = gy[kk][16 + lane % 16];
+        const float b0 = gx[kk][lane % 16], b1 = gx[kk][16 + lane % 16];
+        acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[1], 0, 0, 0);
+        acc[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[2], 0, 0, 0);
+        acc[3] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[3], 0, 0, 0);
+      }
+    }
+    // D layout: lane holds rows 4 (lane / 16) + j, j < 4, of column lane % 16
+    float* out = a.V + ((size_t)fl * nsl + sl) * a.pny * a.pnx;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int x = tx0 + 16 * (q & 1) + lane % 16;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int y = ty0 + 16 * (q >> 1) + 4 * (lane / 16) + j;
+        if (y < a.pny && x < a.pnx) out[(size_t)y * a.pnx + x] = acc[q][j];
+      }
     }
   }
 }
@@ -405,12 +435,6 @@ __global__ void __launch_bounds__((RowCfg<N, VAR>::THREADS)) k_row(PassTable tab
 // wavefront walks over rows with a grid stride; stage twiddles stay in
 // registers for all its rows.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 template <int N>
 struct R8 {
   static constexpr int S = N == 8 ? 1 : N == 64 ? 2 : N == 512 ? 3 : N == 4096 ? 4 : 0;
@@ -623,24 +647,24 @@ __global__ void __launch_bounds__((ColCfg<N, VAR>::THREADS)) k_col(PassTable tab
 // grid stride (XCD-contiguous order), keeping their stage twiddles in
 // registers.
 // ---------------------------------------------------------------------------
-template <int N>
+template <int N, int WIDE>
 struct C8 {
   static constexpr int G = N / 8;               // lanes per column
   static constexpr int CPW = 64 / G;            // columns per wavefront
-  static constexpr int WAVES = N == 512 ? 8 : 4;
+  static constexpr int WAVES = (N == 512 ? 8 : 4) * (WIDE ? 2 : 1);
   static constexpr int CT = WAVES * CPW;        // columns per block
   static constexpr int LD = N + 2;
   static constexpr int THREADS = WAVES * 64;
 };
 
-template <int N>
-__global__ void __launch_bounds__((C8<N>::THREADS)) k_col_r8(PassTable tab, int total_tiles) {
-  constexpr int G = C8<N>::G;
-  constexpr int CPW = C8<N>::CPW;
-  constexpr int CT = C8<N>::CT;
-  constexpr int LD = C8<N>::LD;
+template <int N, int WIDE>
+__global__ void __launch_bounds__((C8<N, WIDE>::THREADS)) k_col_r8(PassTable tab, int total_tiles) {
+  constexpr int G = C8<N, WIDE>::G;
+  constexpr int CPW = C8<N, WIDE>::CPW;
+  constexpr int CT = C8<N, WIDE>::CT;
+  constexpr int LD = C8<N, WIDE>::LD;
   constexpr int S = R8<N>::S;
-  constexpr int THREADS = C8<N>::THREADS;
+  constexpr int THREADS = C8<N, WIDE>::THREADS;
   constexpr int PER = CT * N / THREADS;  // tile values each thread moves
   __shared__ float2 cols[CT * LD];
   const int wave = threadIdx.x / 64;
@@ -886,9 +910,9 @@ hipError_t launch_row_lanes(const PassLane* lanes, int n, int variant, hipStream
   }
 }
 
-template <int N>
+template <int N, int WIDE>
 static hipError_t col_r8_launch(PassTable& t, hipStream_t s) {
-  constexpr int CT = C8<N>::CT;
+  constexpr int CT = C8<N, WIDE>::CT;
   int tiles = 0;
   for (int i = 0; i < t.n; ++i) {
     const PassArgs& a = t.l[i].a;
@@ -897,7 +921,7 @@ static hipError_t col_r8_launch(PassTable& t, hipStream_t s) {
     tiles += a.n_probes * a.fb * (a.nx / CT);
   }
   const int grid = std::min(tiles, 2048);
-  hipLaunchKernelGGL((k_col_r8<N>), dim3(grid), dim3(C8<N>::THREADS), 0, s, t, tiles);
+  hipLaunchKernelGGL((k_col_r8<N, WIDE>), dim3(grid), dim3(C8<N, WIDE>::THREADS), 0, s, t, tiles);
   return hipGetLastError();
 }
 
@@ -906,9 +930,13 @@ hipError_t launch_col_lanes(const PassLane* lanes, int n, int variant, hipStream
   PassTable t{};
   t.n = n;
   for (int i = 0; i < n; ++i) t.l[i] = lanes[i];
+  if (variant == 3) {
+    if (lanes[0].a.ny == 512 && lanes[0].a.nx % C8<512, 1>::CT == 0) return col_r8_launch<512, 1>(t, s);
+    variant = 2;
+  }
   if (variant == 2) {
-    if (lanes[0].a.ny == 512 && lanes[0].a.nx % C8<512>::CT == 0) return col_r8_launch<512>(t, s);
-    if (lanes[0].a.ny == 64 && lanes[0].a.nx % C8<64>::CT == 0) return col_r8_launch<64>(t, s);
+    if (lanes[0].a.ny == 512 && lanes[0].a.nx % C8<512, 0>::CT == 0) return col_r8_launch<512, 0>(t, s);
+    if (lanes[0].a.ny == 64 && lanes[0].a.nx % C8<64, 0>::CT == 0) return col_r8_launch<64, 0>(t, s);
     variant = 0;
   }
   switch (lanes[0].a.ny) {
@@ -944,7 +972,9 @@ hipError_t launch_splat_lanes(const SplatLane* lanes, int n, hipStream_t s) {
     t.l[i] = lanes[i];
     t.l[i].block_start = blocks;
     const SplatArgs& a = lanes[i].a;
-    blocks += a.tiles_x * a.tiles_y * lanes[i].n_slices_launch * ((a.fb + SPLAT_FPB - 1) / SPLAT_FPB);
+    const int items = a.tiles_x * a.tiles_y * lanes[i].n_slices_launch *
+                      ((a.fb + SPLAT_FPW - 1) / SPLAT_FPW);  // one per wavefront
+    blocks += (items + 3) / 4;
   }
   hipLaunchKernelGGL(k_splat, dim3(blocks), dim3(256), 0, s, t);
   return hipGetLastError();
