@@ -262,6 +262,7 @@ TACAW_PLAN(512, 64, 8, 8, 8)
 TACAW_PLAN(640, 16, 8, 4, 4, 5)
 TACAW_PLAN(768, 32, 8, 8, 4, 3)
 TACAW_PLAN(1024, 64, 8, 8, 4, 4)
+TACAW_PLAN(2048, 64, 8, 8, 8, 4)
 #undef TACAW_PLAN
 
 // ---------------------------------------------------------------------------

@@ -825,6 +825,74 @@ __global__ void __launch_bounds__(256) k_time(TimeArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Time stage with a compile-time plan for F frames: a block owns KT adjacent
+// k points of one probe (KT * 8 contiguous bytes per frame row), holds their
+// F-long columns in one LDS buffer, takes the FP64 mean per column with
+// lane shuffles, subtracts it in FP64, runs the in-place Stockham FFT and
+// writes |.|^2 / F^2 of the kept bins.
+// ---------------------------------------------------------------------------
+template <int F>
+struct TimeCfg {
+  static constexpr int G = Plan<F>::G;
+  static constexpr int KT0 = (144 * 1024) / ((F + 1) * 8);
+  static constexpr int KTT = 1024 / G;
+  static constexpr int KTM = KT0 < KTT ? KT0 : KTT;
+  static constexpr int KT = KTM >= 32 ? 32 : KTM >= 16 ? 16 : KTM >= 8 ? 8 : KTM >= 4 ? 4 : KTM >= 2 ? 2 : 1;
+  static constexpr int THREADS = KT * G;
+  static constexpr int LD = F + 1;
+};
+
+template <int F>
+__global__ void __launch_bounds__((TimeCfg<F>::THREADS)) k_time_ct(TimeArgs a) {
+  using PL = Plan<F>;
+  constexpr int G = PL::G;
+  constexpr int KT = TimeCfg<F>::KT;
+  constexpr int LD = TimeCfg<F>::LD;
+  extern __shared__ float2 smem[];
+  float2* tw = smem;
+  float2* cols = smem + F;
+  for (int i = threadIdx.x; i < F; i += blockDim.x) tw[i] = a.tw[i];
+  const int tiles_per_probe = a.n_k / KT;
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int p = tile / tiles_per_probe;
+  const int k0 = (tile % tiles_per_probe) * KT;
+  const float2* src = a.exit + (size_t)p * F * a.n_k + k0;
+  for (int e = threadIdx.x; e < KT * F; e += blockDim.x) {
+    const int c = e % KT, f = e / KT;
+    cols[c * LD + f] = src[(size_t)f * a.n_k + c];
+  }
+  __syncthreads();
+  const int c = threadIdx.x / G;
+  const int t = threadIdx.x % G;
+  float2* col = cols + c * LD;
+  // FP64 mean over frames: strided partial sums, then a butterfly over the
+  // G lanes of this column (fixed order, so the result is deterministic)
+  double sr = 0.0, si = 0.0;
+  for (int f = t; f < F; f += G) {
+    sr += (double)col[f].x;
+    si += (double)col[f].y;
+  }
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1) {
+    sr += __shfl_xor(sr, off, G);
+    si += __shfl_xor(si, off, G);
+  }
+  const double mr = sr / (double)F, mi = si / (double)F;
+  for (int f = t; f < F; f += G) {
+    const float2 v = col[f];
+    col[f] = make_float2((float)((double)v.x - mr), (float)((double)v.y - mi));
+  }
+  __syncthreads();
+  StagesIP<F, G, false, 1, typename PL::R>::run(col, tw, t);
+  float* dst = a.spec + (size_t)p * a.n_bins * a.n_k + k0;
+  for (int e = threadIdx.x; e < KT * a.n_bins; e += blockDim.x) {
+    const int cc = e % KT, m = e / KT;
+    const float2 v = cols[cc * LD + m];
+    dst[(size_t)m * a.n_k + cc] = (v.x * v.x + v.y * v.y) * a.inv_f2;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
 #define TACAW_SIZES(X) X(16) X(32) X(48) X(64) X(96) X(128) X(160) X(192) X(256) X(320) X(384) X(512) \
@@ -993,7 +1061,35 @@ int time_stage_kt(int n_frames, int n_k) {
   return kt;
 }
 
+template <int F>
+static hipError_t time_ct_launch(const TimeArgs& a, hipStream_t s) {
+  constexpr int KT = TimeCfg<F>::KT;
+  if (a.n_k % KT != 0) return hipErrorInvalidValue;
+  const size_t lds = (size_t)(F + KT * TimeCfg<F>::LD) * sizeof(float2);
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_time_ct<F>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  const long blocks = (long)a.n_probes * (a.n_k / KT);
+  hipLaunchKernelGGL(k_time_ct<F>, dim3((unsigned)blocks), dim3(TimeCfg<F>::THREADS), lds, s, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_time_stage(const TimeArgs& a, hipStream_t s) {
+  switch (a.n_frames) {
+#define CASE(NN) \
+  case NN:       \
+    if (a.n_k % TimeCfg<NN>::KT == 0) return time_ct_launch<NN>(a, s); \
+    break;
+    TACAW_SIZES(CASE)
+    CASE(2048)
+#undef CASE
+    default:
+      break;
+  }
   if (a.n_k % a.kt != 0 || a.kt * a.n_frames > TIME_LDS_C) return hipErrorInvalidValue;
   const size_t lds = (size_t)(a.n_frames + 2 * a.kt * a.n_frames) * sizeof(float2);
   const long blocks = (long)a.n_probes * (a.n_k / a.kt);
