@@ -170,71 +170,132 @@ PassArgs pass_args(tacaw_job* j) {
   return a;
 }
 
+static SplatArgs splat_args_of(tacaw_job* job, int f0, int fb) {
+  const HostPlan& hp = job->hp;
+  SplatArgs sa{};
+  sa.pos = job->d_pos;
+  sa.species = job->d_species;
+  sa.tile_start = job->d_tile_start;
+  sa.tile_atoms = job->d_tile_atoms;
+  sa.coef = job->d_coef;
+  sa.V = job->d_V;
+  sa.n_atoms = hp.A;
+  sa.n_species = hp.S;
+  sa.f0 = f0;
+  sa.fb = fb;
+  sa.n_slices = hp.ns;
+  sa.slice0 = 0;
+  sa.pnx = hp.pnx;
+  sa.pny = hp.pny;
+  sa.tiles_x = hp.tiles_x;
+  sa.tiles_y = hp.tiles_y;
+  sa.rcx = hp.rcx;
+  sa.rcy = hp.rcy;
+  sa.img_x = hp.img_x;
+  sa.img_y = hp.img_y;
+  return sa;
+}
+
+// Row pass then column pass of one slice for frames [f0, f0 + fb); the
+// potential of that slice is read from V (one slice, or all slices of the
+// batch when v_all).  after_row, if given, is recorded once the row pass (the
+// potential's only reader) is queued.
+static tacaw_status slice_passes(tacaw_job* job, hipStream_t s, int f0, int fb, int sl, float* V, bool v_all,
+                                 hipEvent_t after_row = nullptr) {
+  const HostPlan& hp = job->hp;
+  PassArgs a = pass_args(job);
+  a.f0 = f0;
+  a.fb = fb;
+  a.V = V;
+  a.v_slices = v_all ? hp.ns : 1;
+  a.v_slice0 = v_all ? 0 : sl;
+  a.slice = sl;
+  PassLane rl{};
+  rl.a = a;
+  rl.mode = sl == 0 ? ROW_FIRST : ROW_REGULAR;
+  const int rv = row_variant_for(job->ctx, hp.nx);
+  tacaw_status st = timed(job, TACAW_K_ROW, s, [&] { return launch_row_lanes(&rl, 1, rv, s); });
+  if (st != TACAW_OK) return st;
+  if (after_row) HIP_TRY(hipEventRecord(after_row, s));
+  const bool last = sl == hp.ns - 1;
+  PassLane cl{};
+  cl.a = a;
+  if (last) {
+    cl.a.px = job->d_px_last;
+    cl.a.py = job->d_py_last;
+  }
+  cl.mode = last ? COL_LAST : COL_REGULAR;
+  const int cv = col_variant_for(job->ctx, hp.ny);
+  return timed(job, TACAW_K_COL, s, [&] { return launch_col_lanes(&cl, 1, cv, s); });
+}
+
 // Potentials + all slices for frames [f_begin, f_end) (one or more frame batches).
+//
+// Overlapped form (per-slice potentials): the potential of step k + 1 (a
+// (frame batch, slice) pair) is built on the job's side stream while the row
+// and column passes of step k run on s.  Potentials alternate between two
+// buffers; step k's row pass waits for its potential, and the potential of
+// step k + 2 waits for step k's row pass, the last reader of that buffer.
+// Every side-stream launch is waited on by s, so s alone orders completion
+// (and a capture of s takes in the side stream's work).
 tacaw_status run_batch_range(tacaw_job* job, hipStream_t s, int f_begin, int f_end) {
   const HostPlan& hp = job->hp;
-  for (int f0 = f_begin; f0 < f_end; f0 += hp.fb) {
-    const int fb = std::min(hp.fb, f_end - f0);
-    SplatArgs sa{};
-    sa.pos = job->d_pos;
-    sa.species = job->d_species;
-    sa.tile_start = job->d_tile_start;
-    sa.tile_atoms = job->d_tile_atoms;
-    sa.coef = job->d_coef;
-    sa.V = job->d_V;
-    sa.n_atoms = hp.A;
-  sa.n_species = hp.S;
-    sa.n_species = hp.S;
-    sa.f0 = f0;
-    sa.fb = fb;
-    sa.n_slices = hp.ns;
-    sa.slice0 = 0;
-    sa.pnx = hp.pnx;
-    sa.pny = hp.pny;
-    sa.tiles_x = hp.tiles_x;
-    sa.tiles_y = hp.tiles_y;
-    sa.rcx = hp.rcx;
-    sa.rcy = hp.rcy;
-    sa.img_x = hp.img_x;
-    sa.img_y = hp.img_y;
-    tacaw_status st = TACAW_OK;
-    if (!hp.splat_per_slice) {
-      st = timed(job, TACAW_K_SPLAT, s, [&] { return launch_splat(sa, hp.ns, s); });
+  if (!hp.splat_per_slice) {
+    for (int f0 = f_begin; f0 < f_end; f0 += hp.fb) {
+      const int fb = std::min(hp.fb, f_end - f0);
+      SplatArgs sa = splat_args_of(job, f0, fb);
+      tacaw_status st = timed(job, TACAW_K_SPLAT, s, [&] { return launch_splat(sa, hp.ns, s); });
       if (st != TACAW_OK) return st;
+      for (int sl = 0; sl < hp.ns; ++sl)
+        if ((st = slice_passes(job, s, f0, fb, sl, job->d_V, true)) != TACAW_OK) return st;
     }
-    PassArgs a = pass_args(job);
-    a.f0 = f0;
-    a.fb = fb;
-    a.v_slices = hp.splat_per_slice ? 1 : hp.ns;
-    a.v_slice0 = 0;
-    for (int sl = 0; sl < hp.ns; ++sl) {
-      a.slice = sl;
-      if (hp.splat_per_slice) {
-        sa.slice0 = sl;
-        a.v_slice0 = sl;
-        st = timed(job, TACAW_K_SPLAT, s, [&] { return launch_splat(sa, 1, s); });
-        if (st != TACAW_OK) return st;
-      }
-      PassLane rl{};
-      rl.a = a;
-      rl.mode = sl == 0 ? ROW_FIRST : ROW_REGULAR;
-      const int rv = row_variant_for(job->ctx, hp.nx);
-      st = timed(job, TACAW_K_ROW, s, [&] { return launch_row_lanes(&rl, 1, rv, s); });
-      if (st != TACAW_OK) return st;
-      const bool last = sl == hp.ns - 1;
-      PassLane cl{};
-      cl.a = a;
-      if (last) {
-        cl.a.px = job->d_px_last;
-        cl.a.py = job->d_py_last;
-      }
-      cl.mode = last ? COL_LAST : COL_REGULAR;
-      const int cv = col_variant_for(job->ctx, hp.ny);
-      st = timed(job, TACAW_K_COL, s, [&] { return launch_col_lanes(&cl, 1, cv, s); });
-      if (st != TACAW_OK) return st;
-    }
+    return TACAW_OK;
   }
-  return TACAW_OK;
+  if (!hp.overlap) {
+    for (int f0 = f_begin; f0 < f_end; f0 += hp.fb) {
+      const int fb = std::min(hp.fb, f_end - f0);
+      for (int sl = 0; sl < hp.ns; ++sl) {
+        SplatArgs sa = splat_args_of(job, f0, fb);
+        sa.slice0 = sl;
+        tacaw_status st = timed(job, TACAW_K_SPLAT, s, [&] { return launch_splat(sa, 1, s); });
+        if (st != TACAW_OK) return st;
+        if ((st = slice_passes(job, s, f0, fb, sl, job->d_V, false)) != TACAW_OK) return st;
+      }
+    }
+    return TACAW_OK;
+  }
+  if (f_begin >= f_end) return TACAW_OK;
+  const size_t slab = (size_t)hp.fb * hp.pnx * hp.pny;
+  const int n_batches = (f_end - f_begin + hp.fb - 1) / hp.fb;
+  const long n_steps = (long)n_batches * hp.ns;
+  auto step_f0 = [&](long k) { return f_begin + (int)(k / hp.ns) * hp.fb; };
+  auto splat_step = [&](long k) -> tacaw_status {
+    const int f0 = step_f0(k), fb = std::min(hp.fb, f_end - f0), b = (int)(k & 1);
+    if (k >= 2) HIP_TRY(hipStreamWaitEvent(job->side, job->ev_row[b], 0));
+    SplatArgs sa = splat_args_of(job, f0, fb);
+    sa.V = job->d_V + b * slab;
+    sa.slice0 = (int)(k % hp.ns);
+    tacaw_status st = timed(job, TACAW_K_SPLAT, job->side, [&] { return launch_splat(sa, 1, job->side); });
+    if (st != TACAW_OK) return st;
+    HIP_TRY(hipEventRecord(job->ev_splat[b], job->side));
+    return TACAW_OK;
+  };
+  // fork: the side stream starts after the work already queued on s
+  HIP_TRY(hipEventRecord(job->ev_fork, s));
+  HIP_TRY(hipStreamWaitEvent(job->side, job->ev_fork, 0));
+  tacaw_status st = splat_step(0);
+  for (long k = 0; k < n_steps && st == TACAW_OK; ++k) {
+    if (k + 1 < n_steps && (st = splat_step(k + 1)) != TACAW_OK) break;
+    HIP_TRY(hipStreamWaitEvent(s, job->ev_splat[k & 1], 0));
+    const int f0 = step_f0(k), fb = std::min(hp.fb, f_end - f0);
+    st = slice_passes(job, s, f0, fb, (int)(k % hp.ns), job->d_V + (k & 1) * slab, false, job->ev_row[k & 1]);
+  }
+  if (st != TACAW_OK) {
+    // join the side stream so nothing it holds outlives an error return
+    (void)hipEventRecord(job->ev_fork, job->side);
+    (void)hipStreamWaitEvent(s, job->ev_fork, 0);
+  }
+  return st;
 }
 
 tacaw_status run_time_stage(tacaw_job* job, hipStream_t s) {
@@ -270,7 +331,7 @@ tacaw_status materialize(tacaw_job* j, hipStream_t s0) {
   if ((e = dalloc(&(ptr), (count))) != hipSuccess) return fail("hipMalloc " #ptr, e);
   if (!j->d_exit) ALLOC(j->d_exit, (size_t)hp.P * hp.F * nk);
   if (!j->d_spec) ALLOC(j->d_spec, (size_t)hp.P * hp.M * nk);
-  ALLOC(j->d_V, (size_t)hp.fb * (hp.splat_per_slice ? 1 : hp.ns) * hp.pnx * hp.pny);
+  ALLOC(j->d_V, (size_t)hp.fb * (hp.splat_per_slice ? (hp.overlap ? 2 : 1) : hp.ns) * hp.pnx * hp.pny);
   ALLOC(j->d_pos, (size_t)hp.F * hp.A);
   ALLOC(j->d_species, (size_t)hp.A);
   ALLOC(j->d_tile_start, hp.tile_start.size());
@@ -288,6 +349,12 @@ tacaw_status materialize(tacaw_job* j, hipStream_t s0) {
   ALLOC(j->d_count, 1);
   if (!hp.plane) ALLOC(j->d_probe0, (size_t)hp.P * nk);
 #undef ALLOC
+  if (hp.overlap && !j->side) {
+    if ((e = hipStreamCreateWithFlags(&j->side, hipStreamNonBlocking)) != hipSuccess) return fail("side stream", e);
+    hipEvent_t* evs[] = {&j->ev_fork, &j->ev_splat[0], &j->ev_splat[1], &j->ev_row[0], &j->ev_row[1]};
+    for (hipEvent_t* ev : evs)
+      if ((e = hipEventCreateWithFlags(ev, hipEventDisableTiming)) != hipSuccess) return fail("event", e);
+  }
 
   if (hp.A > 0) {
     if ((e = hipMemcpyAsync(j->d_pos, j->enc.data(), j->enc.size() * sizeof(AtomPos), hipMemcpyHostToDevice, s0)) !=
@@ -656,6 +723,9 @@ tacaw_status tacaw_job_destroy(tacaw_job* job) {
   }
   free_job_buffers(job);
   if (job->capture_stream) (void)hipStreamDestroy(job->capture_stream);
+  if (job->side) (void)hipStreamDestroy(job->side);
+  for (hipEvent_t ev : {job->ev_fork, job->ev_splat[0], job->ev_splat[1], job->ev_row[0], job->ev_row[1]})
+    if (ev) (void)hipEventDestroy(ev);
   delete job;
   return TACAW_OK;
 }

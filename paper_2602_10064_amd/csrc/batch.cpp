@@ -152,7 +152,7 @@ void load_tune_cache(tacaw_ctx* c) {
     int nx = 0, ny = 0, r = 0, cc = 0;
     if (sscanf(line.c_str(), "{\"nx\": %d, \"ny\": %d, \"row_variant\": %d, \"col_variant\": %d}", &nx, &ny, &r,
                &cc) == 4 &&
-        nx > 0 && nx < 2048 && ny > 0 && ny < 2048 && r >= 0 && r <= 2 && (cc == 0 || cc == 1)) {
+        nx > 0 && nx < 2048 && ny > 0 && ny < 2048 && r >= 0 && r <= 2 && cc >= 0 && cc <= 3) {
       c->row_variant[nx] = r + 1;
       c->col_variant[ny] = cc + 1;
     }
@@ -258,12 +258,17 @@ tacaw_status tacaw_autotune(tacaw_job* job, void* hip_stream, int* row_variant, 
   hipStream_t s = (hipStream_t)hip_stream;
   const HostPlan& hp = job->hp;
   const int fb = std::min(hp.fb, hp.F);
+  // row variants: 0, 1 (LDS rows), 2 (register radix-8, grids 64 and 512);
+  // column variants: 0, 1 (LDS columns), 2 (register radix-8 on 8-column
+  // tiles, ny 64 and 512), 3 (16-column tiles, ny 512)
   const int n_row_var = (hp.nx == 512 || hp.nx == 64) ? 3 : 2;
-  double best_row[3] = {1e30, 1e30, 1e30}, best_col[3] = {1e30, 1e30, 1e30};
+  const int n_col_var = hp.ny == 512 ? 4 : hp.ny == 64 ? 3 : 2;
+  const int n_var = std::max(n_row_var, n_col_var);
+  double best_row[4] = {1e30, 1e30, 1e30, 1e30}, best_col[4] = {1e30, 1e30, 1e30, 1e30};
   const bool was_timing = c->timing;
-  for (int v = 0; v < n_row_var; ++v) {
-    c->row_variant[hp.nx] = v + 1;
-    c->col_variant[hp.ny] = std::min(v, 1) + 1;
+  for (int v = 0; v < n_var; ++v) {
+    c->row_variant[hp.nx] = std::min(v, n_row_var - 1) + 1;
+    c->col_variant[hp.ny] = std::min(v, n_col_var - 1) + 1;
     for (int rep = 0; rep < 2; ++rep) {   // first repetition warms up
       {
         std::lock_guard<std::mutex> lk(c->mu);
@@ -279,8 +284,8 @@ tacaw_status tacaw_autotune(tacaw_job* job, void* hip_stream, int* row_variant, 
       int64_t n = 0;
       tacaw_timing_get(c, TACAW_K_ROW, &row_ms, &n);
       tacaw_timing_get(c, TACAW_K_COL, &col_ms, &n);
-      best_row[v] = row_ms;
-      best_col[v] = col_ms;
+      if (v < n_row_var) best_row[v] = row_ms;
+      if (v < n_col_var) best_col[v] = col_ms;
     }
     if (st != TACAW_OK) break;
   }
@@ -289,10 +294,11 @@ tacaw_status tacaw_autotune(tacaw_job* job, void* hip_stream, int* row_variant, 
     c->timing = was_timing;
   }
   if (st != TACAW_OK) return st;
-  int rv = 0;
+  int rv = 0, cv = 0;
   for (int v = 1; v < n_row_var; ++v)
     if (best_row[v] < best_row[rv]) rv = v;
-  const int cv = best_col[1] <= best_col[0] ? 1 : 0;
+  for (int v = 1; v < n_col_var; ++v)
+    if (best_col[v] < best_col[cv]) cv = v;
   c->row_variant[hp.nx] = rv + 1;
   c->col_variant[hp.ny] = cv + 1;
   if (row_variant) *row_variant = rv;

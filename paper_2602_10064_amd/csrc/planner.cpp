@@ -160,6 +160,15 @@ bool splat_per_slice() {
   return !(e && atoi(e) != 0);
 }
 
+// TACAW_OVERLAP=1: per-slice potentials are built one slice ahead on a side
+// stream (two alternating potential buffers).  Off by default: at 512^2 the
+// concurrent potential launches take occupancy from the column pass and the
+// whole step gets slower.
+bool overlap_splat() {
+  const char* e = getenv("TACAW_OVERLAP");
+  return splat_per_slice() && e && atoi(e) != 0;
+}
+
 // Frames per batch: the waves and potentials of one batch should stay within
 // ~192 MiB, so that between the row and column passes of a slice they can
 // live in the 256 MiB last-level cache.  TACAW_FB overrides the choice and
@@ -190,7 +199,7 @@ Footprint footprint_of(const tacaw_job_desc* d, int fb, size_t n_tile_atoms) {
   const size_t M = (d->flags & TACAW_TWO_SIDED) ? d->n_frames : d->n_frames / 2;
   f.exit = P * d->n_frames * nk * sizeof(float2);
   f.spec = P * M * nk * sizeof(float);
-  f.V = (size_t)fb * (splat_per_slice() ? 1 : d->n_slices) * pnx * pny * sizeof(float);
+  f.V = (size_t)fb * (splat_per_slice() ? (overlap_splat() ? 2 : 1) : d->n_slices) * pnx * pny * sizeof(float);
   f.pos = (size_t)d->n_frames * d->n_atoms * sizeof(AtomPos) + (size_t)d->n_atoms * sizeof(int32_t);
   f.tiles = n_tile_atoms * sizeof(int32_t);
   f.probes = plane ? 0 : P * nk * sizeof(float2) + P * (2 * sizeof(int32_t) + 2 * sizeof(double));
@@ -227,6 +236,7 @@ tacaw_status plan_job(const tacaw_job_desc* d, const int32_t* atom_species, cons
   hp.alpha = d->aperture_mrad * 1e-3;
   hp.fb = choose_frame_batch(d);
   hp.splat_per_slice = splat_per_slice();
+  hp.overlap = overlap_splat();
 
   for (int j = 0; j < hp.A; ++j)
     if (atom_species[j] < 0 || atom_species[j] >= hp.S) {

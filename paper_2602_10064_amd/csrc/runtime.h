@@ -33,6 +33,7 @@ struct HostPlan {
   int img_x = 0, img_y = 0, tiles_x = 0, tiles_y = 0;
   int fb = 1;                          // frames per batch
   bool splat_per_slice = true;         // potentials built slice by slice
+  bool overlap = true;                 // per-slice potentials built one slice ahead on a side stream
   std::vector<int32_t> slice_of;       // per input atom
   std::vector<int32_t> order;          // sorted position -> input atom
   std::vector<int32_t> tile_start;     // [ns * tiles + 1]
@@ -52,6 +53,7 @@ struct Footprint {
 tacaw_status validate_desc(const tacaw_job_desc* d);
 int choose_frame_batch(const tacaw_job_desc* d);
 bool splat_per_slice();
+bool overlap_splat();
 Footprint footprint_of(const tacaw_job_desc* d, int fb, size_t n_tile_atoms_estimate);
 double wavelength_A(double volt);
 double sigma_rad_per_VA(double volt);
@@ -137,6 +139,9 @@ struct tacaw_job {
   std::vector<tacaw::AtomPos> enc;   // encoded positions, kept until the device copy exists
   bool materialized = false;
   hipStream_t last_stream = nullptr;
+  // side stream and events of the overlapped potential pipeline
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_splat[2] = {nullptr, nullptr}, ev_row[2] = {nullptr, nullptr};
   bool has_result = false;
   // HIP-graph replay of the whole launch sequence (TACAW_USE_GRAPH)
   hipStream_t capture_stream = nullptr;

@@ -183,3 +183,44 @@ def test_c2_shape_register_row_kernel(tacaw, ctx, oracle, monkeypatch):
     monkeypatch.setenv("TACAW_FB", "3")
     job = w.c2_plain(n_frames=8)
     check_job(tacaw, ctx, oracle, job)
+
+
+@pytest.mark.parametrize("fb", ["5", "64"])
+def test_overlapped_potentials_bitwise(tacaw, ctx, monkeypatch, fb):
+    # potentials built one slice ahead on a side stream give bitwise the same
+    # result as building each right before its row pass (ragged batches too)
+    monkeypatch.setenv("TACAW_FB", fb)
+    monkeypatch.setenv("TACAW_OVERLAP", "1")
+    job = w.c1_tiny(n_frames=24)
+    ex_a, sp_a, _ = run_gpu(tacaw, ctx, job)
+    monkeypatch.setenv("TACAW_OVERLAP", "0")
+    ex_b, sp_b, _ = run_gpu(tacaw, ctx, job)
+    assert np.array_equal(ex_a.view(np.uint32), ex_b.view(np.uint32))
+    assert np.array_equal(sp_a.view(np.uint32), sp_b.view(np.uint32))
+
+
+def test_overlapped_potentials_graph_replay(tacaw, ctx, monkeypatch):
+    # the side stream's launches are captured with the job's graph; replays
+    # with eager work in between match the eager run
+    import torch
+    monkeypatch.setenv("TACAW_FB", "6")
+    monkeypatch.setenv("TACAW_OVERLAP", "1")
+    job = w.c1_tiny(n_frames=20)
+    _, ref, _ = run_gpu(tacaw, ctx, job)
+    with tacaw.TacawJob(ctx, job, use_graph=True) as j:
+        for i in range(3):
+            j.run()
+            torch.cuda.synchronize()
+            got = j.spectrum()
+            assert np.array_equal(got.view(np.uint32), ref.view(np.uint32)), f"replay {i}"
+            x = torch.randn(1 << 20, device="cuda")
+            (x * 2).sum().item()
+
+
+@pytest.mark.parametrize("variant", ["2", "3"])
+def test_c2_shape_register_column_kernels(tacaw, ctx, oracle, monkeypatch, variant):
+    # register radix-8 column pass on 8-column (2) and 16-column (3) tiles
+    monkeypatch.setenv("TACAW_COL_VARIANT", variant)
+    monkeypatch.setenv("TACAW_FB", "3")
+    job = w.c2_plain(n_frames=5)
+    check_job(tacaw, ctx, oracle, job)
