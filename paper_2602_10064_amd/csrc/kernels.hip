@@ -276,38 +276,29 @@ __global__ void __launch_bounds__(256) k_splat(SplatTable tab) {
       }
       wave_lds_sync();  // the previous round's MFMA reads are done
       if (pr < mp) {
-        if (!along_y) {
-          const float e2 = c[1], rc = c[3];
-          int o = tx0 - p.ix;
-          if (o >= a.pnx - a.pnx / 2) o -= a.pnx;
-          if (o < -(a.pnx / 2)) o += a.pnx;
-          if (simple_x) {
-            // node x sits at d = x - u pixels from the atom, u = fx - o
-            const float u = p.fx - (float)o;
+        // lanes 0-31 and 32-63 run the same instructions on their own axis
+        // (column profile: unit amplitude; row profile: the term's amplitude)
+        const int n_ax = along_y ? a.pny : a.pnx;
+        const int node0 = along_y ? ty0 : tx0;
+        const int ip = along_y ? p.iy : p.ix;
+        const float fp = along_y ? p.fy : p.fx;
+        const float amp = along_y ? c[0] : 1.f;
+        const float e2 = along_y ? c[2] : c[1];
+        const float rc = along_y ? c[4] : c[3];
+        if (along_y ? simple_y : simple_x) {
+          int o = node0 - ip;
+          if (o >= n_ax - n_ax / 2) o -= n_ax;
+          if (o < -(n_ax / 2)) o += n_ax;
+          // node j sits at d = j - u pixels from the atom, u = f - o
+          const float u = fp - (float)o;
 #pragma unroll
-            for (int x = 0; x < SPLAT_TX; ++x) {
-              const float d = (float)x - u;
-              dst[x] = fabsf(d) <= rc ? __builtin_amdgcn_exp2f(-e2 * d * d) : 0.f;
-            }
-          } else {
-            for (int x = 0; x < SPLAT_TX; ++x) dst[x] = profile(tx0 + x, p.ix, p.fx, a.pnx, e2, rc, a.img_x);
+          for (int x = 0; x < SPLAT_TX; ++x) {
+            const float d = (float)x - u;
+            dst[x] = fabsf(d) <= rc ? amp * __builtin_amdgcn_exp2f(-e2 * d * d) : 0.f;
           }
         } else {
-          const float amp = c[0], e2 = c[2], rc = c[4];
-          int o = ty0 - p.iy;
-          if (o >= a.pny - a.pny / 2) o -= a.pny;
-          if (o < -(a.pny / 2)) o += a.pny;
-          if (simple_y) {
-            const float u = p.fy - (float)o;
-#pragma unroll
-            for (int y = 0; y < SPLAT_TY; ++y) {
-              const float d = (float)y - u;
-              dst[y] = fabsf(d) <= rc ? amp * __builtin_amdgcn_exp2f(-e2 * d * d) : 0.f;
-            }
-          } else {
-            for (int y = 0; y < SPLAT_TY; ++y)
-              dst[y] = amp * profile(ty0 + y, p.iy, p.fy, a.pny, e2, rc, a.img_y);
-          }
+          const int img = along_y ? a.img_y : a.img_x;
+          for (int x = 0; x < SPLAT_TX; ++x) dst[x] = amp * profile(node0 + x, ip, fp, n_ax, e2, rc, img);
         }
       } else if (pr < mp4) {
 #pragma unroll
@@ -375,16 +366,17 @@ __global__ void __launch_bounds__((RowCfg<N, VAR>::THREADS)) k_row(PassTable tab
   const int t = threadIdx.x % G;
   float2* buf = rows[g];
 
-  const long total = (long)a.n_probes * a.fb * a.ny;
-  const long rid = (long)lb * RPI + g;
+  // row ids are below 2^31 (checked at launch)
+  const int total = a.n_probes * a.fb * a.ny;
+  const int rid = lb * RPI + g;
   const bool active = rid < total;
   int p = 0, fl = 0, y = 0;
   float2* row = nullptr;
   if (active) {
-    const long w = rid / a.ny;
-    y = (int)(rid % a.ny);
-    p = (int)(w / a.fb);
-    fl = (int)(w % a.fb);
+    const int w = rid / a.ny;
+    y = rid - w * a.ny;
+    p = w / a.fb;
+    fl = w - p * a.fb;
     row = a.exit + (((size_t)p * a.n_frames + a.f0 + fl) * a.ny + y) * (size_t)N;
   }
 
@@ -482,9 +474,11 @@ __global__ void __launch_bounds__(256) k_row_r8(PassTable tab, int blocks_per_la
   const PassArgs& a = tab.l[L].a;
   const int mode = tab.l[L].mode;
   const int lb = blockIdx.x % blocks_per_lane;
-  const int wave = threadIdx.x / 64;
+  // wavefront-uniform: with one row per wavefront the row bookkeeping below
+  // runs on the scalar unit
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
   const int lane = threadIdx.x % 64;
-  const int sub = lane / G;   // row within the wavefront
+  const int sub = RPW == 1 ? 0 : lane / G;   // row within the wavefront
   const int t = lane % G;
   float2* lds = scratch[wave][sub];
 
@@ -501,17 +495,21 @@ __global__ void __launch_bounds__(256) k_row_r8(PassTable tab, int blocks_per_la
       P *= 8;
     }
   }
-  const long total = (long)a.n_probes * a.fb * a.ny;
-  const long stride = (long)blocks_per_lane * 4 * RPW;
+  // row ids are below 2^31 (checked at launch)
+  const int total = a.n_probes * a.fb * a.ny;
+  const int stride = blocks_per_lane * 4 * RPW;
   const bool transmit = mode != ROW_INVERSE_ONLY;
 
-  // global reads of one row: the wave values and the potential row values
-  auto fetch = [&](long rid, float2 (&xv)[8], float (&vv)[8]) {
+  // global reads of one row (the wave values and the potential row values);
+  // `out` receives the row's place in the exit store
+  auto fetch = [&](int rid, float2 (&xv)[8], float (&vv)[8], float2*& out) {
     if (rid >= total) return;
-    const long w = rid / a.ny;
-    const int y = (int)(rid % a.ny);
-    const int p = (int)(w / a.fb);
-    const int fl = (int)(w % a.fb);
+    const int w = rid / a.ny;
+    const int y = rid - w * a.ny;
+    const int p = w / a.fb;
+    const int fl = w - p * a.fb;
+    float2* row = a.exit + (((size_t)p * a.n_frames + a.f0 + fl) * a.ny + y) * (size_t)N;
+    out = row;
     if (mode == ROW_FIRST) {
       if (a.plane) {
 #pragma unroll
@@ -522,7 +520,6 @@ __global__ void __launch_bounds__(256) k_row_r8(PassTable tab, int blocks_per_la
         for (int r = 0; r < 8; ++r) xv[r] = src[t + r * G];
       }
     } else {
-      const float2* row = a.exit + (((size_t)p * a.n_frames + a.f0 + fl) * a.ny + y) * (size_t)N;
 #pragma unroll
       for (int r = 0; r < 8; ++r) xv[r] = row[t + r * G];
     }
@@ -549,10 +546,12 @@ __global__ void __launch_bounds__(256) k_row_r8(PassTable tab, int blocks_per_la
     xn[r] = make_float2(0.f, 0.f);
     vn[r] = 0.f;
   }
-  long rid0 = ((long)lb * 4 + wave) * RPW;
-  fetch(rid0 + sub, xn, vn);
+  float2* out_next = nullptr;
+  int rid0 = (lb * 4 + wave) * RPW;
+  fetch(rid0 + sub, xn, vn, out_next);
   for (; rid0 < total; rid0 += stride) {
-    const long rid = rid0 + sub;
+    const int rid = rid0 + sub;
+    float2* out = out_next;
     float2 x[8];
     float v[8];
 #pragma unroll
@@ -560,7 +559,7 @@ __global__ void __launch_bounds__(256) k_row_r8(PassTable tab, int blocks_per_la
       x[r] = xn[r];
       v[r] = vn[r];
     }
-    fetch(rid0 + stride + sub, xn, vn);  // next row's reads overlap this row's arithmetic
+    fetch(rid0 + stride + sub, xn, vn, out_next);  // next row's reads overlap this row's arithmetic
     if (mode != ROW_FIRST) fft_r8<N, true>(x, lds, tw, t);
     if (transmit) {
 #pragma unroll
@@ -568,13 +567,8 @@ __global__ void __launch_bounds__(256) k_row_r8(PassTable tab, int blocks_per_la
       fft_r8<N, false>(x, lds, tw, t);
     }
     if (rid < total) {
-      const long w = rid / a.ny;
-      const int y = (int)(rid % a.ny);
-      const int p = (int)(w / a.fb);
-      const int fl = (int)(w % a.fb);
-      float2* row = a.exit + (((size_t)p * a.n_frames + a.f0 + fl) * a.ny + y) * (size_t)N;
 #pragma unroll
-      for (int r = 0; r < 8; ++r) row[t + r * G] = x[r];
+      for (int r = 0; r < 8; ++r) out[t + r * G] = x[r];
     }
   }
 }
@@ -916,6 +910,7 @@ static hipError_t row_launch(PassTable& t, hipStream_t s) {
   for (int i = 0; i < t.n; ++i) {
     const PassArgs& a = t.l[i].a;
     const long total = (long)a.n_probes * a.fb * a.ny;
+    if (total + RPI >= (1L << 31)) return hipErrorInvalidValue;  // 32-bit row ids
     t.l[i].block_start = blocks;
     blocks += (int)((total + RPI - 1) / RPI);
   }
@@ -952,6 +947,7 @@ static hipError_t row_r8_launch(PassTable& t, hipStream_t s) {
     most = std::max(most, (long)a.n_probes * a.fb * a.ny);
   }
   constexpr int rows_per_block = 4 * R8<N>::RPW;
+  if (most + (long)2048 * rows_per_block >= (1L << 31)) return hipErrorInvalidValue;  // 32-bit row ids
   long bpl = (most + rows_per_block - 1) / rows_per_block;
   bpl = std::min<long>(bpl, std::max<long>(1, 2048 / t.n));
   hipLaunchKernelGGL((k_row_r8<N>), dim3((unsigned)(bpl * t.n)), dim3(256), 0, s, t, (int)bpl);
