@@ -435,12 +435,22 @@ struct R8 {
   static_assert(S > 0 && G <= 64, "uniform radix-8 row pass");
 };
 
+// LDS layout of a row or column in the register kernels: element i sits in
+// slot i + i/8 (one pad slot after every 8 values), so that the radix-8
+// exchanges (stride-8 and stride-64 writes) and the transposes spread over all
+// banks.  padded(n) slots hold n elements.
+constexpr int padded(int n) { return n + n / 8; }
+
 // One FFT on registers: x[r] at positions t + G r in and out.  lds: this
-// row's N-value scratch.  tw[j][r-1]: stage-j twiddles for this lane.
+// row's scratch of padded(N) values.  tw[j][r-1]: stage-j twiddles for this
+// lane.
 template <int N, bool INV>
 __device__ __forceinline__ void fft_r8(float2 (&x)[8], float2* lds, const float2 (&tw)[R8<N>::S][7], int t) {
   constexpr int S = R8<N>::S;
   constexpr int G = R8<N>::G;
+  static_assert(G % 8 == 0, "padded reads assume G divisible by 8");
+  // x[r] lives at position t + G r: padded slot t + t/8 + (G + G/8) r
+  const int rbase = t + (t >> 3);
   int P = 1;
 #pragma unroll
   for (int j = 0; j < S; ++j) {
@@ -450,25 +460,28 @@ __device__ __forceinline__ void fft_r8(float2 (&x)[8], float2* lds, const float2
     }
     dft8<INV>(x);
     if (j < S - 1) {
+      // output r goes to position base + r P, base = 8 (t - t mod P) + t mod P,
+      // a multiple of 8 when P = 1: padded slot base + base/8 + (P + P/8) r
       const int k = t % P;
       const int base = (t - k) * 8 + k;
+      const int wbase = base + (base >> 3);
       wave_lds_sync();  // earlier reads of lds by this wavefront are done
 #pragma unroll
-      for (int r = 0; r < 8; ++r) lds[base + r * P] = x[r];
+      for (int r = 0; r < 8; ++r) lds[wbase + r * (P + P / 8)] = x[r];
       wave_lds_sync();
 #pragma unroll
-      for (int r = 0; r < 8; ++r) x[r] = lds[t + r * G];
+      for (int r = 0; r < 8; ++r) x[r] = lds[rbase + r * (G + G / 8)];
     }
     P *= 8;
   }
 }
 
 template <int N>
-__global__ void __launch_bounds__(256) k_row_r8(PassTable tab, int blocks_per_lane) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k_row_r8(PassTable tab, int blocks_per_lane) {
   constexpr int G = R8<N>::G;
   constexpr int RPW = R8<N>::RPW;
   constexpr int S = R8<N>::S;
-  __shared__ float2 scratch[4][RPW][N];
+  __shared__ float2 scratch[4][RPW][padded(N)];
 
   const int L = blockIdx.x / blocks_per_lane;
   const PassArgs& a = tab.l[L].a;
@@ -647,7 +660,9 @@ struct C8 {
   static constexpr int CPW = 64 / G;            // columns per wavefront
   static constexpr int WAVES = (N == 512 ? 8 : 4) * (WIDE ? 2 : 1);
   static constexpr int CT = WAVES * CPW;        // columns per block
-  static constexpr int LD = N + 2;
+  // padded column stride: 2 LD = 16 (mod 32) dwords puts the 8 columns that
+  // one transpose instruction touches on disjoint bank halves
+  static constexpr int LD = padded(N) + (N == 512 ? 8 : 0);
   static constexpr int THREADS = WAVES * 64;
 };
 
@@ -666,6 +681,13 @@ __global__ void __launch_bounds__((C8<N, WIDE>::THREADS)) k_col_r8(PassTable tab
   const int cl = wave * CPW + lane / G;  // this lane's column in the tile
   const int t = lane % G;
   float2* lds = cols + cl * LD;
+  // padded LDS slots: this lane's FFT values (t + G r) and its transpose
+  // element (column e mod CT, row e / CT, e = threadIdx.x + q THREADS; the
+  // row step THREADS / CT is a multiple of 8)
+  static_assert((THREADS / CT) % 8 == 0 && G % 8 == 0, "padded slots");
+  const int rslot = t + (t >> 3);
+  const int trow = threadIdx.x / CT;
+  const int tslot = (threadIdx.x % CT) * LD + trow + (trow >> 3);
 
   // stage twiddles of the y transform (every lane of the table has this ny)
   float2 tw[S][7];
@@ -714,10 +736,7 @@ __global__ void __launch_bounds__((C8<N, WIDE>::THREADS)) k_col_r8(PassTable tab
     float2* cur_wp = wp;
     __syncthreads();  // the previous tile's stores from LDS are done
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int e = threadIdx.x + q * THREADS;
-      cols[(e % CT) * LD + e / CT] = pre[q];
-    }
+    for (int q = 0; q < PER; ++q) cols[tslot + q * (THREADS / CT + THREADS / CT / 8)] = pre[q];
     // issue the next tile's loads; they complete during this tile's arithmetic
     const int nit = it + gridDim.x;
     if (nit < total_tiles) {
@@ -732,7 +751,7 @@ __global__ void __launch_bounds__((C8<N, WIDE>::THREADS)) k_col_r8(PassTable tab
     __syncthreads();
     float2 x[8];
 #pragma unroll
-    for (int r = 0; r < 8; ++r) x[r] = lds[t + r * G];
+    for (int r = 0; r < 8; ++r) x[r] = lds[rslot + r * (G + G / 8)];
     if (mode == COL_INVERSE_ONLY) {
       fft_r8<N, true>(x, lds, tw, t);
     } else {
@@ -744,12 +763,12 @@ __global__ void __launch_bounds__((C8<N, WIDE>::THREADS)) k_col_r8(PassTable tab
     }
     wave_lds_sync();
 #pragma unroll
-    for (int r = 0; r < 8; ++r) lds[t + r * G] = x[r];
+    for (int r = 0; r < 8; ++r) lds[rslot + r * (G + G / 8)] = x[r];
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int e = threadIdx.x + q * THREADS;
-      cur_wp[(size_t)(e / CT) * a.nx + cur_x0 + e % CT] = cols[(e % CT) * LD + e / CT];
+      cur_wp[(size_t)(e / CT) * a.nx + cur_x0 + e % CT] = cols[tslot + q * (THREADS / CT + THREADS / CT / 8)];
     }
   }
 }
