@@ -197,18 +197,18 @@ static SplatArgs splat_args_of(tacaw_job* job, int f0, int fb) {
 }
 
 // Row pass then column pass of one slice for frames [f0, f0 + fb); the
-// potential of that slice is read from V (one slice, or all slices of the
-// batch when v_all).  after_row, if given, is recorded once the row pass (the
-// potential's only reader) is queued.
-static tacaw_status slice_passes(tacaw_job* job, hipStream_t s, int f0, int fb, int sl, float* V, bool v_all,
-                                 hipEvent_t after_row = nullptr) {
+// potential of that slice is read from V, which holds slices v_slice0 ..
+// v_slice0 + v_slices - 1 of each frame.  after_row, if given, is recorded
+// once the row pass (the potential's only reader) is queued.
+static tacaw_status slice_passes(tacaw_job* job, hipStream_t s, int f0, int fb, int sl, float* V, int v_slices,
+                                 int v_slice0, hipEvent_t after_row = nullptr) {
   const HostPlan& hp = job->hp;
   PassArgs a = pass_args(job);
   a.f0 = f0;
   a.fb = fb;
   a.V = V;
-  a.v_slices = v_all ? hp.ns : 1;
-  a.v_slice0 = v_all ? 0 : sl;
+  a.v_slices = v_slices;
+  a.v_slice0 = v_slice0;
   a.slice = sl;
   PassLane rl{};
   rl.a = a;
@@ -240,26 +240,20 @@ static tacaw_status slice_passes(tacaw_job* job, hipStream_t s, int f0, int fb, 
 // (and a capture of s takes in the side stream's work).
 tacaw_status run_batch_range(tacaw_job* job, hipStream_t s, int f_begin, int f_end) {
   const HostPlan& hp = job->hp;
-  if (!hp.splat_per_slice) {
-    for (int f0 = f_begin; f0 < f_end; f0 += hp.fb) {
-      const int fb = std::min(hp.fb, f_end - f0);
-      SplatArgs sa = splat_args_of(job, f0, fb);
-      tacaw_status st = timed(job, TACAW_K_SPLAT, s, [&] { return launch_splat(sa, hp.ns, s); });
-      if (st != TACAW_OK) return st;
-      for (int sl = 0; sl < hp.ns; ++sl)
-        if ((st = slice_passes(job, s, f0, fb, sl, job->d_V, true)) != TACAW_OK) return st;
-    }
-    return TACAW_OK;
-  }
   if (!hp.overlap) {
+    // serial form: potentials of hp.splat_group slices (all slices when not
+    // per slice), then their row and column passes
+    const int G = hp.splat_group;
     for (int f0 = f_begin; f0 < f_end; f0 += hp.fb) {
       const int fb = std::min(hp.fb, f_end - f0);
-      for (int sl = 0; sl < hp.ns; ++sl) {
+      for (int g0 = 0; g0 < hp.ns; g0 += G) {
+        const int gn = std::min(G, hp.ns - g0);
         SplatArgs sa = splat_args_of(job, f0, fb);
-        sa.slice0 = sl;
-        tacaw_status st = timed(job, TACAW_K_SPLAT, s, [&] { return launch_splat(sa, 1, s); });
+        sa.slice0 = g0;
+        tacaw_status st = timed(job, TACAW_K_SPLAT, s, [&] { return launch_splat(sa, gn, s); });
         if (st != TACAW_OK) return st;
-        if ((st = slice_passes(job, s, f0, fb, sl, job->d_V, false)) != TACAW_OK) return st;
+        for (int sl = g0; sl < g0 + gn; ++sl)
+          if ((st = slice_passes(job, s, f0, fb, sl, job->d_V, gn, g0)) != TACAW_OK) return st;
       }
     }
     return TACAW_OK;
@@ -288,7 +282,8 @@ tacaw_status run_batch_range(tacaw_job* job, hipStream_t s, int f_begin, int f_e
     if (k + 1 < n_steps && (st = splat_step(k + 1)) != TACAW_OK) break;
     HIP_TRY(hipStreamWaitEvent(s, job->ev_splat[k & 1], 0));
     const int f0 = step_f0(k), fb = std::min(hp.fb, f_end - f0);
-    st = slice_passes(job, s, f0, fb, (int)(k % hp.ns), job->d_V + (k & 1) * slab, false, job->ev_row[k & 1]);
+    const int sl = (int)(k % hp.ns);
+    st = slice_passes(job, s, f0, fb, sl, job->d_V + (k & 1) * slab, 1, sl, job->ev_row[k & 1]);
   }
   if (st != TACAW_OK) {
     // join the side stream so nothing it holds outlives an error return
@@ -331,7 +326,7 @@ tacaw_status materialize(tacaw_job* j, hipStream_t s0) {
   if ((e = dalloc(&(ptr), (count))) != hipSuccess) return fail("hipMalloc " #ptr, e);
   if (!j->d_exit) ALLOC(j->d_exit, (size_t)hp.P * hp.F * nk);
   if (!j->d_spec) ALLOC(j->d_spec, (size_t)hp.P * hp.M * nk);
-  ALLOC(j->d_V, (size_t)hp.fb * (hp.splat_per_slice ? (hp.overlap ? 2 : 1) : hp.ns) * hp.pnx * hp.pny);
+  ALLOC(j->d_V, (size_t)hp.fb * (hp.overlap ? 2 : hp.splat_group) * hp.pnx * hp.pny);
   ALLOC(j->d_pos, (size_t)hp.F * hp.A);
   ALLOC(j->d_species, (size_t)hp.A);
   ALLOC(j->d_tile_start, hp.tile_start.size());

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 
 #include "fft_engine.h"
 #include "tacaw_internal.h"
@@ -190,7 +191,6 @@ __device__ __forceinline__ float profile_tile(int o, int j, float f, float e2, f
 __global__ void __launch_bounds__(256) k_splat(SplatTable tab) {
   constexpr int MP = 32;          // pairs per round: one row profile and one column profile per lane
   constexpr int PAD = SPLAT_TX + 1;
-  constexpr int FPW = SPLAT_FPW;  // frames per wavefront
   static_assert(SPLAT_TX == 32 && SPLAT_TY == 32, "MFMA tiling assumes 32 x 32 tiles");
   __shared__ float gxs[4][MP][PAD];
   __shared__ float gys[4][MP][PAD];
@@ -209,6 +209,7 @@ __global__ void __launch_bounds__(256) k_splat(SplatTable tab) {
   __syncthreads();  // the only workgroup barrier: everything below is per wavefront
   const float* coef = coef_in_lds ? coef_s : a.coef;
   const int n_tiles = a.tiles_x * a.tiles_y;
+  const int FPW = tab.l[L].fpw;  // frames per wavefront
   const int n_fg = (a.fb + FPW - 1) / FPW;
   const int item = (blockIdx.x - tab.l[L].block_start) * 4 + wave;
   if (item >= n_tiles * nsl * n_fg) return;
@@ -1051,12 +1052,18 @@ hipError_t launch_splat_lanes(const SplatLane* lanes, int n, hipStream_t s) {
   SplatTable t{};
   t.n = n;
   int blocks = 0;
+  static const int fpw_env = [] {
+    const char* e = getenv("TACAW_SPLAT_FPW");
+    const int v = e ? atoi(e) : 0;
+    return v >= 1 && v <= 64 ? v : SPLAT_FPW;
+  }();
   for (int i = 0; i < n; ++i) {
     t.l[i] = lanes[i];
     t.l[i].block_start = blocks;
+    t.l[i].fpw = fpw_env;
     const SplatArgs& a = lanes[i].a;
     const int items = a.tiles_x * a.tiles_y * lanes[i].n_slices_launch *
-                      ((a.fb + SPLAT_FPW - 1) / SPLAT_FPW);  // one per wavefront
+                      ((a.fb + fpw_env - 1) / fpw_env);  // one per wavefront
     blocks += (items + 3) / 4;
   }
   hipLaunchKernelGGL(k_splat, dim3(blocks), dim3(256), 0, s, t);

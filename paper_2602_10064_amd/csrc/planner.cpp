@@ -169,9 +169,22 @@ bool overlap_splat() {
   return splat_per_slice() && e && atoi(e) != 0;
 }
 
-// Frames per batch: the waves and potentials of one batch should stay within
-// ~192 MiB, so that between the row and column passes of a slice they can
-// live in the 256 MiB last-level cache.  TACAW_FB overrides the choice and
+// Slices whose potentials one launch builds in the serial form
+// (TACAW_SPLAT_GROUP, default 4: fewer, larger potential launches; measured
+// faster than one slice per launch at 512^2 even though the row pass then
+// reads potentials written further back); the overlapped form builds one at a
+// time.
+int splat_group(int n_slices) {
+  if (!splat_per_slice()) return n_slices;
+  if (overlap_splat()) return 1;
+  const char* e = getenv("TACAW_SPLAT_GROUP");
+  const int g = e ? atoi(e) : 4;
+  return std::max(1, std::min(g, n_slices));
+}
+
+// Frames per batch: the waves and one slice of potentials of one batch should
+// stay within ~192 MiB, so that between the row and column passes of a slice
+// they can live in the 256 MiB last-level cache.  TACAW_FB overrides the choice and
 // TACAW_BATCH_MB the target.
 int choose_frame_batch(const tacaw_job_desc* d) {
   if (const char* e = getenv("TACAW_FB")) {
@@ -181,8 +194,7 @@ int choose_frame_batch(const tacaw_job_desc* d) {
   const int pnx = d->pot_nx > 0 ? d->pot_nx : d->nx;
   const int pny = d->pot_ny > 0 ? d->pot_ny : d->ny;
   const double P = d->aperture_mrad == 0.0 ? 1.0 : (double)d->n_probes;
-  const double v_slices = splat_per_slice() ? 1.0 : (double)d->n_slices;
-  const double per_frame = P * d->nx * d->ny * 8.0 + v_slices * pnx * pny * 4.0;
+  const double per_frame = P * d->nx * d->ny * 8.0 + pnx * pny * 4.0;
   double target = 192.0 * (1 << 20);
   if (const char* e = getenv("TACAW_BATCH_MB")) target = atof(e) * (1 << 20);
   const int fb = (int)std::max(1.0, floor(target / per_frame));
@@ -199,7 +211,7 @@ Footprint footprint_of(const tacaw_job_desc* d, int fb, size_t n_tile_atoms) {
   const size_t M = (d->flags & TACAW_TWO_SIDED) ? d->n_frames : d->n_frames / 2;
   f.exit = P * d->n_frames * nk * sizeof(float2);
   f.spec = P * M * nk * sizeof(float);
-  f.V = (size_t)fb * (splat_per_slice() ? (overlap_splat() ? 2 : 1) : d->n_slices) * pnx * pny * sizeof(float);
+  f.V = (size_t)fb * (overlap_splat() ? 2 : splat_group(d->n_slices)) * pnx * pny * sizeof(float);
   f.pos = (size_t)d->n_frames * d->n_atoms * sizeof(AtomPos) + (size_t)d->n_atoms * sizeof(int32_t);
   f.tiles = n_tile_atoms * sizeof(int32_t);
   f.probes = plane ? 0 : P * nk * sizeof(float2) + P * (2 * sizeof(int32_t) + 2 * sizeof(double));
@@ -237,6 +249,7 @@ tacaw_status plan_job(const tacaw_job_desc* d, const int32_t* atom_species, cons
   hp.fb = choose_frame_batch(d);
   hp.splat_per_slice = splat_per_slice();
   hp.overlap = overlap_splat();
+  hp.splat_group = splat_group(d->n_slices);
 
   for (int j = 0; j < hp.A; ++j)
     if (atom_species[j] < 0 || atom_species[j] >= hp.S) {

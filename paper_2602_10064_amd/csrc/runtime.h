@@ -34,6 +34,7 @@ struct HostPlan {
   int fb = 1;                          // frames per batch
   bool splat_per_slice = true;         // potentials built slice by slice
   bool overlap = true;                 // per-slice potentials built one slice ahead on a side stream
+  int splat_group = 1;                 // slices per potential launch (all slices when !splat_per_slice)
   std::vector<int32_t> slice_of;       // per input atom
   std::vector<int32_t> order;          // sorted position -> input atom
   std::vector<int32_t> tile_start;     // [ns * tiles + 1]
@@ -54,6 +55,7 @@ tacaw_status validate_desc(const tacaw_job_desc* d);
 int choose_frame_batch(const tacaw_job_desc* d);
 bool splat_per_slice();
 bool overlap_splat();
+int splat_group(int n_slices);
 Footprint footprint_of(const tacaw_job_desc* d, int fb, size_t n_tile_atoms_estimate);
 double wavelength_A(double volt);
 double sigma_rad_per_VA(double volt);

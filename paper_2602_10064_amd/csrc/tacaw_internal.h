@@ -19,7 +19,7 @@ constexpr int SPLAT_TX = 32;   // splat tile: columns
 constexpr int SPLAT_TY = 32;   // splat tile: rows
 constexpr int COEF_STRIDE = 5; // per (species, term): amplitude, exp2 x, exp2 y, cutoff x, cutoff y
 constexpr int SPLAT_MC = 64;   // candidate (atom, term) pairs staged in LDS per round
-constexpr int SPLAT_FPW = 4;   // frames per splat wavefront (candidate lists are frame independent)
+constexpr int SPLAT_FPW = 4;   // default frames per splat wavefront (candidate lists are frame independent)
 constexpr int SPLAT_MAX_SPECIES = 16;  // species whose coefficients are staged in LDS
 constexpr int COL_CT = 16;     // columns per column-pass workgroup (128-byte rows)
 
@@ -76,6 +76,7 @@ struct SplatLane {
   SplatArgs a;
   int n_slices_launch;  // slices slice0 .. slice0 + n - 1 of frames f0 .. f0 + fb - 1
   int block_start;      // set by the launcher
+  int fpw;              // frames per wavefront, set by the launcher
 };
 struct SplatTable {
   int n;

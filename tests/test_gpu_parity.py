@@ -224,3 +224,13 @@ def test_c2_shape_register_column_kernels(tacaw, ctx, oracle, monkeypatch, varia
     monkeypatch.setenv("TACAW_FB", "3")
     job = w.c2_plain(n_frames=5)
     check_job(tacaw, ctx, oracle, job)
+
+
+def test_splat_slice_groups_bitwise(tacaw, ctx, monkeypatch):
+    # potentials of several slices per launch (8 slices in groups of 3: 3+3+2)
+    job = w.c1_tiny(n_frames=16)
+    _, a, _ = run_gpu(tacaw, ctx, job)
+    monkeypatch.setenv("TACAW_SPLAT_GROUP", "3")
+    monkeypatch.setenv("TACAW_FB", "6")
+    _, b, _ = run_gpu(tacaw, ctx, job)
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
