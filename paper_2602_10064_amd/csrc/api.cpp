@@ -98,20 +98,22 @@ void drain_records(tacaw_ctx* c) {
 namespace tacaw {
 
 // Tile variant of the row pass (0: base rows per block, 1: doubled, 2: the
-// register radix-8 kernel for 64 and 512) and of the column pass (0: half
-// width, 1: full width).  Tuned choices win; $TACAW_ROW_VARIANT and
-// $TACAW_COL_VARIANT override untuned defaults.
+// register kernel for 64, 128, 256 and 512) and of the column pass (0: half
+// width, 1: full width, 2: register kernel on 8-16 column tiles for 64-512
+// rows, 3: 16-column register tiles for 512 rows).  Tuned choices win;
+// $TACAW_ROW_VARIANT and $TACAW_COL_VARIANT override untuned defaults.
+static bool has_register_fft(int n) { return n == 64 || n == 128 || n == 256 || n == 512; }
 int row_variant_for(tacaw_ctx* c, int n) {
   const int v = (n > 0 && n < 2048) ? c->row_variant[n] : 0;
   if (v) return v - 1;
   if (const char* e = getenv("TACAW_ROW_VARIANT")) return atoi(e);
-  return (n == 512 || n == 64) ? 2 : 1;
+  return has_register_fft(n) ? 2 : 1;
 }
 int col_variant_for(tacaw_ctx* c, int n) {
   const int v = (n > 0 && n < 2048) ? c->col_variant[n] : 0;
   if (v) return v - 1;
   if (const char* e = getenv("TACAW_COL_VARIANT")) return atoi(e);
-  return (n == 512 || n == 64) ? 2 : 0;
+  return has_register_fft(n) ? 2 : 0;
 }
 
 // Launch wrapper: brackets the launch with events on its stream when timing.

@@ -258,11 +258,12 @@ tacaw_status tacaw_autotune(tacaw_job* job, void* hip_stream, int* row_variant, 
   hipStream_t s = (hipStream_t)hip_stream;
   const HostPlan& hp = job->hp;
   const int fb = std::min(hp.fb, hp.F);
-  // row variants: 0, 1 (LDS rows), 2 (register radix-8, grids 64 and 512);
-  // column variants: 0, 1 (LDS columns), 2 (register radix-8 on 8-column
-  // tiles, ny 64 and 512), 3 (16-column tiles, ny 512)
-  const int n_row_var = (hp.nx == 512 || hp.nx == 64) ? 3 : 2;
-  const int n_col_var = hp.ny == 512 ? 4 : hp.ny == 64 ? 3 : 2;
+  // row variants: 0, 1 (LDS rows), 2 (register FFT, grids 64-512);
+  // column variants: 0, 1 (LDS columns), 2 (register FFT on 8-32 column
+  // tiles, ny 64-512), 3 (16-column tiles, ny 512)
+  auto reg = [](int n) { return n == 64 || n == 128 || n == 256 || n == 512; };
+  const int n_row_var = reg(hp.nx) ? 3 : 2;
+  const int n_col_var = hp.ny == 512 ? 4 : reg(hp.ny) ? 3 : 2;
   const int n_var = std::max(n_row_var, n_col_var);
   double best_row[4] = {1e30, 1e30, 1e30, 1e30}, best_col[4] = {1e30, 1e30, 1e30, 1e30};
   const bool was_timing = c->timing;

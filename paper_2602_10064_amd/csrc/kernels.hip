@@ -420,8 +420,9 @@ __global__ void __launch_bounds__((RowCfg<N, VAR>::THREADS)) k_row(PassTable tab
 }
 
 // ---------------------------------------------------------------------------
-// Row pass, uniform radix 8 (N = 8^S): one row per G = N/8 lanes inside one
-// wavefront; lane t keeps the row values at x = t + G r (r < 8) in registers,
+// Row pass on registers (N = 64, 128, 256, 512; radix-8 stages, then radix 4
+// where N needs it): one row per G = N/8 lanes inside one wavefront; lane t
+// keeps the row values at x = t + G r (r < 8) in registers,
 // which is both the first Stockham stage's input layout and the last stage's
 // output layout, so global loads and stores are coalesced and only S-1 LDS
 // exchanges per FFT remain, synchronised within the wavefront only.  Each
@@ -430,51 +431,99 @@ __global__ void __launch_bounds__((RowCfg<N, VAR>::THREADS)) k_row(PassTable tab
 // ---------------------------------------------------------------------------
 template <int N>
 struct R8 {
-  static constexpr int S = N == 8 ? 1 : N == 64 ? 2 : N == 512 ? 3 : N == 4096 ? 4 : 0;
+  // stage radices, radix 8 first (so every later stage stride is a multiple
+  // of 8); each divides the 8 values a lane holds
+  static constexpr int S = N == 64 ? 2 : (N == 128 || N == 256 || N == 512) ? 3 : 0;
+  static constexpr int radix(int j) {
+    return j == 0 ? 8 : N == 128 ? 4 : (N == 256 && j == 2) ? 4 : 8;
+  }
+  static constexpr int stride(int j) { return j == 0 ? 1 : stride(j - 1) * radix(j - 1); }
   static constexpr int G = N / 8;            // lanes per row
   static constexpr int RPW = 64 / G;         // rows per wavefront
-  static_assert(S > 0 && G <= 64, "uniform radix-8 row pass");
+  static_assert(S > 0 && G <= 64 && G % 8 == 0, "register FFT sizes: 64, 128, 256, 512");
+  static_assert(S < 1 || stride(S - 1) * radix(S - 1) == N, "radices multiply to N");
 };
 
 // LDS layout of a row or column in the register kernels: element i sits in
-// slot i + i/8 (one pad slot after every 8 values), so that the radix-8
-// exchanges (stride-8 and stride-64 writes) and the transposes spread over all
-// banks.  padded(n) slots hold n elements.
+// slot i + i/8 (one pad slot after every 8 values), so that the exchanges
+// (stride-8 and stride-64 writes) and the transposes spread over all banks.
+// padded(n) slots hold n elements.
 constexpr int padded(int n) { return n + n / 8; }
 
+// Stage twiddles of one lane: stage j with radix R and stride P runs Q = 8/R
+// butterflies b = t + G q; input r of butterfly q takes W_{PR}^{r (b mod P)},
+// stored at tw[j][q (R - 1) + r - 1].  Stage 0 (P = 1) has none.
+template <int N>
+__device__ __forceinline__ void reg_twiddles(float2 (&tw)[R8<N>::S][7], const float2* table, int t) {
+  int P = R8<N>::radix(0);
+#pragma unroll
+  for (int j = 1; j < R8<N>::S; P *= R8<N>::radix(j), ++j) {
+    const int R = R8<N>::radix(j), Q = 8 / R;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int k = (t + R8<N>::G * q) % P;
+#pragma unroll
+      for (int r = 1; r < R; ++r) tw[j][q * (R - 1) + r - 1] = table[(r * k * (N / (P * R))) % N];
+    }
+  }
+}
+
+// Stage J of the register FFT and the stages after it.  x[r'] holds position
+// t + G r'; butterfly q of a radix-R stage takes x[q + Q r], r < R, which sit
+// at b + r N/R.  Outputs go to positions (b - k) R + k + r P, k = b mod P,
+// through LDS, except after the last stage, where they already sit at
+// t + G (q + Q r).
+template <int N, bool INV, int J>
+__device__ __forceinline__ void reg_fft_stage(float2 (&x)[8], float2* lds, const float2 (&tw)[R8<N>::S][7],
+                                              int t) {
+  constexpr int S = R8<N>::S, G = R8<N>::G;
+  constexpr int R = R8<N>::radix(J), P = R8<N>::stride(J), Q = 8 / R;
+  if constexpr (J > 0) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        const float2 w = tw[J][q * (R - 1) + r - 1];
+        x[q + Q * r] = INV ? cmulc(x[q + Q * r], w) : cmul(x[q + Q * r], w);
+      }
+  }
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    float2 y[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) y[r] = x[q + Q * r];
+    dft<R, INV>(y);
+#pragma unroll
+    for (int r = 0; r < R; ++r) x[q + Q * r] = y[r];
+  }
+  if constexpr (J < S - 1) {
+    static_assert(P == 1 ? R == 8 : P % 8 == 0, "padded write offsets");
+    wave_lds_sync();  // earlier reads of lds by this wavefront are done
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      // base is a multiple of 8 when P = 1, and P is a multiple of 8 otherwise:
+      // slot of base + r P is base + base/8 + (P + P/8) r
+      const int b = t + G * q;
+      const int k = b % P;
+      const int base = (b - k) * R + k;
+      const int wbase = base + (base >> 3);
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds[wbase + r * (P + P / 8)] = x[q + Q * r];
+    }
+    wave_lds_sync();
+    // x[r'] from position t + G r': slot t + t/8 + (G + G/8) r'
+    const int rbase = t + (t >> 3);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) x[r] = lds[rbase + r * (G + G / 8)];
+    reg_fft_stage<N, INV, J + 1>(x, lds, tw, t);
+  }
+}
+
 // One FFT on registers: x[r] at positions t + G r in and out.  lds: this
-// row's scratch of padded(N) values.  tw[j][r-1]: stage-j twiddles for this
-// lane.
+// row's scratch of padded(N) values.
 template <int N, bool INV>
 __device__ __forceinline__ void fft_r8(float2 (&x)[8], float2* lds, const float2 (&tw)[R8<N>::S][7], int t) {
-  constexpr int S = R8<N>::S;
-  constexpr int G = R8<N>::G;
-  static_assert(G % 8 == 0, "padded reads assume G divisible by 8");
-  // x[r] lives at position t + G r: padded slot t + t/8 + (G + G/8) r
-  const int rbase = t + (t >> 3);
-  int P = 1;
-#pragma unroll
-  for (int j = 0; j < S; ++j) {
-    if (j > 0) {
-#pragma unroll
-      for (int r = 1; r < 8; ++r) x[r] = INV ? cmulc(x[r], tw[j][r - 1]) : cmul(x[r], tw[j][r - 1]);
-    }
-    dft8<INV>(x);
-    if (j < S - 1) {
-      // output r goes to position base + r P, base = 8 (t - t mod P) + t mod P,
-      // a multiple of 8 when P = 1: padded slot base + base/8 + (P + P/8) r
-      const int k = t % P;
-      const int base = (t - k) * 8 + k;
-      const int wbase = base + (base >> 3);
-      wave_lds_sync();  // earlier reads of lds by this wavefront are done
-#pragma unroll
-      for (int r = 0; r < 8; ++r) lds[wbase + r * (P + P / 8)] = x[r];
-      wave_lds_sync();
-#pragma unroll
-      for (int r = 0; r < 8; ++r) x[r] = lds[rbase + r * (G + G / 8)];
-    }
-    P *= 8;
-  }
+  reg_fft_stage<N, INV, 0>(x, lds, tw, t);
 }
 
 template <int N>
@@ -496,19 +545,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k
   const int t = lane % G;
   float2* lds = scratch[wave][sub];
 
-  // stage twiddles W_{8P}^{r (t mod P)} = tw[r (t mod P) N / (8P)]
   float2 tw[S][7];
-  {
-    int P = 1;
-#pragma unroll
-    for (int j = 0; j < S; ++j) {
-      const int k = t % P;
-      const int step = N / (8 * P);
-#pragma unroll
-      for (int r = 1; r < 8; ++r) tw[j][r - 1] = a.tw_x[(r * k * step) % N];
-      P *= 8;
-    }
-  }
+  reg_twiddles<N>(tw, a.tw_x, t);
   // row ids are below 2^31 (checked at launch)
   const int total = a.n_probes * a.fb * a.ny;
   const int stride = blocks_per_lane * 4 * RPW;
@@ -663,7 +701,7 @@ struct C8 {
   static constexpr int CT = WAVES * CPW;        // columns per block
   // padded column stride: 2 LD = 16 (mod 32) dwords puts the 8 columns that
   // one transpose instruction touches on disjoint bank halves
-  static constexpr int LD = padded(N) + (N == 512 ? 8 : 0);
+  static constexpr int LD = padded(N) + (padded(N) % 16 == 8 ? 0 : 8);
   static constexpr int THREADS = WAVES * 64;
 };
 
@@ -692,18 +730,7 @@ __global__ void __launch_bounds__((C8<N, WIDE>::THREADS)) k_col_r8(PassTable tab
 
   // stage twiddles of the y transform (every lane of the table has this ny)
   float2 tw[S][7];
-  {
-    const float2* twy = tab.l[0].a.tw_y;
-    int P = 1;
-#pragma unroll
-    for (int j = 0; j < S; ++j) {
-      const int k = t % P;
-      const int step = N / (8 * P);
-#pragma unroll
-      for (int r = 1; r < 8; ++r) tw[j][r - 1] = twy[(r * k * step) % N];
-      P *= 8;
-    }
-  }
+  reg_twiddles<N>(tw, tab.l[0].a.tw_y, t);
   // tile geometry of a logical tile index
   auto locate = [&](int it, int& L, int& x0, float2*& wp) {
     const int tile_g = xcd_remap(it, total_tiles);
@@ -980,9 +1007,13 @@ hipError_t launch_row_lanes(const PassLane* lanes, int n, int variant, hipStream
   t.n = n;
   for (int i = 0; i < n; ++i) t.l[i] = lanes[i];
   if (variant == 2) {
-    if (lanes[0].a.nx == 512) return row_r8_launch<512>(t, s);
-    if (lanes[0].a.nx == 64) return row_r8_launch<64>(t, s);
-    variant = 1;
+    switch (lanes[0].a.nx) {
+      case 512: return row_r8_launch<512>(t, s);
+      case 256: return row_r8_launch<256>(t, s);
+      case 128: return row_r8_launch<128>(t, s);
+      case 64: return row_r8_launch<64>(t, s);
+      default: variant = 1;
+    }
   }
   switch (lanes[0].a.nx) {
 #define CASE(NN) \
@@ -1019,8 +1050,11 @@ hipError_t launch_col_lanes(const PassLane* lanes, int n, int variant, hipStream
     variant = 2;
   }
   if (variant == 2) {
-    if (lanes[0].a.ny == 512 && lanes[0].a.nx % C8<512, 0>::CT == 0) return col_r8_launch<512, 0>(t, s);
-    if (lanes[0].a.ny == 64 && lanes[0].a.nx % C8<64, 0>::CT == 0) return col_r8_launch<64, 0>(t, s);
+    const int ny = lanes[0].a.ny, nx = lanes[0].a.nx;
+    if (ny == 512 && nx % C8<512, 0>::CT == 0) return col_r8_launch<512, 0>(t, s);
+    if (ny == 256 && nx % C8<256, 0>::CT == 0) return col_r8_launch<256, 0>(t, s);
+    if (ny == 128 && nx % C8<128, 0>::CT == 0) return col_r8_launch<128, 0>(t, s);
+    if (ny == 64 && nx % C8<64, 0>::CT == 0) return col_r8_launch<64, 0>(t, s);
     variant = 0;
   }
   switch (lanes[0].a.ny) {

@@ -102,9 +102,21 @@ def test_autotune_keeps_results(tacaw, tmp_path, monkeypatch):
         h.run()
         before = h.spectrum()
         rv, cv = h.autotune()
-        assert rv in (0, 1) and cv in (0, 1)
+        assert rv in (0, 1, 2) and cv in (0, 1, 2)
         h.run()
-        assert np.array_equal(h.spectrum().view(np.uint32), before.view(np.uint32))
+        after = h.spectrum()
+        if (rv, cv) == (2, 2):      # the untuned default: the same kernels
+            assert np.array_equal(after.view(np.uint32), before.view(np.uint32))
+        else:                       # another FFT tiling: same values up to FP32 rounding
+            err = np.linalg.norm(after - before) / np.linalg.norm(before)
+            assert err < 1e-5, err
         h.destroy()
     text = (tmp_path / "tune.jsonl").read_text()
     assert '"nx": 256' in text
+    # a new context reads the tuned choice back and reproduces the tuned run
+    monkeypatch.setenv("TACAW_TUNE_CACHE", str(tmp_path / "tune.jsonl"))
+    with tacaw.Context(0) as ctx:
+        h = tacaw.TacawJob(ctx, job)
+        h.run()
+        assert np.array_equal(h.spectrum().view(np.uint32), after.view(np.uint32))
+        h.destroy()
