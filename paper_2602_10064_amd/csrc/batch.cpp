@@ -68,18 +68,41 @@ SplatArgs splat_args(tacaw_job* j, int f0, int fb, int slice) {
   return sa;
 }
 
-// One group of same-grid jobs on one stream.
-tacaw_status run_group(tacaw_ctx* c, std::vector<tacaw_job*>& jobs, hipStream_t s) {
+// One group of same-grid jobs on one stream, advanced one iteration at a
+// time: each iteration launches the potentials of the lanes that start a
+// slice group, then one row pass and one column pass over all active lanes.
+struct GroupRun {
+  tacaw_ctx* c = nullptr;
+  hipStream_t s = nullptr;
   std::deque<BLane> pending;
-  for (tacaw_job* j : jobs)
-    for (int f0 = 0; f0 < j->hp.F; f0 += j->hp.fb) pending.push_back({j, f0, std::min(j->hp.fb, j->hp.F - f0), 0});
   std::vector<BLane> active;
   std::map<tacaw_job*, int> left;  // frame batches not finished per job
-  for (tacaw_job* j : jobs) left[j] = (j->hp.F + j->hp.fb - 1) / j->hp.fb;
-  const int nx = jobs[0]->hp.nx, ny = jobs[0]->hp.ny;
-  const int rv = row_variant_for(c, nx), cv = col_variant_for(c, ny);
-  while (!pending.empty() || !active.empty()) {
-    // fill free lanes, at most one lane per job
+  int rv = 0, cv = 0;
+
+  GroupRun(tacaw_ctx* ctx, const std::vector<tacaw_job*>& jobs, hipStream_t stream) : c(ctx), s(stream) {
+    for (tacaw_job* j : jobs) {
+      for (int f0 = 0; f0 < j->hp.F; f0 += j->hp.fb) pending.push_back({j, f0, std::min(j->hp.fb, j->hp.F - f0), 0});
+      left[j] = (j->hp.F + j->hp.fb - 1) / j->hp.fb;
+    }
+    rv = row_variant_for(c, jobs[0]->hp.nx);
+    cv = col_variant_for(c, jobs[0]->hp.ny);
+  }
+  bool done() const { return pending.empty() && active.empty(); }
+
+  // waves and one potential slice of a lane's frame batch
+  static double lane_bytes(const BLane& l) {
+    const HostPlan& hp = l.job->hp;
+    return (double)l.fb * ((double)hp.P * hp.nx * hp.ny * 8.0 + (double)hp.pnx * hp.pny * 4.0);
+  }
+
+  tacaw_status step() {
+    // fill free lanes: at most one lane per job (a job has one potential
+    // buffer), and while the lanes' waves fit the working-set target
+    // (TACAW_BATCH_LANE_MB, default 256: the last-level cache), at least one
+    const char* e = getenv("TACAW_BATCH_LANE_MB");
+    const double cap = (e ? atof(e) : 256.0) * (1 << 20);
+    double in_use = 0.0;
+    for (auto& l : active) in_use += lane_bytes(l);
     for (auto it = pending.begin(); it != pending.end() && (int)active.size() < MAX_LANES;) {
       bool busy = false;
       for (auto& l : active) busy |= l.job == it->job;
@@ -87,24 +110,35 @@ tacaw_status run_group(tacaw_ctx* c, std::vector<tacaw_job*>& jobs, hipStream_t 
         ++it;
         continue;
       }
+      if (!active.empty() && in_use + lane_bytes(*it) > cap) break;
+      in_use += lane_bytes(*it);
       active.push_back(*it);
       it = pending.erase(it);
     }
     const int n = (int)active.size();
+    // potentials: a lane at the start of a slice group builds that group's
+    // slices (the job's splat_group) in this iteration's potential launch
     SplatLane sl[MAX_LANES];
     PassLane rl[MAX_LANES], cl[MAX_LANES];
+    int n_splat = 0;
     for (int i = 0; i < n; ++i) {
       BLane& L = active[i];
       tacaw_job* j = L.job;
-      sl[i] = SplatLane{};
-      sl[i].a = splat_args(j, L.f0, L.fb, L.slice);
-      sl[i].n_slices_launch = 1;
+      const int G = j->hp.splat_group;
+      const int g0 = L.slice - L.slice % G;
+      const int gn = std::min(G, j->hp.ns - g0);
+      if (L.slice == g0) {
+        sl[n_splat] = SplatLane{};
+        sl[n_splat].a = splat_args(j, L.f0, L.fb, g0);
+        sl[n_splat].n_slices_launch = gn;
+        ++n_splat;
+      }
       PassArgs a = pass_args(j);
       a.f0 = L.f0;
       a.fb = L.fb;
       a.slice = L.slice;
-      a.v_slices = 1;
-      a.v_slice0 = L.slice;
+      a.v_slices = gn;
+      a.v_slice0 = g0;
       rl[i] = PassLane{};
       rl[i].a = a;
       rl[i].mode = L.slice == 0 ? ROW_FIRST : ROW_REGULAR;
@@ -117,8 +151,11 @@ tacaw_status run_group(tacaw_ctx* c, std::vector<tacaw_job*>& jobs, hipStream_t 
       }
       cl[i].mode = last ? COL_LAST : COL_REGULAR;
     }
-    tacaw_status st = timed_launch(c, TACAW_K_SPLAT, s, [&] { return launch_splat_lanes(sl, n, s); });
-    if (st != TACAW_OK) return st;
+    tacaw_status st = TACAW_OK;
+    if (n_splat > 0) {
+      st = timed_launch(c, TACAW_K_SPLAT, s, [&] { return launch_splat_lanes(sl, n_splat, s); });
+      if (st != TACAW_OK) return st;
+    }
     st = timed_launch(c, TACAW_K_ROW, s, [&] { return launch_row_lanes(rl, n, rv, s); });
     if (st != TACAW_OK) return st;
     st = timed_launch(c, TACAW_K_COL, s, [&] { return launch_col_lanes(cl, n, cv, s); });
@@ -136,9 +173,9 @@ tacaw_status run_group(tacaw_ctx* c, std::vector<tacaw_job*>& jobs, hipStream_t 
       }
     }
     active.swap(still);
+    return TACAW_OK;
   }
-  return TACAW_OK;
-}
+};
 
 void load_tune_cache(tacaw_ctx* c) {
   if (c->tune_loaded) return;
@@ -195,14 +232,10 @@ tacaw_status tacaw_run_batch(tacaw_job* const* jobs, int n_jobs, void* hip_strea
   if (st != TACAW_OK) return st;
   hipStream_t user = (hipStream_t)hip_stream;
   std::map<std::pair<int, int>, std::vector<tacaw_job*>> groups;
-  std::vector<tacaw_job*> plain;   // jobs planned with all-slice potentials run one by one
   for (int i = 0; i < n_jobs; ++i) {
     st = materialize(jobs[i], nullptr);
     if (st != TACAW_OK) return st;
-    if (jobs[i]->hp.splat_per_slice)
-      groups[{jobs[i]->hp.nx, jobs[i]->hp.ny}].push_back(jobs[i]);
-    else
-      plain.push_back(jobs[i]);
+    groups[{jobs[i]->hp.nx, jobs[i]->hp.ny}].push_back(jobs[i]);
   }
   hipEvent_t start;
   if (hipEventCreateWithFlags(&start, hipEventDisableTiming) != hipSuccess) {
@@ -210,17 +243,28 @@ tacaw_status tacaw_run_batch(tacaw_job* const* jobs, int n_jobs, void* hip_strea
     return TACAW_EDEVICE;
   }
   (void)hipEventRecord(start, user);
-  int k = 0;
+  std::vector<GroupRun> runs;
   bool used[4] = {false, false, false, false};
+  int n_streams = 4;   // TACAW_BATCH_STREAMS: streams the groups spread over (1-4)
+  if (const char* e = getenv("TACAW_BATCH_STREAMS")) n_streams = std::max(1, std::min(4, atoi(e)));
   for (auto& g : groups) {
-    hipStream_t s = c->batch_streams[k % 4];
-    if (!used[k % 4]) (void)hipStreamWaitEvent(s, start, 0);
-    used[k % 4] = true;
-    st = run_group(c, g.second, s);
-    if (st != TACAW_OK) break;
-    ++k;
+    const int k = (int)runs.size() % n_streams;
+    if (!used[k]) (void)hipStreamWaitEvent(c->batch_streams[k], start, 0);
+    used[k] = true;
+    runs.emplace_back(c, g.second, c->batch_streams[k]);
   }
-  for (int i = 0; i < 4 && st == TACAW_OK; ++i) {
+  // enqueue the groups' iterations round-robin, so that every stream has
+  // work queued while the others run
+  for (bool more = true; more && st == TACAW_OK;) {
+    more = false;
+    for (auto& r : runs) {
+      if (r.done()) continue;
+      st = r.step();
+      if (st != TACAW_OK) break;
+      more = true;
+    }
+  }
+  for (int i = 0; i < 4; ++i) {
     if (!used[i]) continue;
     hipEvent_t done;
     if (hipEventCreateWithFlags(&done, hipEventDisableTiming) != hipSuccess) continue;
@@ -230,13 +274,6 @@ tacaw_status tacaw_run_batch(tacaw_job* const* jobs, int n_jobs, void* hip_strea
   }
   (void)hipEventDestroy(start);
   if (st != TACAW_OK) return st;
-  for (tacaw_job* j : plain) {
-    st = run_batch_range(j, user, 0, j->hp.F);
-    if (st != TACAW_OK) return st;
-    st = run_time_stage(j, user);
-    if (st != TACAW_OK) return st;
-    j->has_result = true;
-  }
   for (int i = 0; i < n_jobs; ++i) jobs[i]->last_stream = user;
   return TACAW_OK;
 }

@@ -527,16 +527,19 @@ __device__ __forceinline__ void fft_r8(float2 (&x)[8], float2* lds, const float2
 }
 
 template <int N>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k_row_r8(PassTable tab, int blocks_per_lane) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k_row_r8(PassTable tab) {
   constexpr int G = R8<N>::G;
   constexpr int RPW = R8<N>::RPW;
   constexpr int S = R8<N>::S;
   __shared__ float2 scratch[4][RPW][padded(N)];
 
-  const int L = blockIdx.x / blocks_per_lane;
+  // lane L owns blocks [block_start, next lane's block_start), in proportion
+  // to its rows
+  const int L = find_lane(tab, blockIdx.x);
   const PassArgs& a = tab.l[L].a;
   const int mode = tab.l[L].mode;
-  const int lb = blockIdx.x % blocks_per_lane;
+  const int lb = blockIdx.x - tab.l[L].block_start;
+  const int blocks_per_lane = (L + 1 < tab.n ? tab.l[L + 1].block_start : (int)gridDim.x) - tab.l[L].block_start;
   // wavefront-uniform: with one row per wavefront the row bookkeeping below
   // runs on the scalar unit
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
@@ -987,17 +990,27 @@ static bool same_grid(const PassLane* lanes, int n) {
 
 template <int N>
 static hipError_t row_r8_launch(PassTable& t, hipStream_t s) {
-  // blocks per lane: enough waves for the lane's rows, at most 2048 blocks in all
-  long most = 0;
+  // blocks: one per rows_per_block rows, at most 2048 in all, shared among
+  // the lanes in proportion to their rows (each walks its rows with a grid
+  // stride over its own blocks)
+  constexpr int rows_per_block = 4 * R8<N>::RPW;
+  constexpr long max_blocks = 2048;
+  long rows[MAX_LANES], total = 0;
   for (int i = 0; i < t.n; ++i) {
     const PassArgs& a = t.l[i].a;
-    most = std::max(most, (long)a.n_probes * a.fb * a.ny);
+    rows[i] = (long)a.n_probes * a.fb * a.ny;
+    if (rows[i] + max_blocks * rows_per_block >= (1L << 31)) return hipErrorInvalidValue;  // 32-bit row ids
+    total += rows[i];
   }
-  constexpr int rows_per_block = 4 * R8<N>::RPW;
-  if (most + (long)2048 * rows_per_block >= (1L << 31)) return hipErrorInvalidValue;  // 32-bit row ids
-  long bpl = (most + rows_per_block - 1) / rows_per_block;
-  bpl = std::min<long>(bpl, std::max<long>(1, 2048 / t.n));
-  hipLaunchKernelGGL((k_row_r8<N>), dim3((unsigned)(bpl * t.n)), dim3(256), 0, s, t, (int)bpl);
+  const long need = (total + rows_per_block - 1) / rows_per_block;
+  int blocks = 0;
+  for (int i = 0; i < t.n; ++i) {
+    const long own = (rows[i] + rows_per_block - 1) / rows_per_block;
+    const long b = need <= max_blocks ? own : std::max(1L, std::min(own, rows[i] * max_blocks / total));
+    t.l[i].block_start = blocks;
+    blocks += (int)b;
+  }
+  hipLaunchKernelGGL((k_row_r8<N>), dim3(blocks), dim3(256), 0, s, t);
   return hipGetLastError();
 }
 
