@@ -702,9 +702,12 @@ struct C8 {
   static constexpr int CPW = 64 / G;            // columns per wavefront
   static constexpr int WAVES = (N == 512 ? 8 : 4) * (WIDE ? 2 : 1);
   static constexpr int CT = WAVES * CPW;        // columns per block
-  // padded column stride: 2 LD = 16 (mod 32) dwords puts the 8 columns that
-  // one transpose instruction touches on disjoint bank halves
-  static constexpr int LD = padded(N) + (padded(N) % 16 == 8 ? 0 : 8);
+  // column stride in LDS (8-byte slots).  An 8-byte LDS access serves 16
+  // lanes per pass over the 32 banks, so the 16 lanes of a transpose
+  // instruction must land on 16 distinct slots mod 16: two adjacent rows of 8
+  // columns need LD = 2 (mod 16), one row of 16 columns an odd LD; 64-point
+  // columns (two per 16 lanes in the FFT exchanges) need LD = 8 (mod 16).
+  static constexpr int LD = N == 64 ? padded(N) : CT >= 16 ? padded(N) + 1 : padded(N) + 2;
   static constexpr int THREADS = WAVES * 64;
 };
 
