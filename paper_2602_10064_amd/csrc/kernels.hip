@@ -190,10 +190,13 @@ __device__ __forceinline__ float profile_tile(int o, int j, float f, float e2, f
 // deterministic.
 __global__ void __launch_bounds__(256) k_splat(SplatTable tab) {
   constexpr int MP = 32;          // pairs per round: one row profile and one column profile per lane
-  constexpr int PAD = SPLAT_TX + 1;
+  // profiles in LDS as [node][pair], rows of PS = MP + 2 floats: a fill
+  // instruction (32 lanes, one node, consecutive pairs) and an MFMA operand
+  // read (16 nodes x 2 pairs, node stride 2 banks) both hit 32 distinct banks
+  constexpr int PS = MP + 2;
   static_assert(SPLAT_TX == 32 && SPLAT_TY == 32, "MFMA tiling assumes 32 x 32 tiles");
-  __shared__ float gxs[4][MP][PAD];
-  __shared__ float gys[4][MP][PAD];
+  __shared__ float gxs[4][SPLAT_TX][PS];
+  __shared__ float gys[4][SPLAT_TY][PS];
   __shared__ float coef_s[SPLAT_MAX_SPECIES * N_GAUSS * COEF_STRIDE];
 
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
@@ -224,11 +227,11 @@ __global__ void __launch_bounds__(256) k_splat(SplatTable tab) {
   const int ce = a.tile_start[s * n_tiles + tile + 1];
   const bool simple_x = a.img_x == 0 && 2 * (a.rcx + SPLAT_TX + 2) < a.pnx;
   const bool simple_y = a.img_y == 0 && 2 * (a.rcy + SPLAT_TY + 2) < a.pny;
-  float (*gx)[PAD] = gxs[wave];
-  float (*gy)[PAD] = gys[wave];
+  float (*gx)[PS] = gxs[wave];
+  float (*gy)[PS] = gys[wave];
   const int pr = lane % MP;         // pair of this lane
   const bool along_y = lane >= MP;  // lanes 0-31 build column profiles, 32-63 row profiles
-  float* dst = along_y ? gy[pr] : gx[pr];
+  float* dst = along_y ? &gy[0][pr] : &gx[0][pr];   // node j at dst[j * PS]
   typedef float v4f __attribute__((ext_vector_type(4)));
 
   // per round: this lane's atom and coefficients are the same for every
@@ -295,23 +298,23 @@ __global__ void __launch_bounds__(256) k_splat(SplatTable tab) {
 #pragma unroll
           for (int x = 0; x < SPLAT_TX; ++x) {
             const float d = (float)x - u;
-            dst[x] = fabsf(d) <= rc ? amp * __builtin_amdgcn_exp2f(-e2 * d * d) : 0.f;
+            dst[x * PS] = fabsf(d) <= rc ? amp * __builtin_amdgcn_exp2f(-e2 * d * d) : 0.f;
           }
         } else {
           const int img = along_y ? a.img_y : a.img_x;
-          for (int x = 0; x < SPLAT_TX; ++x) dst[x] = amp * profile(node0 + x, ip, fp, n_ax, e2, rc, img);
+          for (int x = 0; x < SPLAT_TX; ++x) dst[x * PS] = amp * profile(node0 + x, ip, fp, n_ax, e2, rc, img);
         }
       } else if (pr < mp4) {
 #pragma unroll
-        for (int x = 0; x < SPLAT_TX; ++x) dst[x] = 0.f;
+        for (int x = 0; x < SPLAT_TX; ++x) dst[x * PS] = 0.f;
       }
       wave_lds_sync();
       // V[r][c] += sum_k gy[k][r] gx[k][c] over four 16 x 16 quarters; A is 16 x 4
       // (row lane % 16, k lane / 16), B is 4 x 16 (k lane / 16, column lane % 16)
       for (int k0 = 0; k0 < mp4; k0 += 4) {
         const int kk = k0 + lane / 16;
-        const float a0 = gy[kk][lane % 16], a1 = gy[kk][16 + lane % 16];
-        const float b0 = gx[kk][lane % 16], b1 = gx[kk][16 + lane % 16];
+        const float a0 = gy[lane % 16][kk], a1 = gy[16 + lane % 16][kk];
+        const float b0 = gx[lane % 16][kk], b1 = gx[16 + lane % 16][kk];
         acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0], 0, 0, 0);
         acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[1], 0, 0, 0);
         acc[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[2], 0, 0, 0);
