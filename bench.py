@@ -227,6 +227,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--frames", type=int, default=1024, help="frames (1024 = the named workload)")
     ap.add_argument("--cpu-sample", type=int, default=16, help="frames of the oracle baseline (0: skip)")
+    ap.add_argument("--timing", default="passes", choices=["passes", "all", "none"],
+                    help="kernel classes bracketed with HIP events in the timed region")
+    ap.add_argument("--timing-every", type=int, default=7,
+                    help="time one launch in this many of each timed class (7: coprime with the
+                    "slice count, so the sampled launches rotate over the slices)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for counter calibration)")
     args = ap.parse_args()
@@ -259,7 +264,11 @@ def main():
     torch.cuda.synchronize()
     print("[bench] warmup done", file=sys.stderr, flush=True)
 
-    ctx.timing_enable(True)
+    # timed region: one launch in --timing-every of the two HBM passes (the
+    # roofline candidates) records start/end events; the rest run without
+    timed_classes = {"all": None, "passes": ("row", "col"), "none": ()}[args.timing]
+    ctx.timing_select(timed_classes, args.timing_every)
+    ctx.timing_enable(args.timing != "none")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -269,6 +278,14 @@ def main():
     timing = {k: ctx.timing_get(k) for k in ("splat", "row", "col", "time")}
     ctx.timing_enable(False)
     print("[bench] timed steps done", file=sys.stderr, flush=True)
+    # one more step, outside the timed region, with every class timed: the
+    # per-class breakdown of a step
+    ctx.timing_select(None)
+    ctx.timing_enable(True)
+    j.run(stream=stream)
+    torch.cuda.synchronize()
+    breakdown = {k: round(ctx.timing_get(k)[0], 3) for k in ("splat", "row", "col", "time")}
+    ctx.timing_enable(False)
 
     if args.copy_calibration:
         a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")      # 1 GiB
@@ -281,29 +298,30 @@ def main():
     slice_steps = job.nx * job.ny * job.n_slices * job.n_frames * job.n_probes
     value = slice_steps / (elapsed / args.steps)
 
-    # roofline of the dominant kernel class (largest total time)
-    per_launch_units = {
-        "row": None, "col": None, "splat": None, "time": job.nx * job.ny * job.n_frames * job.n_probes,
-    }
-    totals = {k: v[0] for k, v in timing.items()}
-    dom = max(("row", "col", "splat"), key=lambda k: totals[k])
-    ms, n = timing[dom]
-    units = job.nx * job.ny * job.n_frames * job.n_probes * job.n_slices / max(1, n) * args.steps
-    avg_ms = ms / max(1, n)
-    achieved = BYTES_PER_UNIT[dom] * units / (avg_ms * 1e-3) / 1e9
-    traffic = None
-    tpath = os.path.join(ROOT, "profiles", "traffic.json")
-    if os.path.exists(tpath):
-        tr = json.load(open(tpath))
-        if tr.get("source_hash") == kernel_source_hash() and dom in tr.get("per_launch_bytes", {}):
-            traffic = tr["per_launch_bytes"][dom]
-    roofline = {"bound": "hbm", "kernel": f"{dom} pass", "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                "traffic": traffic, "avg_launch_ms": round(avg_ms, 4), "launches": n,
-                "algorithmic_bytes_per_launch": BYTES_PER_UNIT[dom] * units}
+    # roofline of the dominant kernel class: the timed class with the largest
+    # total time in the timed region
+    timed = {k: v for k, v in timing.items() if v[1] > 0 and k in ("row", "col", "splat")}
+    roofline = None
+    if timed:
+        dom = max(timed, key=lambda k: timed[k][0])
+        ms, n = timed[dom]
+        # every launch of a pass advances one frame batch by one slice
+        units = job.nx * job.ny * job.n_probes * j.plan()[0]
+        avg_ms = ms / n
+        achieved = BYTES_PER_UNIT[dom] * units / (avg_ms * 1e-3) / 1e9
+        traffic = None
+        tpath = os.path.join(ROOT, "profiles", "traffic.json")
+        if os.path.exists(tpath):
+            tr = json.load(open(tpath))
+            if tr.get("source_hash") == kernel_source_hash() and dom in tr.get("per_launch_bytes", {}):
+                traffic = tr["per_launch_bytes"][dom]
+        roofline = {"bound": "hbm", "kernel": f"{dom} pass", "achieved": round(achieved, 1),
+                    "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                    "traffic": traffic, "avg_launch_ms": round(avg_ms, 4), "launches": n,
+                    "algorithmic_bytes_per_launch": BYTES_PER_UNIT[dom] * units}
     model_bytes = sum(BYTES_PER_UNIT[k] for k in ("row", "col", "splat")) * slice_steps + \
         BYTES_PER_UNIT["time"] * job.nx * job.ny * job.n_frames
-    kernel_ms = {k: round(v[0] / args.steps, 3) for k, v in timing.items()}
+    kernel_ms = {k: round(v[0] / args.steps, 3) for k, v in timing.items() if v[1] > 0}
 
     cpu = None
     if args.cpu_sample > 0:
@@ -328,7 +346,8 @@ def main():
                    "precision": "complex64 (FP32) multislice and time FFT, FP64 frame mean"},
         "hbm_effective_GBps": round(model_bytes / (elapsed / args.steps) / 1e9, 1),
         "hbm_frac": round(model_bytes / (elapsed / args.steps) / 1e9 / HBM_PEAK_GBPS, 4),
-        "kernel_ms_per_step": kernel_ms,
+        "kernel_ms_per_step": breakdown,
+        "timed_region_kernel_ms_per_step": kernel_ms,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

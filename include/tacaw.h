@@ -212,6 +212,11 @@ tacaw_status tacaw_axes(const tacaw_job_desc* desc, double* kx, double* ky, doub
 /* Slice index of every atom (n_atoms int32, host), as the planner binned it. */
 tacaw_status tacaw_job_slices(const tacaw_job* job, int32_t* slice_of_atom, size_t n);
 
+/* The planner's launch shapes for a job: frames advanced together through
+ * the slices (every row or column pass launch covers one such batch and one
+ * slice), and slices per potential launch.  NULL outputs are skipped. */
+tacaw_status tacaw_job_plan(const tacaw_job* job, int32_t* frame_batch, int32_t* slices_per_potential_launch);
+
 /* Release a job's device memory.  EBUSY while it is in the serving loop. */
 tacaw_status tacaw_job_destroy(tacaw_job* job);
 
@@ -226,15 +231,22 @@ typedef enum {
   TACAW_K_ROW = 1,        /* row pass: iFFT_x, transmission, FFT_x     */
   TACAW_K_COL = 2,        /* column pass: FFT_y, propagator, iFFT_y    */
   TACAW_K_TIME = 3,       /* FP64 mean, time FFT, |.|^2                */
-  TACAW_K_OTHER = 4,      /* tables, probes, fused/persistent kernels  */
-  TACAW_K_FUSED = 5,      /* fused whole-multislice kernel             */
-  TACAW_K_COUNT = 6
+  TACAW_K_OTHER = 4,      /* tables and incident probes                */
+  TACAW_K_COUNT = 5
 } tacaw_kernel_class;
 
 /* Turn per-kernel HIP-event timing on (1) or off (0) for jobs of this
- * context; turning it on clears the accumulated figures.  Events are
- * recorded on the stream each kernel is launched on. */
+ * context; turning it on clears the accumulated figures.  A timed launch
+ * records a start and an end event itself, on the stream the kernel runs on
+ * (hipExtLaunchKernel), for the launches tacaw_timing_select picks. */
 tacaw_status tacaw_timing_enable(tacaw_ctx* ctx, int on);
+
+/* Select what timing measures: the kernel classes (bit c of class_mask for
+ * class c; default all) and one launch in `every` of each selected class
+ * (default 1: every launch; the first launch of a class after this call is
+ * timed).  Other launches run without events and are not counted.  EINVAL if
+ * every < 1. */
+tacaw_status tacaw_timing_select(tacaw_ctx* ctx, unsigned class_mask, int every);
 
 /* Accumulated kernel time (ms) and launch count of one class since timing
  * was enabled; synchronises the recorded events first. */

@@ -116,22 +116,24 @@ int col_variant_for(tacaw_ctx* c, int n) {
   return has_register_fft(n) ? 2 : 0;
 }
 
-// Launch wrapper: brackets the launch with events on its stream when timing.
+// Launch wrapper: when timing, the launch records a start and an end event
+// on its stream.
 tacaw_status timed_launch(tacaw_ctx* c, int cls, hipStream_t s, const std::function<hipError_t()>& launch) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   bool tm = false;
   {
     std::lock_guard<std::mutex> lk(c->mu);
-    tm = c->timing;
+    tm = c->timing && ((c->timing_mask >> cls) & 1u) && (c->launch_seq[cls]++ % c->timing_every) == 0;
     if (tm) {
       if (c->records.size() > 8192) drain_records(c);
       e0 = take_event(c);
       e1 = take_event(c);
     }
   }
-  if (tm && e0) (void)hipEventRecord(e0, s);
+  // the launch itself records the events (no separate event packets)
+  if (tm && e0 && e1) set_launch_events(e0, e1);
   hipError_t e = launch();
-  if (tm && e1) (void)hipEventRecord(e1, s);
+  set_launch_events(nullptr, nullptr);
   if (tm && e0 && e1) {
     std::lock_guard<std::mutex> lk(c->mu);
     c->records.push_back({cls, e0, e1});
@@ -704,6 +706,17 @@ tacaw_status tacaw_job_slices(const tacaw_job* job, int32_t* out, size_t n) {
   return TACAW_OK;
 }
 
+tacaw_status tacaw_job_plan(const tacaw_job* job, int32_t* frame_batch, int32_t* slices_per_potential_launch) {
+  clear_error();
+  if (!job) {
+    set_error("job is NULL");
+    return TACAW_EINVAL;
+  }
+  if (frame_batch) *frame_batch = job->hp.fb;
+  if (slices_per_potential_launch) *slices_per_potential_launch = job->hp.splat_group;
+  return TACAW_OK;
+}
+
 tacaw_status tacaw_job_destroy(tacaw_job* job) {
   clear_error();
   if (!job) return TACAW_OK;
@@ -741,6 +754,19 @@ tacaw_status tacaw_timing_enable(tacaw_ctx* c, int on) {
       c->total_ms[i] = 0.0;
       c->launches[i] = 0;
     }
+  return TACAW_OK;
+}
+
+tacaw_status tacaw_timing_select(tacaw_ctx* c, unsigned class_mask, int every) {
+  clear_error();
+  if (!c || every < 1) {
+    set_error("ctx is NULL or every < 1");
+    return TACAW_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->timing_mask = class_mask;
+  c->timing_every = every;
+  for (int i = 0; i < TACAW_K_COUNT; ++i) c->launch_seq[i] = 0;
   return TACAW_OK;
 }
 

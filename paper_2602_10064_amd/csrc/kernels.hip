@@ -10,6 +10,7 @@
 //   k_time       per (probe, k): FP64 frame mean, FP64 subtraction, time FFT,
 //                |.|^2 / F^2 for the kept frequency bins
 //   setup        twiddles, propagator factors, probe aperture fill
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -19,6 +20,24 @@
 #include "tacaw_internal.h"
 
 namespace tacaw {
+
+// Timing events for the next main-kernel launch on this thread: when set, the
+// launch records them itself (start and end of the kernel) instead of separate
+// event packets around it.
+static thread_local hipEvent_t t_ev_start = nullptr, t_ev_stop = nullptr;
+void set_launch_events(hipEvent_t start, hipEvent_t stop) {
+  t_ev_start = start;
+  t_ev_stop = stop;
+}
+#define TACAW_LAUNCH(K, GRID, BLOCK, SHM, S, ...)                                   \
+  do {                                                                              \
+    hipEvent_t e0_ = t_ev_start, e1_ = t_ev_stop;                                   \
+    t_ev_start = t_ev_stop = nullptr;                                               \
+    if (e0_)                                                                        \
+      hipExtLaunchKernelGGL(K, GRID, BLOCK, SHM, S, e0_, e1_, 0, __VA_ARGS__);      \
+    else                                                                            \
+      hipLaunchKernelGGL(K, GRID, BLOCK, SHM, S, __VA_ARGS__);                      \
+  } while (0)
 
 // Blocks are dealt to the 8 XCDs round-robin (block b runs on XCD b mod 8).
 // Remap so that each XCD works on a contiguous range of logical tiles: tiles
@@ -970,7 +989,7 @@ static hipError_t row_launch(PassTable& t, hipStream_t s) {
     t.l[i].block_start = blocks;
     blocks += (int)((total + RPI - 1) / RPI);
   }
-  hipLaunchKernelGGL((k_row<N, VAR>), dim3(blocks), dim3(RowCfg<N, VAR>::THREADS), 0, s, t);
+  TACAW_LAUNCH((k_row<N, VAR>), dim3(blocks), dim3(RowCfg<N, VAR>::THREADS), 0, s, t);
   return hipGetLastError();
 }
 
@@ -984,7 +1003,7 @@ static hipError_t col_launch(PassTable& t, hipStream_t s) {
     t.l[i].block_start = blocks;
     blocks += a.n_probes * a.fb * (a.nx / CT);
   }
-  hipLaunchKernelGGL((k_col<N, VAR>), dim3(blocks), dim3(ColCfg<N, VAR>::THREADS), 0, s, t);
+  TACAW_LAUNCH((k_col<N, VAR>), dim3(blocks), dim3(ColCfg<N, VAR>::THREADS), 0, s, t);
   return hipGetLastError();
 }
 
@@ -1016,7 +1035,7 @@ static hipError_t row_r8_launch(PassTable& t, hipStream_t s) {
     t.l[i].block_start = blocks;
     blocks += (int)b;
   }
-  hipLaunchKernelGGL((k_row_r8<N>), dim3(blocks), dim3(256), 0, s, t);
+  TACAW_LAUNCH((k_row_r8<N>), dim3(blocks), dim3(256), 0, s, t);
   return hipGetLastError();
 }
 
@@ -1055,7 +1074,7 @@ static hipError_t col_r8_launch(PassTable& t, hipStream_t s) {
     tiles += a.n_probes * a.fb * (a.nx / CT);
   }
   const int grid = std::min(tiles, 2048);
-  hipLaunchKernelGGL((k_col_r8<N, WIDE>), dim3(grid), dim3(C8<N, WIDE>::THREADS), 0, s, t, tiles);
+  TACAW_LAUNCH((k_col_r8<N, WIDE>), dim3(grid), dim3(C8<N, WIDE>::THREADS), 0, s, t, tiles);
   return hipGetLastError();
 }
 
@@ -1119,7 +1138,7 @@ hipError_t launch_splat_lanes(const SplatLane* lanes, int n, hipStream_t s) {
                       ((a.fb + fpw_env - 1) / fpw_env);  // one per wavefront
     blocks += (items + 3) / 4;
   }
-  hipLaunchKernelGGL(k_splat, dim3(blocks), dim3(256), 0, s, t);
+  TACAW_LAUNCH(k_splat, dim3(blocks), dim3(256), 0, s, t);
   return hipGetLastError();
 }
 
@@ -1149,7 +1168,7 @@ static hipError_t time_ct_launch(const TimeArgs& a, hipStream_t s) {
     attr_set = true;
   }
   const long blocks = (long)a.n_probes * (a.n_k / KT);
-  hipLaunchKernelGGL(k_time_ct<F>, dim3((unsigned)blocks), dim3(TimeCfg<F>::THREADS), lds, s, a);
+  TACAW_LAUNCH((k_time_ct<F>), dim3((unsigned)blocks), dim3(TimeCfg<F>::THREADS), lds, s, a);
   return hipGetLastError();
 }
 
@@ -1169,7 +1188,7 @@ hipError_t launch_time_stage(const TimeArgs& a, hipStream_t s) {
   const size_t lds = (size_t)(a.n_frames + 2 * a.kt * a.n_frames) * sizeof(float2);
   const long blocks = (long)a.n_probes * (a.n_k / a.kt);
   dim3 grid((unsigned)blocks), block(a.kt * TIME_G);
-  hipLaunchKernelGGL(k_time, grid, block, lds, s, a);
+  TACAW_LAUNCH(k_time, grid, block, lds, s, a);
   return hipGetLastError();
 }
 

@@ -90,6 +90,9 @@ struct tacaw_ctx {
   size_t resident = 0;           // bytes held by jobs admitted by the serving loop
   // timing
   bool timing = false;
+  unsigned timing_mask = ~0u;    // kernel classes timed with events while timing
+  int timing_every = 1;          // time one launch in this many of each selected class
+  int64_t launch_seq[TACAW_K_COUNT] = {0};
   std::vector<tacaw::TimingRecord> records;
   std::vector<hipEvent_t> event_pool;
   double total_ms[TACAW_K_COUNT] = {0};

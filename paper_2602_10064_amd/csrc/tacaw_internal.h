@@ -90,6 +90,8 @@ enum ColMode { COL_REGULAR = 0, COL_LAST = 1, COL_INVERSE_ONLY = 2 };
 bool grid_supported(int n);
 hipError_t launch_splat(const SplatArgs& a, int n_slices_launch, hipStream_t s);
 hipError_t launch_row_pass(const PassArgs& a, int mode, hipStream_t s);
+// Events the next main-kernel launch on this thread records around itself.
+void set_launch_events(hipEvent_t start, hipEvent_t stop);
 hipError_t launch_row_lanes(const PassLane* lanes, int n, int variant, hipStream_t s);
 hipError_t launch_col_lanes(const PassLane* lanes, int n, int variant, hipStream_t s);
 hipError_t launch_splat_lanes(const SplatLane* lanes, int n, hipStream_t s);

@@ -23,9 +23,8 @@ KEEP_EXIT_WAVES = 2
 DEFER_ALLOC = 4
 USE_GRAPH = 8
 
-K_SPLAT, K_ROW, K_COL, K_TIME, K_OTHER, K_FUSED = range(6)
-KERNEL_CLASSES = {"splat": K_SPLAT, "row": K_ROW, "col": K_COL, "time": K_TIME, "other": K_OTHER,
-                  "fused": K_FUSED}
+K_SPLAT, K_ROW, K_COL, K_TIME, K_OTHER = range(5)
+KERNEL_CLASSES = {"splat": K_SPLAT, "row": K_ROW, "col": K_COL, "time": K_TIME, "other": K_OTHER}
 
 
 class TacawError(RuntimeError):
@@ -61,8 +60,8 @@ EXPORTED = [
     "tacaw_ctx_create", "tacaw_ctx_destroy", "tacaw_job_footprint", "tacaw_job_create", "tacaw_run",
     "tacaw_submit", "tacaw_poll", "tacaw_wait", "tacaw_cancel", "tacaw_get_spectrum",
     "tacaw_get_exit_waves", "tacaw_axes", "tacaw_job_slices", "tacaw_job_destroy", "tacaw_last_error",
-    "tacaw_timing_enable", "tacaw_timing_get", "tacaw_version", "tacaw_job_latency",
-    "tacaw_run_batch", "tacaw_autotune",
+    "tacaw_timing_enable", "tacaw_timing_select", "tacaw_timing_get", "tacaw_version", "tacaw_job_latency",
+    "tacaw_run_batch", "tacaw_autotune", "tacaw_job_plan",
 ]
 
 
@@ -93,10 +92,12 @@ def lib() -> ctypes.CDLL:
         "tacaw_job_slices": [vp, P(i32), sz],
         "tacaw_job_destroy": [vp],
         "tacaw_timing_enable": [vp, ctypes.c_int],
+        "tacaw_timing_select": [vp, ctypes.c_uint, ctypes.c_int],
         "tacaw_timing_get": [vp, ctypes.c_int, P(dp), P(ctypes.c_int64)],
         "tacaw_job_latency": [vp, P(dp), P(dp)],
         "tacaw_run_batch": [P(vp), ctypes.c_int, vp],
         "tacaw_autotune": [vp, vp, P(ctypes.c_int), P(ctypes.c_int)],
+        "tacaw_job_plan": [vp, P(i32), P(i32)],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -179,6 +180,17 @@ class Context:
 
     def timing_enable(self, on: bool = True):
         _check(lib().tacaw_timing_enable(self.handle, 1 if on else 0))
+
+    def timing_select(self, classes=None, every: int = 1):
+        """Time only these kernel classes (names or numbers; None: all), one
+        launch in `every` of each."""
+        if classes is None:
+            mask = 0xFFFFFFFF
+        else:
+            mask = 0
+            for k in classes:
+                mask |= 1 << (KERNEL_CLASSES[k] if isinstance(k, str) else int(k))
+        _check(lib().tacaw_timing_select(self.handle, ctypes.c_uint(mask), int(every)))
 
     def timing_get(self, kernel_class) -> tuple:
         cls = KERNEL_CLASSES[kernel_class] if isinstance(kernel_class, str) else int(kernel_class)
@@ -287,6 +299,12 @@ class TacawJob:
         out = np.empty(n, dtype=np.int32)
         _check(lib().tacaw_job_slices(self.handle, _ptr(out, ctypes.c_int32), n))
         return out
+
+    def plan(self) -> tuple:
+        """(frames per batch, slices per potential launch) chosen by the planner."""
+        fb, g = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().tacaw_job_plan(self.handle, ctypes.byref(fb), ctypes.byref(g)))
+        return fb.value, g.value
 
     def destroy(self):
         if self.handle:
