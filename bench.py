@@ -230,8 +230,8 @@ def main():
     ap.add_argument("--timing", default="passes", choices=["passes", "all", "none"],
                     help="kernel classes bracketed with HIP events in the timed region")
     ap.add_argument("--timing-every", type=int, default=7,
-                    help="time one launch in this many of each timed class (7: coprime with the
-                    "slice count, so the sampled launches rotate over the slices)")
+                    help="time one launch in this many of each timed class (7: coprime with the "
+                         "slice count, so the sampled launches rotate over the slices)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for counter calibration)")
     args = ap.parse_args()
