@@ -26,6 +26,10 @@ HBM_PEAK_GBPS = 8000.0
 WORKLOAD = ("12x12x8 diamond-cubic C/Si supercell (9216 atoms, 50/50 Z=6/14), 512x512 grid, "
             "32 slices of 1.3575 A, 100 kV plane wave, 1024 frames at 2 fs, seeded harmonic "
             "phonons (32 modes, 0.08 A rms), 512 one-sided energy bins")
+WORKLOAD_C3 = ("hexagonal B/N layer stack (a=2.5 A, 40x20 orthohexagonal cells, 12 AA' layers, "
+               "38400 atoms), 1000x866 full-cell potential grid, 256x256 probe windows, 20 slices, "
+               "30 mrad probe at 60 kV, 32x32 probe positions over 20 A, 256 frames at 10 fs, "
+               "seeded harmonic phonons, per-position I(k, w) with 128 bins")
 
 # Algorithmic HBM bytes per slice-step of each kernel class (complex64 = 8 B):
 #   row pass: read psi (8) + write psi (8) + read V (4)            = 20 B
@@ -45,7 +49,7 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def cpu_baseline(job, sample_frames: int):
+def cpu_baseline(job, sample_frames: int, what: str = ""):
     """FP64 oracle on `sample_frames` frames of the workload, one frame per worker."""
     from tests.oracle_pool import exit_waves_parallel
     from oracle import tacaw_oracle
@@ -57,8 +61,8 @@ def cpu_baseline(job, sample_frames: int):
     dt = time.perf_counter() - t0
     steps = job.nx * job.ny * job.n_slices * sample_frames * job.n_probes
     return {"value": steps / dt, "unit": "slice-steps/s", "cores": workers, "kind": "oracle",
-            "sample": f"{sample_frames} of the 1024 frames (full 512^2 grid, all 32 slices, "
-                      f"spectrum of the sample), FP64 numpy, one frame per process, {dt:.1f} s"}
+            "sample": (what or f"{sample_frames} of the 1024 frames (full 512^2 grid, all 32 slices, "
+                               f"spectrum of the sample)") + f", FP64 numpy, one frame per process, {dt:.1f} s"}
 
 
 def bench_c4(args):
@@ -215,7 +219,7 @@ def bench_c5(args):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="c2", choices=["c2", "c4", "c5"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"],
                     help="c2: the 512^2 x 32 x 1024 plane-wave workload (default); c4: uneven-job "
                          "batch; c5: serving")
     ap.add_argument("--jobs", type=int, default=64)
@@ -252,7 +256,10 @@ def main():
         print(json.dumps(bench_c5(args)), flush=True)
         return
     t_gen = time.perf_counter()
-    job = workloads.c2_plain(n_frames=args.frames)
+    if args.workload == "c3":
+        job = workloads.c3_probe(n_frames=min(args.frames, 256))
+    else:
+        job = workloads.c2_plain(n_frames=args.frames)
     t_gen = time.perf_counter() - t_gen
     print(f"[bench] inputs generated in {t_gen:.1f} s", file=sys.stderr, flush=True)
 
@@ -319,14 +326,25 @@ def main():
                     "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
                     "traffic": traffic, "avg_launch_ms": round(avg_ms, 4), "launches": n,
                     "algorithmic_bytes_per_launch": BYTES_PER_UNIT[dom] * units}
-    model_bytes = sum(BYTES_PER_UNIT[k] for k in ("row", "col", "splat")) * slice_steps + \
-        BYTES_PER_UNIT["time"] * job.nx * job.ny * job.n_frames
+    # potentials are written once per (frame, slice) on the potential grid and
+    # shared by all probes
+    pot_pts = (job.pot_nx or job.nx) * (job.pot_ny or job.ny)
+    model_bytes = (BYTES_PER_UNIT["row"] + BYTES_PER_UNIT["col"]) * slice_steps + \
+        BYTES_PER_UNIT["splat"] * pot_pts * job.n_frames * job.n_slices + \
+        BYTES_PER_UNIT["time"] * job.nx * job.ny * job.n_frames * job.n_probes
     kernel_ms = {k: round(v[0] / args.steps, 3) for k, v in timing.items() if v[1] > 0}
 
     cpu = None
     if args.cpu_sample > 0:
         print("[bench] timing the FP64 oracle on a sample", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(job, args.cpu_sample)
+        if args.workload == "c3":
+            # 4 probe positions x the sample frames, full windows and slices
+            sub = job.replace(probe_xy=job.probe_xy[:4], positions=job.positions[:args.cpu_sample])  # ~30 s at 8 frames
+            cpu = cpu_baseline(sub, args.cpu_sample, what="4 of the 1024 probe positions x %d of the "
+                               "256 frames (256^2 windows, all 20 slices, potentials on the 1000x866 "
+                               "grid, spectrum of the sample)" % args.cpu_sample)
+        else:
+            cpu = cpu_baseline(job, args.cpu_sample)
 
     out = {
         "metric": "slice-steps/sec (grid-pts*slices*frames/s) + %HBM peak",
@@ -341,7 +359,8 @@ def main():
         "vs_baseline": None,
         "dtype": "fp32",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD, "grid": [job.nx, job.ny], "slices": job.n_slices,
+        "config": {"workload": WORKLOAD_C3 if args.workload == "c3" else WORKLOAD,
+                   "grid": [job.nx, job.ny], "slices": job.n_slices,
                    "frames": job.n_frames, "probes": job.n_probes, "atoms": job.n_atoms,
                    "precision": "complex64 (FP32) multislice and time FFT, FP64 frame mean"},
         "hbm_effective_GBps": round(model_bytes / (elapsed / args.steps) / 1e9, 1),
