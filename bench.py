@@ -339,7 +339,7 @@ def main():
         print("[bench] timing the FP64 oracle on a sample", file=sys.stderr, flush=True)
         if args.workload == "c3":
             # 4 probe positions x the sample frames, full windows and slices
-            sub = job.replace(probe_xy=job.probe_xy[:4], positions=job.positions[:args.cpu_sample])  # ~30 s at 8 frames
+            sub = job.replace(probe_xy=job.probe_xy[:4], positions=job.positions[:args.cpu_sample])
             cpu = cpu_baseline(sub, args.cpu_sample, what="4 of the 1024 probe positions x %d of the "
                                "256 frames (256^2 windows, all 20 slices, potentials on the 1000x866 "
                                "grid, spectrum of the sample)" % args.cpu_sample)
