@@ -165,12 +165,13 @@ tacaw_status tacaw_run(tacaw_job* job, void* hip_stream);
 tacaw_status tacaw_run_batch(tacaw_job* const* jobs, int n_jobs, void* hip_stream);
 
 /* Autotuner: time the row-pass variants (rows per workgroup, and for grids
- * of 64 and 512 a register-resident radix-8 kernel) and the column-pass
+ * of 64 to 512 register-resident kernels with one or two rows in flight) and
+ * the column-pass
  * variants (tile widths, and for 64 and 512 rows register-resident radix-8
  * kernels on 8- or 16-column tiles) on one frame batch of `job` and keep the
  * faster of each for the job's grid size in the context (appended to the
  * JSON-lines file named by $TACAW_TUNE_CACHE, read back by later contexts).
- * Writes the chosen variants (row 0-2, column 0-3) when the pointers are not
+ * Writes the chosen variants (row 0-3, column 0-3) when the pointers are not
  * NULL.  Resets the context's timing totals. */
 tacaw_status tacaw_autotune(tacaw_job* job, void* hip_stream, int* row_variant, int* col_variant);
 

@@ -98,7 +98,8 @@ void drain_records(tacaw_ctx* c) {
 namespace tacaw {
 
 // Tile variant of the row pass (0: base rows per block, 1: doubled, 2: the
-// register kernel for 64, 128, 256 and 512) and of the column pass (0: half
+// register kernel for 64, 128, 256 and 512, 3: the same with two rows in
+// flight per wavefront) and of the column pass (0: half
 // width, 1: full width, 2: register kernel on 8-16 column tiles for 64-512
 // rows, 3: 16-column register tiles for 512 rows).  Tuned choices win;
 // $TACAW_ROW_VARIANT and $TACAW_COL_VARIANT override untuned defaults.

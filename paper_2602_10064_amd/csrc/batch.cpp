@@ -189,7 +189,7 @@ void load_tune_cache(tacaw_ctx* c) {
     int nx = 0, ny = 0, r = 0, cc = 0;
     if (sscanf(line.c_str(), "{\"nx\": %d, \"ny\": %d, \"row_variant\": %d, \"col_variant\": %d}", &nx, &ny, &r,
                &cc) == 4 &&
-        nx > 0 && nx < 2048 && ny > 0 && ny < 2048 && r >= 0 && r <= 2 && cc >= 0 && cc <= 3) {
+        nx > 0 && nx < 2048 && ny > 0 && ny < 2048 && r >= 0 && r <= 3 && cc >= 0 && cc <= 3) {
       c->row_variant[nx] = r + 1;
       c->col_variant[ny] = cc + 1;
     }
@@ -295,11 +295,12 @@ tacaw_status tacaw_autotune(tacaw_job* job, void* hip_stream, int* row_variant, 
   hipStream_t s = (hipStream_t)hip_stream;
   const HostPlan& hp = job->hp;
   const int fb = std::min(hp.fb, hp.F);
-  // row variants: 0, 1 (LDS rows), 2 (register FFT, grids 64-512);
+  // row variants: 0, 1 (LDS rows), 2, 3 (register FFT with one or two rows
+  // in flight, grids 64-512);
   // column variants: 0, 1 (LDS columns), 2 (register FFT on 8-32 column
   // tiles, ny 64-512), 3 (16-column tiles, ny 512)
   auto reg = [](int n) { return n == 64 || n == 128 || n == 256 || n == 512; };
-  const int n_row_var = reg(hp.nx) ? 3 : 2;
+  const int n_row_var = reg(hp.nx) ? 4 : 2;
   const int n_col_var = hp.ny == 512 ? 4 : reg(hp.ny) ? 3 : 2;
   const int n_var = std::max(n_row_var, n_col_var);
   double best_row[4] = {1e30, 1e30, 1e30, 1e30}, best_col[4] = {1e30, 1e30, 1e30, 1e30};

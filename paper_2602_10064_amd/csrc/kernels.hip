@@ -548,8 +548,12 @@ __device__ __forceinline__ void fft_r8(float2 (&x)[8], float2* lds, const float2
   reg_fft_stage<N, INV, 0>(x, lds, tw, t);
 }
 
-template <int N>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k_row_r8(PassTable tab) {
+// DEPTH 1: the next row's reads are in flight while a row is transformed
+// (five wavefronts per SIMD); DEPTH 2: the next two rows' (three rotating
+// register buffers, four wavefronts per SIMD).
+template <int N, int DEPTH>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DEPTH == 1 ? 5 : 4)))
+k_row_r8(PassTable tab) {
   constexpr int G = R8<N>::G;
   constexpr int RPW = R8<N>::RPW;
   constexpr int S = R8<N>::S;
@@ -616,27 +620,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k
     }
   };
 
-  float2 xn[8];
-  float vn[8];
-#pragma unroll
-  for (int r = 0; r < 8; ++r) {
-    xn[r] = make_float2(0.f, 0.f);
-    vn[r] = 0.f;
-  }
-  float2* out_next = nullptr;
-  int rid0 = (lb * 4 + wave) * RPW;
-  fetch(rid0 + sub, xn, vn, out_next);
-  for (; rid0 < total; rid0 += stride) {
-    const int rid = rid0 + sub;
-    float2* out = out_next;
-    float2 x[8];
-    float v[8];
-#pragma unroll
-    for (int r = 0; r < 8; ++r) {
-      x[r] = xn[r];
-      v[r] = vn[r];
-    }
-    fetch(rid0 + stride + sub, xn, vn, out_next);  // next row's reads overlap this row's arithmetic
+  // transform one row held in (x, v) and store it to out
+  auto transform = [&](float2 (&x)[8], const float (&v)[8], float2* out, int rid) {
     if (mode != ROW_FIRST) fft_r8<N, true>(x, lds, tw, t);
     if (transmit) {
 #pragma unroll
@@ -646,6 +631,53 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k
     if (rid < total) {
 #pragma unroll
       for (int r = 0; r < 8; ++r) out[t + r * G] = x[r];
+    }
+  };
+  int rid0 = (lb * 4 + wave) * RPW;
+  if constexpr (DEPTH == 1) {
+    float2 xn[8];
+    float vn[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      xn[r] = make_float2(0.f, 0.f);
+      vn[r] = 0.f;
+    }
+    float2* out_next = nullptr;
+    fetch(rid0 + sub, xn, vn, out_next);
+    for (; rid0 < total; rid0 += stride) {
+      float2* out = out_next;
+      float2 x[8];
+      float v[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        x[r] = xn[r];
+        v[r] = vn[r];
+      }
+      fetch(rid0 + stride + sub, xn, vn, out_next);  // next row's reads overlap this row's arithmetic
+      transform(x, v, out, rid0 + sub);
+    }
+  } else {
+    // rows i, i+1, i+2 of this wavefront rotate through buffers A, B, C: while
+    // one is transformed, the reads of the two after it are in flight
+    float2 xa[8], xb[8], xc[8];
+    float va[8], vb[8], vc[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      xa[r] = xb[r] = xc[r] = make_float2(0.f, 0.f);
+      va[r] = vb[r] = vc[r] = 0.f;
+    }
+    float2 *oa = nullptr, *ob = nullptr, *oc = nullptr;
+    fetch(rid0 + sub, xa, va, oa);
+    fetch(rid0 + stride + sub, xb, vb, ob);
+    for (; rid0 < total; rid0 += 3 * stride) {
+      fetch(rid0 + 2 * stride + sub, xc, vc, oc);
+      transform(xa, va, oa, rid0 + sub);
+      if (rid0 + stride >= total) break;
+      fetch(rid0 + 3 * stride + sub, xa, va, oa);
+      transform(xb, vb, ob, rid0 + stride + sub);
+      if (rid0 + 2 * stride >= total) break;
+      fetch(rid0 + 4 * stride + sub, xb, vb, ob);
+      transform(xc, vc, oc, rid0 + 2 * stride + sub);
     }
   }
 }
@@ -1013,7 +1045,7 @@ static bool same_grid(const PassLane* lanes, int n) {
   return true;
 }
 
-template <int N>
+template <int N, int DEPTH>
 static hipError_t row_r8_launch(PassTable& t, hipStream_t s) {
   // blocks: one per rows_per_block rows, at most 2048 in all, shared among
   // the lanes in proportion to their rows (each walks its rows with a grid
@@ -1024,7 +1056,7 @@ static hipError_t row_r8_launch(PassTable& t, hipStream_t s) {
   for (int i = 0; i < t.n; ++i) {
     const PassArgs& a = t.l[i].a;
     rows[i] = (long)a.n_probes * a.fb * a.ny;
-    if (rows[i] + max_blocks * rows_per_block >= (1L << 31)) return hipErrorInvalidValue;  // 32-bit row ids
+    if (rows[i] + 4 * max_blocks * rows_per_block >= (1L << 31)) return hipErrorInvalidValue;  // 32-bit row ids
     total += rows[i];
   }
   const long need = (total + rows_per_block - 1) / rows_per_block;
@@ -1035,7 +1067,7 @@ static hipError_t row_r8_launch(PassTable& t, hipStream_t s) {
     t.l[i].block_start = blocks;
     blocks += (int)b;
   }
-  TACAW_LAUNCH((k_row_r8<N>), dim3(blocks), dim3(256), 0, s, t);
+  TACAW_LAUNCH((k_row_r8<N, DEPTH>), dim3(blocks), dim3(256), 0, s, t);
   return hipGetLastError();
 }
 
@@ -1044,12 +1076,13 @@ hipError_t launch_row_lanes(const PassLane* lanes, int n, int variant, hipStream
   PassTable t{};
   t.n = n;
   for (int i = 0; i < n; ++i) t.l[i] = lanes[i];
-  if (variant == 2) {
+  if (variant == 2 || variant == 3) {
+    const bool deep = variant == 3;
     switch (lanes[0].a.nx) {
-      case 512: return row_r8_launch<512>(t, s);
-      case 256: return row_r8_launch<256>(t, s);
-      case 128: return row_r8_launch<128>(t, s);
-      case 64: return row_r8_launch<64>(t, s);
+      case 512: return deep ? row_r8_launch<512, 2>(t, s) : row_r8_launch<512, 1>(t, s);
+      case 256: return deep ? row_r8_launch<256, 2>(t, s) : row_r8_launch<256, 1>(t, s);
+      case 128: return deep ? row_r8_launch<128, 2>(t, s) : row_r8_launch<128, 1>(t, s);
+      case 64: return deep ? row_r8_launch<64, 2>(t, s) : row_r8_launch<64, 1>(t, s);
       default: variant = 1;
     }
   }

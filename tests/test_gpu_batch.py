@@ -102,7 +102,7 @@ def test_autotune_keeps_results(tacaw, tmp_path, monkeypatch):
         h.run()
         before = h.spectrum()
         rv, cv = h.autotune()
-        assert rv in (0, 1, 2) and cv in (0, 1, 2)
+        assert rv in (0, 1, 2, 3) and cv in (0, 1, 2)
         h.run()
         after = h.spectrum()
         if (rv, cv) == (2, 2):      # the untuned default: the same kernels

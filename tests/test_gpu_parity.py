@@ -172,6 +172,17 @@ def test_c3_shape_reduced_probes_frames(tacaw, ctx, oracle):
     check_job(tacaw, ctx, oracle, job)
 
 
+@pytest.mark.parametrize("n", [64, 128])
+def test_deep_row_kernel_matches(tacaw, ctx, monkeypatch, n):
+    # two rows in flight per wavefront: the same per-row arithmetic, so the
+    # same values to FP32 rounding (ragged grid stride over 9 frames)
+    job = w.random_small_job(41, nx=n, ny=n, n_slices=3, n_frames=9, cell=(n / 9.0, n / 9.0, 4.0))
+    _, a, _ = run_gpu(tacaw, ctx, job)
+    monkeypatch.setenv("TACAW_ROW_VARIANT", "3")
+    _, b, _ = run_gpu(tacaw, ctx, job)
+    assert rel_l2(b, a) < 1e-6
+
+
 def test_fft_variants_agree(tacaw, ctx, monkeypatch):
     # the LDS Stockham kernels with one or two rows per workgroup run the same
     # arithmetic per row (bitwise equal); the register kernels agree with them
@@ -187,8 +198,10 @@ def test_fft_variants_agree(tacaw, ctx, monkeypatch):
     assert rel_l2(reg, v0) < 1e-5
 
 
-def test_c2_shape_register_row_kernel(tacaw, ctx, oracle, monkeypatch):
-    monkeypatch.setenv("TACAW_ROW_VARIANT", "2")
+@pytest.mark.parametrize("variant", ["2", "3"])
+def test_c2_shape_register_row_kernel(tacaw, ctx, oracle, monkeypatch, variant):
+    # register row kernels with one (2) or two (3) rows in flight per wavefront
+    monkeypatch.setenv("TACAW_ROW_VARIANT", variant)
     monkeypatch.setenv("TACAW_FB", "3")
     job = w.c2_plain(n_frames=8)
     check_job(tacaw, ctx, oracle, job)
