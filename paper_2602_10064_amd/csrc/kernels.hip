@@ -312,12 +312,16 @@ __global__ void __launch_bounds__(256) k_splat(SplatTable tab) {
           int o = node0 - ip;
           if (o >= n_ax - n_ax / 2) o -= n_ax;
           if (o < -(n_ax / 2)) o += n_ax;
-          // node j sits at d = j - u pixels from the atom, u = f - o
+          // node j sits at d = j - u pixels from the atom, u = f - o.  Every
+          // node of a tile the term's box reaches gets the exact value (beyond
+          // the radius it is below 1e-8 of the peak, or underflows to 0; only
+          // this image reaches the tile), which saves the cutoff test.
           const float u = fp - (float)o;
+          const float ne2 = -e2;
 #pragma unroll
           for (int x = 0; x < SPLAT_TX; ++x) {
             const float d = (float)x - u;
-            dst[x * PS] = fabsf(d) <= rc ? amp * __builtin_amdgcn_exp2f(-e2 * d * d) : 0.f;
+            dst[x * PS] = amp * __builtin_amdgcn_exp2f(ne2 * d * d);
           }
         } else {
           const int img = along_y ? a.img_y : a.img_x;
