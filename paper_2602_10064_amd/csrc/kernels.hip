@@ -166,47 +166,17 @@ __device__ __forceinline__ float profile(int node, int ipos, float fpos, int n, 
   return g;
 }
 
-// Periodic distance in pixels from position u to the node interval [lo, hi].
-__device__ __forceinline__ float interval_distance(float u, int lo, int hi, int n) {
-  const float c = 0.5f * (float)(lo + hi), h = 0.5f * (float)(hi - lo);
-  float d = u - c;
-  d -= (float)n * rintf(d / (float)n);
-  return fmaxf(0.f, fabsf(d) - h);
-}
-
-// One workgroup computes a 32 x 64 tile of V for one (frame, slice).  Each
-// candidate atom contributes, per Gaussian term, an outer product of a column
-// profile and a row profile (the 2D Gaussian and its periodic images factor
-// into x and y parts); the profiles of up to SPLAT_MC atoms are staged in LDS
-// and every thread accumulates a 2 x 4 block of pixels.  Terms whose own
-// cutoff box misses the tile are skipped by a per-atom bit mask.  The
-// summation order is fixed, so the result is deterministic.
-// Per active (atom, term) pair of a tile: what the profile fill needs.
-struct PairData {
-  int ix, iy;     // atom pixel (for the general periodic-image path)
-  int ox, oy;     // minimal-image pixel offset of the tile's first node from the atom
-  float fx, fy;
-  float e2x, e2y, rcx, rcy, amp;
-};
-
-// Profile value at tile node `j` for a pair whose tile-origin offset is `o`:
-// d = (o + j) - f pixels.  Valid when no second periodic image can reach the
-// tile (then the minimal image of the origin stays minimal across the tile
-// for every node within the cutoff).
-__device__ __forceinline__ float profile_tile(int o, int j, float f, float e2, float rc) {
-  const float d = (float)(o + j) - f;
-  return fabsf(d) <= rc ? __builtin_amdgcn_exp2f(-e2 * d * d) : 0.f;
-}
-
-// One workgroup (4 wavefronts) computes a 32 x 32 tile of V for one (frame,
-// slice).  V_tile = Gy^T Gx, a sum over the tile's active (atom, term) pairs
-// of outer(row profile, column profile): the 2D Gaussian of a term and its
-// periodic images factor into x and y parts.  The profiles of up to 80 pairs
-// are built in LDS (a pair is active when its own cutoff box meets the
-// tile), then each wavefront accumulates one 16 x 16 quarter of the tile with
-// v_mfma_f32_16x16x4f32 (FP32 products and sums), four pairs per instruction.
-// The pair order and the instruction sequence are fixed, so the result is
-// deterministic.
+// Potentials: each wavefront computes one 32 x 32 tile of V for one slice
+// and up to `fpw` frames (four wavefronts per workgroup, independent after the
+// coefficients are staged).  V_tile = sum over the tile's candidate (atom,
+// term) pairs, from the planner's per-tile lists, of outer(row profile, column
+// profile): the 2D Gaussian of one term and its periodic images factor into x
+// and y parts.  Pairs go in rounds of 32: lanes 0-31 build the column profiles
+// and lanes 32-63 the row profiles (scaled by the term's amplitude), node-major
+// in LDS; then v_mfma_f32_16x16x4f32 adds four pairs per instruction to each
+// of the tile's four 16 x 16 quarters (FP32 products and sums).  Positions of
+// the first rounds are prefetched one frame ahead.  Pair order and instruction
+// sequence are fixed, so the result is deterministic.
 __global__ void __launch_bounds__(256) k_splat(SplatTable tab) {
   constexpr int MP = 32;          // pairs per round: one row profile and one column profile per lane
   // profiles in LDS as [node][pair], rows of PS = MP + 2 floats: a fill
