@@ -177,12 +177,18 @@ __device__ __forceinline__ float profile(int node, int ipos, float fpos, int n, 
 // of the tile's four 16 x 16 quarters (FP32 products and sums).  Positions of
 // the first rounds are prefetched one frame ahead.  Pair order and instruction
 // sequence are fixed, so the result is deterministic.
+template <int MP>
 __global__ void __launch_bounds__(256) k_splat(SplatTable tab) {
-  constexpr int MP = 32;          // pairs per round: one row profile and one column profile per lane
-  // profiles in LDS as [node][pair], rows of PS = MP + 2 floats: a fill
-  // instruction (32 lanes, one node, consecutive pairs) and an MFMA operand
-  // read (16 nodes x 2 pairs, node stride 2 banks) both hit 32 distinct banks
-  constexpr int PS = MP + 2;
+  // MP pairs per round (32 or 16).  Lanes split into 64 / MP parts of MP
+  // lanes; each part fills NPL = MP nodes of the column (x) or row (y)
+  // profiles of the round's pairs.
+  static_assert(MP == 32 || MP == 16, "round sizes 32 and 16");
+  constexpr int NPL = MP;                 // profile nodes per lane
+  constexpr int PARTS_PER_AXIS = 32 / MP;
+  // profiles in LDS as [node][pair], rows of PS floats: a fill instruction
+  // (32 lanes: consecutive pairs of one or two nodes) and an MFMA operand
+  // read (16 nodes x 2 pairs) both hit 32 distinct banks
+  constexpr int PS = MP == 32 ? MP + 2 : MP + 1;
   static_assert(SPLAT_TX == 32 && SPLAT_TY == 32, "MFMA tiling assumes 32 x 32 tiles");
   __shared__ float gxs[4][SPLAT_TX][PS];
   __shared__ float gys[4][SPLAT_TY][PS];
@@ -218,9 +224,11 @@ __global__ void __launch_bounds__(256) k_splat(SplatTable tab) {
   const bool simple_y = a.img_y == 0 && 2 * (a.rcy + SPLAT_TY + 2) < a.pny;
   float (*gx)[PS] = gxs[wave];
   float (*gy)[PS] = gys[wave];
-  const int pr = lane % MP;         // pair of this lane
-  const bool along_y = lane >= MP;  // lanes 0-31 build column profiles, 32-63 row profiles
-  float* dst = along_y ? &gy[0][pr] : &gx[0][pr];   // node j at dst[j * PS]
+  const int pr = lane % MP;                       // pair of this lane
+  const int part = lane / MP;
+  const bool along_y = part >= PARTS_PER_AXIS;    // lanes 0-31: column profiles, 32-63: row profiles
+  const int nbase = (part % PARTS_PER_AXIS) * NPL;  // first profile node of this lane
+  float* dst = along_y ? &gy[nbase][pr] : &gx[nbase][pr];   // node nbase + j at dst[j * PS]
   typedef float v4f __attribute__((ext_vector_type(4)));
 
   // per round: this lane's atom and coefficients are the same for every
@@ -286,20 +294,21 @@ __global__ void __launch_bounds__(256) k_splat(SplatTable tab) {
           // node of a tile the term's box reaches gets the exact value (beyond
           // the radius it is below 1e-8 of the peak, or underflows to 0; only
           // this image reaches the tile), which saves the cutoff test.
-          const float u = fp - (float)o;
+          const float u = fp - (float)(o + nbase);
           const float ne2 = -e2;
 #pragma unroll
-          for (int x = 0; x < SPLAT_TX; ++x) {
+          for (int x = 0; x < NPL; ++x) {
             const float d = (float)x - u;
             dst[x * PS] = amp * __builtin_amdgcn_exp2f(ne2 * d * d);
           }
         } else {
           const int img = along_y ? a.img_y : a.img_x;
-          for (int x = 0; x < SPLAT_TX; ++x) dst[x * PS] = amp * profile(node0 + x, ip, fp, n_ax, e2, rc, img);
+          for (int x = 0; x < NPL; ++x)
+            dst[x * PS] = amp * profile(node0 + nbase + x, ip, fp, n_ax, e2, rc, img);
         }
       } else if (pr < mp4) {
 #pragma unroll
-        for (int x = 0; x < SPLAT_TX; ++x) dst[x * PS] = 0.f;
+        for (int x = 0; x < NPL; ++x) dst[x * PS] = 0.f;
       }
       wave_lds_sync();
       // V[r][c] += sum_k gy[k][r] gx[k][c] over four 16 x 16 quarters; A is 16 x 4
@@ -1131,11 +1140,10 @@ hipError_t launch_splat_lanes(const SplatLane* lanes, int n, hipStream_t s) {
   SplatTable t{};
   t.n = n;
   int blocks = 0;
-  static const int fpw_env = [] {
-    const char* e = getenv("TACAW_SPLAT_FPW");
-    const int v = e ? atoi(e) : 0;
-    return v >= 1 && v <= 64 ? v : SPLAT_FPW;
-  }();
+  // TACAW_SPLAT_FPW and TACAW_SPLAT_ROUND are read at every launch
+  const char* fe = getenv("TACAW_SPLAT_FPW");
+  const int fpw_v = fe ? atoi(fe) : 0;
+  const int fpw_env = fpw_v >= 1 && fpw_v <= 64 ? fpw_v : SPLAT_FPW;
   for (int i = 0; i < n; ++i) {
     t.l[i] = lanes[i];
     t.l[i].block_start = blocks;
@@ -1145,7 +1153,13 @@ hipError_t launch_splat_lanes(const SplatLane* lanes, int n, hipStream_t s) {
                       ((a.fb + fpw_env - 1) / fpw_env);  // one per wavefront
     blocks += (items + 3) / 4;
   }
-  TACAW_LAUNCH(k_splat, dim3(blocks), dim3(256), 0, s, t);
+  // pairs per round: TACAW_SPLAT_ROUND (16 or 32; default 32)
+  const char* re = getenv("TACAW_SPLAT_ROUND");
+  const int round = re && atoi(re) == 16 ? 16 : 32;
+  if (round == 16)
+    TACAW_LAUNCH((k_splat<16>), dim3(blocks), dim3(256), 0, s, t);
+  else
+    TACAW_LAUNCH((k_splat<32>), dim3(blocks), dim3(256), 0, s, t);
   return hipGetLastError();
 }
 

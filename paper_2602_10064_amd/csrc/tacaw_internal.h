@@ -30,7 +30,8 @@ struct SplatArgs {
   const int32_t* tile_atoms;   // candidate pairs: sorted-atom index * 8 + Gaussian term
   const float* coef;           // [S][5][COEF_STRIDE]: amplitude (V A), exp2 factor per pixel^2
                                // along x and y, truncation radius in pixels along x and y
-  float* V;                    // [fb][gridDim.y][pny][pnx]: slices slice0 .. slice0+gridDim.y-1
+  float* V;                    // [fb][n][pny][pnx]: slices slice0 .. slice0+n-1, n = the lane's
+                               // n_slices_launch
   int n_atoms, n_species, f0, fb, n_slices, slice0, pnx, pny, tiles_x, tiles_y;
   float rcx, rcy;              // truncation radius in pixels along x and y
   int img_x, img_y;            // periodic images -img..img searched per axis
@@ -39,7 +40,7 @@ struct SplatArgs {
 // One row or column pass over a batch of (probe, frame) waves.
 struct PassArgs {
   float2* exit;                // [P][F][ny][nx] exit store, also the in-flight waves
-  const float* V;              // [fb][v_slices][pny][pnx], holding slices v_slice0 ..
+  const float* V;              // [fb][v_slices][pny][pnx]: slices v_slice0 .. v_slice0+v_slices-1
   const float2* probe0;        // [P][ny][nx] incident probes (real space)
   const int32_t* origin;       // [P][2] window origin on the potential grid
   const float2* tw_x;          // [nx] exp(-2 pi i m / nx)
@@ -85,12 +86,14 @@ struct SplatTable {
 enum RowMode { ROW_FIRST = 0, ROW_REGULAR = 1, ROW_INVERSE_ONLY = 2 };
 enum ColMode { COL_REGULAR = 0, COL_LAST = 1, COL_INVERSE_ONLY = 2 };
 
+// Events the next main-kernel launch on this thread records itself (start
+// and end of the kernel); cleared by that launch.
+void set_launch_events(hipEvent_t start, hipEvent_t stop);
+
 // Kernel launchers (kernels.hip).  Each returns hipSuccess or the launch error.
 bool grid_supported(int n);
 hipError_t launch_splat(const SplatArgs& a, int n_slices_launch, hipStream_t s);
 hipError_t launch_row_pass(const PassArgs& a, int mode, hipStream_t s);
-// Events the next main-kernel launch on this thread records around itself.
-void set_launch_events(hipEvent_t start, hipEvent_t stop);
 hipError_t launch_row_lanes(const PassLane* lanes, int n, int variant, hipStream_t s);
 hipError_t launch_col_lanes(const PassLane* lanes, int n, int variant, hipStream_t s);
 hipError_t launch_splat_lanes(const SplatLane* lanes, int n, hipStream_t s);

@@ -248,6 +248,17 @@ def test_c2_shape_register_column_kernels(tacaw, ctx, oracle, monkeypatch, varia
     check_job(tacaw, ctx, oracle, job)
 
 
+def test_splat_rounds_of_16(tacaw, ctx, oracle, monkeypatch):
+    # potentials built in rounds of 16 (atom, term) pairs: same values as
+    # rounds of 32 up to the order of the FP32 sums, parity with the oracle
+    job = w.c1_tiny(n_frames=16)
+    _, a, _ = run_gpu(tacaw, ctx, job)
+    monkeypatch.setenv("TACAW_SPLAT_ROUND", "16")
+    check_job(tacaw, ctx, oracle, job)
+    _, b, _ = run_gpu(tacaw, ctx, job)
+    assert rel_l2(b, a) < 1e-5
+
+
 def test_splat_slice_groups_bitwise(tacaw, ctx, monkeypatch):
     # potentials of several slices per launch (8 slices in groups of 3: 3+3+2)
     job = w.c1_tiny(n_frames=16)
