@@ -55,7 +55,7 @@ tacaw_status validate_desc(const tacaw_job_desc* d);
 int choose_frame_batch(const tacaw_job_desc* d);
 bool splat_per_slice();
 bool overlap_splat();
-int splat_group(int n_slices);
+int splat_group(int n_slices, int fb, int pnx, int pny);
 Footprint footprint_of(const tacaw_job_desc* d, int fb, size_t n_tile_atoms_estimate);
 double wavelength_A(double volt);
 double sigma_rad_per_VA(double volt);
