@@ -231,11 +231,24 @@ tacaw_status tacaw_run_batch(tacaw_job* const* jobs, int n_jobs, void* hip_strea
   tacaw_status st = ensure_streams(c);
   if (st != TACAW_OK) return st;
   hipStream_t user = (hipStream_t)hip_stream;
+  // Jobs whose frame batches hold at least TACAW_BATCH_LARGE_MB (default 64)
+  // MiB of waves fill the device on their own: they run one after another on
+  // the first stream, exactly as the plain form runs them (sharing launches
+  // would only make the working set outgrow the last-level cache).  The
+  // smaller jobs share launches, grouped by grid, on the other streams.
+  double large_mb = 64.0;
+  if (const char* e = getenv("TACAW_BATCH_LARGE_MB")) large_mb = atof(e);
   std::map<std::pair<int, int>, std::vector<tacaw_job*>> groups;
+  std::vector<tacaw_job*> large;
   for (int i = 0; i < n_jobs; ++i) {
     st = materialize(jobs[i], nullptr);
     if (st != TACAW_OK) return st;
-    groups[{jobs[i]->hp.nx, jobs[i]->hp.ny}].push_back(jobs[i]);
+    const HostPlan& hp = jobs[i]->hp;
+    const double wave_mb = (double)hp.fb * hp.P * hp.nx * hp.ny * 8.0 / (1 << 20);
+    if (wave_mb >= large_mb)
+      large.push_back(jobs[i]);
+    else
+      groups[{hp.nx, hp.ny}].push_back(jobs[i]);
   }
   hipEvent_t start;
   if (hipEventCreateWithFlags(&start, hipEventDisableTiming) != hipSuccess) {
@@ -245,18 +258,48 @@ tacaw_status tacaw_run_batch(tacaw_job* const* jobs, int n_jobs, void* hip_strea
   (void)hipEventRecord(start, user);
   std::vector<GroupRun> runs;
   bool used[4] = {false, false, false, false};
-  int n_streams = 4;   // TACAW_BATCH_STREAMS: streams the groups spread over (1-4)
+  int n_streams = 4;   // TACAW_BATCH_STREAMS: streams the work spreads over (1-4)
   if (const char* e = getenv("TACAW_BATCH_STREAMS")) n_streams = std::max(1, std::min(4, atoi(e)));
+  const int first_group_stream = (large.empty() || n_streams == 1) ? 0 : 1;
   for (auto& g : groups) {
-    const int k = (int)runs.size() % n_streams;
+    const int span = n_streams - first_group_stream;
+    const int k = first_group_stream + (int)runs.size() % span;
     if (!used[k]) (void)hipStreamWaitEvent(c->batch_streams[k], start, 0);
     used[k] = true;
     runs.emplace_back(c, g.second, c->batch_streams[k]);
   }
+  // the large jobs advance one frame batch per round of the loop below
+  size_t li = 0;
+  int lf = 0;
+  hipStream_t s0 = c->batch_streams[0];
+  if (!large.empty()) {
+    if (!used[0]) (void)hipStreamWaitEvent(s0, start, 0);
+    used[0] = true;
+  }
+  auto large_step = [&]() -> tacaw_status {
+    tacaw_job* j = large[li];
+    const int f1 = std::min(lf + j->hp.fb, j->hp.F);
+    tacaw_status r = run_batch_range(j, s0, lf, f1);
+    if (r != TACAW_OK) return r;
+    lf = f1;
+    if (lf == j->hp.F) {
+      r = run_time_stage(j, s0);
+      if (r != TACAW_OK) return r;
+      j->has_result = true;
+      ++li;
+      lf = 0;
+    }
+    return TACAW_OK;
+  };
   // enqueue the groups' iterations round-robin, so that every stream has
   // work queued while the others run
-  for (bool more = true; more && st == TACAW_OK;) {
+  for (bool more = st == TACAW_OK; more && st == TACAW_OK;) {
     more = false;
+    if (li < large.size()) {
+      st = large_step();
+      if (st != TACAW_OK) break;
+      more = true;
+    }
     for (auto& r : runs) {
       if (r.done()) continue;
       st = r.step();

@@ -44,9 +44,13 @@ def plain_results(tacaw, ctx, jobs):
     return out
 
 
-def test_run_batch_equals_plain_bitwise(tacaw, monkeypatch):
+@pytest.mark.parametrize("large_mb", ["64", "0", "0.3"], ids=["shared", "sequential", "mixed"])
+def test_run_batch_equals_plain_bitwise(tacaw, monkeypatch, large_mb):
+    # shared launches for every job, one after another for every job, or both
+    # (the 256^2 job and the 3-probe job count as large at 0.3 MiB of waves)
     jobs = uneven_jobs()
     monkeypatch.setenv("TACAW_FB", "5")          # several frame batches per job, ragged tails
+    monkeypatch.setenv("TACAW_BATCH_LARGE_MB", large_mb)
     with tacaw.Context(0) as ctx:
         ref = plain_results(tacaw, ctx, jobs)
         hs = [tacaw.TacawJob(ctx, j) for j in jobs]
