@@ -325,12 +325,11 @@ tacaw_status plan_job(const tacaw_job_desc* d, const int32_t* atom_species, cons
     }
 
   // Candidate (atom, term) pairs per (slice, tile): a term of an atom is listed
-  // for a tile when its own truncation box, widened by the largest
-  // displacement of any atom from its mean position (and two pixels), can
-  // reach the tile along both axes (periodic).  Entries are sorted-atom * 8 +
-  // term, in atom order then term order.
-  std::vector<double> xbar(hp.A), ybar(hp.A);
-  double dmx = 0.0, dmy = 0.0;
+  // for a tile when its own truncation box, widened by that atom's largest
+  // displacement from its mean position (and half a pixel for the rounding
+  // of positions), can reach the tile along both axes (periodic).  Entries
+  // are sorted-atom * 8 + term, in atom order then term order.
+  std::vector<double> xbar(hp.A), ybar(hp.A), dmx(hp.A, 0.0), dmy(hp.A, 0.0);
   for (int j = 0; j < hp.A; ++j) {
     const double x0 = pos[(size_t)j * 3], y0 = pos[(size_t)j * 3 + 1];
     double sx = 0.0, sy = 0.0;
@@ -343,8 +342,8 @@ tacaw_status plan_job(const tacaw_job_desc* d, const int32_t* atom_species, cons
   }
   for (int f = 0; f < hp.F; ++f)
     for (int j = 0; j < hp.A; ++j) {
-      dmx = std::max(dmx, fabs(wrap_min_image(pos[((size_t)f * hp.A + j) * 3] - xbar[j], hp.lx)));
-      dmy = std::max(dmy, fabs(wrap_min_image(pos[((size_t)f * hp.A + j) * 3 + 1] - ybar[j], hp.ly)));
+      dmx[j] = std::max(dmx[j], fabs(wrap_min_image(pos[((size_t)f * hp.A + j) * 3] - xbar[j], hp.lx)));
+      dmy[j] = std::max(dmy[j], fabs(wrap_min_image(pos[((size_t)f * hp.A + j) * 3 + 1] - ybar[j], hp.ly)));
     }
   hp.tiles_x = (hp.pnx + SPLAT_TX - 1) / SPLAT_TX;
   hp.tiles_y = (hp.pny + SPLAT_TY - 1) / SPLAT_TY;
@@ -370,8 +369,8 @@ tacaw_status plan_job(const tacaw_job_desc* d, const int32_t* atom_species, cons
       const int sp = hp.sorted_species[j];
       for (int i = 0; i < N_GAUSS; ++i) {
         const double rci = sqrt(d->gauss_b[sp * N_GAUSS + i] * log(1e8)) / M_PI;
-        reached(xbar[oj], hp.lx, hp.dx, hp.pnx, SPLAT_TX, hp.tiles_x, rci + dmx + 2.0 * hp.dx, txs);
-        reached(ybar[oj], hp.ly, hp.dy, hp.pny, SPLAT_TY, hp.tiles_y, rci + dmy + 2.0 * hp.dy, tys);
+        reached(xbar[oj], hp.lx, hp.dx, hp.pnx, SPLAT_TX, hp.tiles_x, rci + dmx[oj] + 0.5 * hp.dx, txs);
+        reached(ybar[oj], hp.ly, hp.dy, hp.pny, SPLAT_TY, hp.tiles_y, rci + dmy[oj] + 0.5 * hp.dy, tys);
         for (int ty : tys)
           for (int tx : txs) bucket[ty * hp.tiles_x + tx].push_back((int32_t)(j * 8 + i));
       }
