@@ -1089,7 +1089,11 @@ static hipError_t col_r8_launch(PassTable& t, hipStream_t s) {
     t.l[i].block_start = tiles;
     tiles += a.n_probes * a.fb * (a.nx / CT);
   }
-  const int grid = std::min(tiles, 2048);
+  // resident workgroups walk the tiles with a grid stride (each prefetches
+  // its next tile); TACAW_COL_GRID caps the grid (default 2048)
+  const char* ge = getenv("TACAW_COL_GRID");
+  const int cap = ge && atoi(ge) > 0 ? atoi(ge) : 2048;
+  const int grid = std::min(tiles, cap);
   TACAW_LAUNCH((k_col_r8<N, WIDE>), dim3(grid), dim3(C8<N, WIDE>::THREADS), 0, s, t, tiles);
   return hipGetLastError();
 }
