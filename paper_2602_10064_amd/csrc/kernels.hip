@@ -748,7 +748,10 @@ struct C8 {
   static constexpr int THREADS = WAVES * 64;
 };
 
-template <int N, int WIDE>
+// DB = 1: two LDS tile buffers in turn, so a tile's transposed stores and the
+// next tile's staging need no barrier between them (two barriers per tile
+// instead of three).
+template <int N, int WIDE, int DB>
 __global__ void __launch_bounds__((C8<N, WIDE>::THREADS)) k_col_r8(PassTable tab, int total_tiles) {
   constexpr int G = C8<N, WIDE>::G;
   constexpr int CPW = C8<N, WIDE>::CPW;
@@ -757,12 +760,11 @@ __global__ void __launch_bounds__((C8<N, WIDE>::THREADS)) k_col_r8(PassTable tab
   constexpr int S = R8<N>::S;
   constexpr int THREADS = C8<N, WIDE>::THREADS;
   constexpr int PER = CT * N / THREADS;  // tile values each thread moves
-  __shared__ float2 cols[CT * LD];
+  __shared__ float2 cols_mem[(DB ? 2 : 1) * CT * LD];
   const int wave = threadIdx.x / 64;
   const int lane = threadIdx.x % 64;
   const int cl = wave * CPW + lane / G;  // this lane's column in the tile
   const int t = lane % G;
-  float2* lds = cols + cl * LD;
   // padded LDS slots: this lane's FFT values (t + G r) and its transpose
   // element (column e mod CT, row e / CT, e = threadIdx.x + q THREADS; the
   // row step THREADS / CT is a multiple of 8)
@@ -800,12 +802,16 @@ __global__ void __launch_bounds__((C8<N, WIDE>::THREADS)) k_col_r8(PassTable tab
       pre[q] = wp[(size_t)(e / CT) * nx + x0 + e % CT];
     }
   }
-  for (; it < total_tiles; it += gridDim.x) {
+  for (int n_done = 0; it < total_tiles; it += gridDim.x, ++n_done) {
     const PassArgs& a = tab.l[L].a;
     const int mode = tab.l[L].mode;
     const int cur_x0 = x0;
     float2* cur_wp = wp;
-    __syncthreads();  // the previous tile's stores from LDS are done
+    float2* cols = cols_mem + (DB ? (n_done & 1) * CT * LD : 0);
+    float2* lds = cols + cl * LD;
+    // single buffer: the previous tile's stores from LDS must be done; two
+    // buffers: this one was last read two tiles ago, before the last barrier
+    if (!DB) __syncthreads();
 #pragma unroll
     for (int q = 0; q < PER; ++q) cols[tslot + q * (THREADS / CT + THREADS / CT / 8)] = pre[q];
     // issue the next tile's loads; they complete during this tile's arithmetic
@@ -1079,7 +1085,7 @@ hipError_t launch_row_lanes(const PassLane* lanes, int n, int variant, hipStream
   }
 }
 
-template <int N, int WIDE>
+template <int N, int WIDE, int DB = 0>
 static hipError_t col_r8_launch(PassTable& t, hipStream_t s) {
   constexpr int CT = C8<N, WIDE>::CT;
   int tiles = 0;
@@ -1094,7 +1100,7 @@ static hipError_t col_r8_launch(PassTable& t, hipStream_t s) {
   const char* ge = getenv("TACAW_COL_GRID");
   const int cap = ge && atoi(ge) > 0 ? atoi(ge) : 2048;
   const int grid = std::min(tiles, cap);
-  TACAW_LAUNCH((k_col_r8<N, WIDE>), dim3(grid), dim3(C8<N, WIDE>::THREADS), 0, s, t, tiles);
+  TACAW_LAUNCH((k_col_r8<N, WIDE, DB>), dim3(grid), dim3(C8<N, WIDE>::THREADS), 0, s, t, tiles);
   return hipGetLastError();
 }
 
@@ -1103,6 +1109,12 @@ hipError_t launch_col_lanes(const PassLane* lanes, int n, int variant, hipStream
   PassTable t{};
   t.n = n;
   for (int i = 0; i < n; ++i) t.l[i] = lanes[i];
+  if (variant == 4) {
+    const int ny = lanes[0].a.ny, nx = lanes[0].a.nx;
+    if (ny == 512 && nx % C8<512, 0>::CT == 0) return col_r8_launch<512, 0, 1>(t, s);
+    if (ny == 256 && nx % C8<256, 0>::CT == 0) return col_r8_launch<256, 0, 1>(t, s);
+    variant = 2;
+  }
   if (variant == 3) {
     if (lanes[0].a.ny == 512 && lanes[0].a.nx % C8<512, 1>::CT == 0) return col_r8_launch<512, 1>(t, s);
     variant = 2;

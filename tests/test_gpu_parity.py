@@ -241,9 +241,10 @@ def test_overlapped_potentials_graph_replay(tacaw, ctx, monkeypatch):
             (x * 2).sum().item()
 
 
-@pytest.mark.parametrize("variant", ["2", "3"])
+@pytest.mark.parametrize("variant", ["2", "3", "4"])
 def test_c2_shape_register_column_kernels(tacaw, ctx, oracle, monkeypatch, variant):
-    # register radix-8 column pass on 8-column (2) and 16-column (3) tiles
+    # register column pass on 8-column tiles (2), 16-column tiles (3) and
+    # 8-column tiles with two LDS buffers (4)
     monkeypatch.setenv("TACAW_COL_VARIANT", variant)
     monkeypatch.setenv("TACAW_FB", "3")
     job = w.c2_plain(n_frames=5)
