@@ -316,11 +316,15 @@ def main():
         units = job.nx * job.ny * job.n_probes * j.plan()[0]
         avg_ms = ms / n
         achieved = BYTES_PER_UNIT[dom] * units / (avg_ms * 1e-3) / 1e9
+        # counter-measured HBM bytes per launch, when they were taken for this
+        # grid and frame batch with the kernels as they are now
         traffic = None
         tpath = os.path.join(ROOT, "profiles", "traffic.json")
         if os.path.exists(tpath):
             tr = json.load(open(tpath))
-            if tr.get("source_hash") == kernel_source_hash() and dom in tr.get("per_launch_bytes", {}):
+            if (tr.get("source_hash") == kernel_source_hash() and dom in tr.get("per_launch_bytes", {})
+                    and tr.get("grid") == [job.nx, job.ny] and tr.get("frame_batch") == j.plan()[0]
+                    and tr.get("probes") == job.n_probes):
                 traffic = tr["per_launch_bytes"][dom]
         roofline = {"bound": "hbm", "kernel": f"{dom} pass", "achieved": round(achieved, 1),
                     "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
