@@ -68,9 +68,12 @@ typedef struct tacaw_job tacaw_job;
  * q in cycles/A, a in A, b in A^2, C = 2 pi a0 e = 47.8776 V A^2.  Its
  * projected potential v_s(r) = C sum_i a_i (pi/b_i) exp(-pi^2 r^2 / b_i) (V A)
  * is point-sampled at grid nodes r_p = (p_x Lx/Nx, p_y Ly/Ny) and summed over
- * the atoms of a slice and their periodic images.  The library truncates each
- * Gaussian term of an atom (box cutoff per axis) at r_i = sqrt(b_i ln 1e8)/pi,
- * where it has fallen below 1e-8 of its peak.
+ * the atoms of a slice and their periodic images.  The library evaluates each
+ * Gaussian term of an atom exactly on the 32 x 32 tiles of the potential grid
+ * that its box of half-width r_i = sqrt(b_i ln 1e8)/pi (the radius where the
+ * term has fallen to 1e-8 of its peak), widened by the atom's largest
+ * displacement from its mean position, reaches; other tiles get nothing from
+ * that term.
  *
  * Slices (Methods 2.2, "atoms within the slice z-bounds"): atom j belongs to
  * slice floor((zbar_j mod Lz)/dz), clamped to [0, n_slices), where zbar_j is
@@ -101,7 +104,9 @@ typedef struct tacaw_job tacaw_job;
  */
 typedef struct {
   double cell[3];              /* orthorhombic Lx, Ly, Lz [A], all > 0                  */
-  int32_t nx, ny;              /* wave grid; each a product of 2, 3, 5 (EINVAL otherwise) */
+  int32_t nx, ny;              /* wave grid; each a product of 2, 3, 5 (EINVAL otherwise);
+                                  EUNSUPPORTED for sizes without compiled FFT plans:
+                                  16 32 48 64 96 128 160 192 256 320 384 512 640 768 1024 */
   int32_t n_slices;            /* >= 1                                                   */
   double voltage_V;            /* beam energy [V], > 0                                   */
   double aperture_mrad;        /* 0 -> plane wave; > 0 -> probe semi-angle [mrad]        */
@@ -156,23 +161,26 @@ tacaw_status tacaw_job_create(tacaw_ctx* ctx, const tacaw_job_desc* desc,
 tacaw_status tacaw_run(tacaw_job* job, void* hip_stream);
 
 /* Batched form for uneven jobs (several grids, slice and frame counts): run
- * n_jobs jobs of one context together, ordered on `hip_stream`.  Jobs with
- * the same grid share launches: each launch advances up to 8 frame batches
- * of different jobs by one pass, each at its own slice, and a finished frame
- * batch is replaced by the next one at once.  Groups of different grid sizes
- * run on the context's own streams and are joined back to `hip_stream`.
- * Every result equals the job's tacaw_run result bit for bit. */
+ * n_jobs jobs of one context together, ordered on `hip_stream`.  Jobs whose
+ * frame batches fill the device on their own (at least 64 MiB of waves,
+ * $TACAW_BATCH_LARGE_MB) run one after another on one of the context's
+ * streams.  The smaller jobs with the same grid share launches: each launch
+ * advances up to 8 frame batches of different jobs by one pass, each at its
+ * own slice, and a finished frame batch is replaced by the next one at once;
+ * groups of different grid sizes run on the context's other streams.  All
+ * streams are joined back to `hip_stream`.  Every result equals the job's
+ * tacaw_run result bit for bit. */
 tacaw_status tacaw_run_batch(tacaw_job* const* jobs, int n_jobs, void* hip_stream);
 
 /* Autotuner: time the row-pass variants (rows per workgroup, and for grids
  * of 64 to 512 register-resident kernels with one or two rows in flight) and
- * the column-pass
- * variants (tile widths, and for 64 and 512 rows register-resident radix-8
- * kernels on 8- or 16-column tiles) on one frame batch of `job` and keep the
- * faster of each for the job's grid size in the context (appended to the
- * JSON-lines file named by $TACAW_TUNE_CACHE, read back by later contexts).
- * Writes the chosen variants (row 0-3, column 0-3) when the pointers are not
- * NULL.  Resets the context's timing totals. */
+ * the column-pass variants (tile widths, and for 64 to 512 rows
+ * register-resident kernels on 8- to 32-column tiles, 16-column tiles at 512)
+ * on one frame batch of `job` and keep the faster of each for the job's grid
+ * size in the context (appended to the JSON-lines file named by
+ * $TACAW_TUNE_CACHE, read back by later contexts).  Writes the chosen
+ * variants (row 0-3, column 0-3) when the pointers are not NULL.  Resets the
+ * context's timing totals. */
 tacaw_status tacaw_autotune(tacaw_job* job, void* hip_stream, int* row_variant, int* col_variant);
 
 /* Serving form: hand the job to the context's continuous-batching loop.
