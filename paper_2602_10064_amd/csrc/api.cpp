@@ -103,7 +103,9 @@ namespace tacaw {
 // width, 1: full width, 2: register kernel on 8-16 column tiles for 64-512
 // rows, 3: 16-column register tiles for 512 rows).  Tuned choices win;
 // $TACAW_ROW_VARIANT and $TACAW_COL_VARIANT override untuned defaults.
-static bool has_register_fft(int n) { return n == 64 || n == 128 || n == 256 || n == 512; }
+static bool has_register_fft(int n) {
+  return n == 64 || n == 128 || n == 256 || n == 384 || n == 512 || n == 768 || n == 1024;
+}
 int row_variant_for(tacaw_ctx* c, int n) {
   const int v = (n > 0 && n < 2048) ? c->row_variant[n] : 0;
   if (v) return v - 1;

@@ -342,7 +342,7 @@ tacaw_status tacaw_autotune(tacaw_job* job, void* hip_stream, int* row_variant, 
   // in flight, grids 64-512);
   // column variants: 0, 1 (LDS columns), 2 (register FFT on 8-32 column
   // tiles, ny 64-512), 3 (16-column tiles, ny 512)
-  auto reg = [](int n) { return n == 64 || n == 128 || n == 256 || n == 512; };
+  auto reg = [](int n) { return n == 64 || n == 128 || n == 256 || n == 384 || n == 512 || n == 768 || n == 1024; };
   const int n_row_var = reg(hp.nx) ? 4 : 2;
   const int n_col_var = hp.ny == 512 ? 4 : reg(hp.ny) ? 3 : 2;
   const int n_var = std::max(n_row_var, n_col_var);

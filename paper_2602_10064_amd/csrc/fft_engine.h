@@ -86,6 +86,27 @@ __device__ __forceinline__ void dft5(float2* x) {
   x[3] = csub(r2, i2);
 }
 
+// 6-point DFT: two 3-point DFTs (even and odd inputs), the odd outputs
+// rotated by W6^k, then 2-point butterflies.
+template <bool INV>
+__device__ __forceinline__ void dft6(float2* x) {
+  const float h = 0.5f, s = 0.86602540378443864676f;
+  float2 e[3] = {x[0], x[2], x[4]};
+  float2 o[3] = {x[1], x[3], x[5]};
+  dft3<INV>(e);
+  dft3<INV>(o);
+  // W6^1 = (1/2, -s), W6^2 = (-1/2, -s) forward; conjugates inverse
+  const float sg = INV ? s : -s;
+  const float2 o1 = make_float2(h * o[1].x - sg * o[1].y, h * o[1].y + sg * o[1].x);
+  const float2 o2 = make_float2(-h * o[2].x - sg * o[2].y, -h * o[2].y + sg * o[2].x);
+  x[0] = cadd(e[0], o[0]);
+  x[3] = csub(e[0], o[0]);
+  x[1] = cadd(e[1], o1);
+  x[4] = csub(e[1], o1);
+  x[2] = cadd(e[2], o2);
+  x[5] = csub(e[2], o2);
+}
+
 template <bool INV>
 __device__ __forceinline__ void dft8(float2* x) {
   const float h = 0.70710678118654752440f;
@@ -115,6 +136,7 @@ __device__ __forceinline__ void dft(float2* x) {
   else if constexpr (R == 3) dft3<INV>(x);
   else if constexpr (R == 4) dft4<INV>(x);
   else if constexpr (R == 5) dft5<INV>(x);
+  else if constexpr (R == 6) dft6<INV>(x);
   else if constexpr (R == 8) dft8<INV>(x);
   else static_assert(R == 2, "unsupported radix");
 }

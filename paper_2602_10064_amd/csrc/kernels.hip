@@ -851,6 +851,302 @@ __global__ void __launch_bounds__((C8<N, WIDE>::THREADS)) k_col_r8(PassTable tab
 }
 
 // ---------------------------------------------------------------------------
+// Register FFTs with 12 or 16 values per lane (N = 384 and 768: 12 values,
+// radices 6, 4, 4, 4 [, 2]; N = 1024: 16 values, radices 8, 8, 4, 4).  Same
+// layout and wavefront-local exchanges as the 8-value kernels; the stage
+// twiddles are read from a table in LDS, since the register file cannot hold
+// them beside 12-16 values and their prefetch.  PAD selects the padded LDS
+// slots (element i in slot i + i/8) or plain ones.
+// ---------------------------------------------------------------------------
+template <int N>
+struct RV {
+  static constexpr int V = N == 1024 ? 16 : 12;   // values per lane
+  static constexpr int G = N / V;                 // lanes per row
+  static constexpr int RPW = 64 / G;              // rows per wavefront
+  static constexpr int S = N == 384 ? 4 : N == 768 ? 5 : N == 1024 ? 4 : 0;
+  static constexpr int radix(int j) { return N == 1024 ? (j < 2 ? 8 : 4) : (j == 0 ? 6 : j < 4 ? 4 : 2); }
+  static constexpr int stride(int j) { return j == 0 ? 1 : stride(j - 1) * radix(j - 1); }
+  // per-lane twiddles of stages 1 .. J-1: (R - 1) Q each
+  static constexpr int tw_offset(int j) {
+    return j <= 1 ? 0 : tw_offset(j - 1) + (radix(j - 1) - 1) * (V / radix(j - 1));
+  }
+  static constexpr int NT = tw_offset(S);          // twiddles per lane
+  static_assert(S > 0 && G <= 64 && G % 8 == 0, "register FFT sizes 384, 768, 1024");
+  static_assert(stride(S - 1) * radix(S - 1) == N, "radices multiply to N");
+};
+
+// Per-lane stage twiddles in LDS, laid out [twiddle][lane t] (NT x G), so a
+// lane reads twiddle i at a fixed offset from its own slot: entry
+// tw_offset(J) + q (R - 1) + r - 1 of stage J is W_{PR}^{r (b mod P)},
+// b = t + G q.  Built from the FP64-derived table `tw` (N entries).
+template <int N>
+__device__ __forceinline__ void build_lane_twiddles(float2* twl, const float2* tw) {
+  constexpr int G = RV<N>::G, V = RV<N>::V, S = RV<N>::S;
+  for (int e = threadIdx.x; e < RV<N>::NT * G; e += blockDim.x) {
+    const int i = e / G, t = e % G;
+    int j = 1, off = 0, P = RV<N>::radix(0);
+    while (j < S - 1 && i >= off + (RV<N>::radix(j) - 1) * (V / RV<N>::radix(j))) {
+      off += (RV<N>::radix(j) - 1) * (V / RV<N>::radix(j));
+      P *= RV<N>::radix(j);
+      ++j;
+    }
+    const int R = RV<N>::radix(j);
+    const int q = (i - off) / (R - 1), r = (i - off) % (R - 1) + 1;
+    const int k = (t + G * q) % P;
+    twl[e] = tw[r * k * (N / (P * R))];
+  }
+}
+
+template <int N, bool INV, bool PAD, int J>
+__device__ __forceinline__ void rv_fft_stage(float2 (&x)[RV<N>::V], float2* lds, const float2* twl, int t) {
+  constexpr int V = RV<N>::V, S = RV<N>::S, G = RV<N>::G;
+  constexpr int R = RV<N>::radix(J), P = RV<N>::stride(J), Q = V / R;
+  static_assert(V % R == 0, "the radix divides the values per lane");
+  if constexpr (J > 0) {
+    // input r of butterfly q takes W_{PR}^{r (b mod P)}, b = t + G q, from
+    // this lane's column of the twiddle table
+    constexpr int OFF = RV<N>::tw_offset(J);
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        const float2 w = twl[(OFF + q * (R - 1) + r - 1) * G + t];
+        x[q + Q * r] = INV ? cmulc(x[q + Q * r], w) : cmul(x[q + Q * r], w);
+      }
+  }
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    float2 y[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) y[r] = x[q + Q * r];
+    dft<R, INV>(y);
+#pragma unroll
+    for (int r = 0; r < R; ++r) x[q + Q * r] = y[r];
+  }
+  if constexpr (J < S - 1) {
+    wave_lds_sync();  // earlier reads of lds by this wavefront are done
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int b = t + G * q;
+      const int k = b % P;
+      const int base = (b - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int pos = base + r * P;
+        lds[PAD ? pos + (pos >> 3) : pos] = x[q + Q * r];
+      }
+    }
+    wave_lds_sync();
+    const int rbase = PAD ? t + (t >> 3) : t;
+#pragma unroll
+    for (int r = 0; r < V; ++r) x[r] = lds[rbase + r * (PAD ? G + G / 8 : G)];
+    rv_fft_stage<N, INV, PAD, J + 1>(x, lds, twl, t);
+  }
+}
+
+template <int N, bool INV, bool PAD>
+__device__ __forceinline__ void fft_rv(float2 (&x)[RV<N>::V], float2* lds, const float2* twl, int t) {
+  rv_fft_stage<N, INV, PAD, 0>(x, lds, twl, t);
+}
+
+// Row pass on 12- or 16-value registers: one row per G lanes, the next row
+// prefetched, rows shared among the lanes of the table as in k_row_r8.
+template <int N>
+__global__ void __launch_bounds__(256) k_row_rv(PassTable tab) {
+  constexpr int V = RV<N>::V, G = RV<N>::G, RPW = RV<N>::RPW;
+  __shared__ float2 twt[RV<N>::NT * G];
+  __shared__ float2 scratch[4][RPW][padded(N)];
+  const int L = find_lane(tab, blockIdx.x);
+  const PassArgs& a = tab.l[L].a;
+  const int mode = tab.l[L].mode;
+  const int lb = blockIdx.x - tab.l[L].block_start;
+  const int blocks_per_lane = (L + 1 < tab.n ? tab.l[L + 1].block_start : (int)gridDim.x) - tab.l[L].block_start;
+  build_lane_twiddles<N>(twt, a.tw_x);
+  __syncthreads();
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+  const int lane = threadIdx.x % 64;
+  const int sub = RPW == 1 ? 0 : lane / G;
+  const int t = lane % G;
+  float2* lds = scratch[wave][sub];
+  const int total = a.n_probes * a.fb * a.ny;   // below 2^31 (checked at launch)
+  const int stride = blocks_per_lane * 4 * RPW;
+  const bool transmit = mode != ROW_INVERSE_ONLY;
+  auto fetch = [&](int rid, float2 (&xv)[V], float (&vv)[V], float2*& out) {
+    if (rid >= total) return;
+    const int w = rid / a.ny;
+    const int y = rid - w * a.ny;
+    const int p = w / a.fb;
+    const int fl = w - p * a.fb;
+    float2* row = a.exit + (((size_t)p * a.n_frames + a.f0 + fl) * a.ny + y) * (size_t)N;
+    out = row;
+    if (mode == ROW_FIRST) {
+      if (a.plane) {
+#pragma unroll
+        for (int r = 0; r < V; ++r) xv[r] = make_float2(a.plane_amp, 0.f);
+      } else {
+        const float2* src = a.probe0 + ((size_t)p * a.ny + y) * (size_t)N;
+#pragma unroll
+        for (int r = 0; r < V; ++r) xv[r] = src[t + r * G];
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < V; ++r) xv[r] = row[t + r * G];
+    }
+    if (transmit) {
+      const int ox = a.plane ? 0 : a.origin[2 * p];
+      const int oy = a.plane ? 0 : a.origin[2 * p + 1];
+      int yy = oy + y;
+      if (yy >= a.pny) yy -= a.pny;
+      const float* vrow =
+          a.V + (((size_t)fl * a.v_slices + (a.slice - a.v_slice0)) * a.pny + yy) * (size_t)a.pnx;
+#pragma unroll
+      for (int r = 0; r < V; ++r) {
+        int xx = ox + t + r * G;
+        if (xx >= a.pnx) xx -= a.pnx;
+        vv[r] = vrow[xx];
+      }
+    }
+  };
+  float2 xn[V];
+  float vn[V];
+#pragma unroll
+  for (int r = 0; r < V; ++r) {
+    xn[r] = make_float2(0.f, 0.f);
+    vn[r] = 0.f;
+  }
+  float2* out_next = nullptr;
+  int rid0 = (lb * 4 + wave) * RPW;
+  fetch(rid0 + sub, xn, vn, out_next);
+  for (; rid0 < total; rid0 += stride) {
+    // compiler barrier: the twiddles are read from LDS at every use instead of
+    // being hoisted into registers
+    __asm__ volatile("" ::: "memory");
+    const int rid = rid0 + sub;
+    float2* out = out_next;
+    float2 x[V];
+    float v[V];
+#pragma unroll
+    for (int r = 0; r < V; ++r) {
+      x[r] = xn[r];
+      v[r] = vn[r];
+    }
+    fetch(rid0 + stride + sub, xn, vn, out_next);
+    if (mode != ROW_FIRST) fft_rv<N, true, true>(x, lds, twt, t);
+    if (transmit) {
+#pragma unroll
+      for (int r = 0; r < V; ++r) x[r] = cmul(x[r], phase_factor(a.sigma * v[r]));
+      fft_rv<N, false, true>(x, lds, twt, t);
+    }
+    if (rid < total) {
+#pragma unroll
+      for (int r = 0; r < V; ++r) out[t + r * G] = x[r];
+    }
+  }
+}
+
+template <int N>
+struct CV {
+  static constexpr int G = RV<N>::G;
+  static constexpr int CPW = 64 / G;                 // columns per wavefront
+  static constexpr int WAVES = N == 384 ? 4 : 8;
+  static constexpr int CT = WAVES * CPW;             // columns per block (8)
+  static constexpr bool PAD = N != 1024;             // 1024: plain slots keep two blocks per CU
+  static constexpr int LD = (PAD ? padded(N) : N) + 2;   // = 2 (mod 16): conflict-free transposes
+  static constexpr int THREADS = WAVES * 64;
+};
+
+// Column pass on 12- or 16-value registers: CT-column tiles through an LDS
+// transpose, as k_col_r8.
+template <int N>
+__global__ void __launch_bounds__((CV<N>::THREADS)) k_col_rv(PassTable tab, int total_tiles) {
+  constexpr int V = RV<N>::V, G = CV<N>::G, CPW = CV<N>::CPW, CT = CV<N>::CT, LD = CV<N>::LD;
+  constexpr bool PAD = CV<N>::PAD;
+  constexpr int THREADS = CV<N>::THREADS;
+  constexpr int PER = CT * N / THREADS;   // tile values each thread moves
+  constexpr int TR = THREADS / CT;        // tile rows per transpose step
+  static_assert(TR % 8 == 0 && (CT * N) % THREADS == 0, "transpose layout");
+  __shared__ float2 twt[RV<N>::NT * G];
+  __shared__ float2 cols[CT * LD];
+  build_lane_twiddles<N>(twt, tab.l[0].a.tw_y);
+  const int wave = threadIdx.x / 64;
+  const int lane = threadIdx.x % 64;
+  const int cl = wave * CPW + lane / G;
+  const int t = lane % G;
+  float2* lds = cols + cl * LD;
+  const int rslot = PAD ? t + (t >> 3) : t;
+  const int trow = threadIdx.x / CT;
+  const int tslot = (threadIdx.x % CT) * LD + (PAD ? trow + (trow >> 3) : trow);
+  constexpr int TSTEP = PAD ? TR + TR / 8 : TR;
+  auto locate = [&](int it, int& L, int& x0, float2*& wp) {
+    const int tile_g = xcd_remap(it, total_tiles);
+    L = find_lane(tab, tile_g);
+    const PassArgs& a = tab.l[L].a;
+    const int tile = tile_g - tab.l[L].block_start;
+    const int tiles_per_wave = a.nx / CT;
+    const int w = tile / tiles_per_wave;
+    x0 = (tile % tiles_per_wave) * CT;
+    const int p = w / a.fb;
+    const int fl = w % a.fb;
+    wp = a.exit + ((size_t)p * a.n_frames + a.f0 + fl) * (size_t)N * a.nx;
+  };
+  float2 pre[PER];
+  int L = 0, x0 = 0;
+  float2* wp = nullptr;
+  int it = blockIdx.x;
+  if (it < total_tiles) {
+    locate(it, L, x0, wp);
+    const int nx = tab.l[L].a.nx;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = threadIdx.x + q * THREADS;
+      pre[q] = wp[(size_t)(e / CT) * nx + x0 + e % CT];
+    }
+  }
+  for (; it < total_tiles; it += gridDim.x) {
+    const PassArgs& a = tab.l[L].a;
+    const int mode = tab.l[L].mode;
+    const int cur_x0 = x0;
+    float2* cur_wp = wp;
+    __asm__ volatile("" ::: "memory");  // twiddles are read from LDS at every use
+    __syncthreads();  // the previous tile's stores from LDS are done (and the table is in)
+#pragma unroll
+    for (int q = 0; q < PER; ++q) cols[tslot + q * TSTEP] = pre[q];
+    const int nit = it + gridDim.x;
+    if (nit < total_tiles) {
+      locate(nit, L, x0, wp);
+      const int nx = tab.l[L].a.nx;
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int e = threadIdx.x + q * THREADS;
+        pre[q] = wp[(size_t)(e / CT) * nx + x0 + e % CT];
+      }
+    }
+    __syncthreads();
+    float2 x[V];
+#pragma unroll
+    for (int r = 0; r < V; ++r) x[r] = lds[rslot + r * (PAD ? G + G / 8 : G)];
+    if (mode == COL_INVERSE_ONLY) {
+      fft_rv<N, true, PAD>(x, lds, twt, t);
+    } else {
+      fft_rv<N, false, PAD>(x, lds, twt, t);
+      const float2 pxv = a.px[cur_x0 + cl];
+#pragma unroll
+      for (int r = 0; r < V; ++r) x[r] = cmul(x[r], cmul(pxv, a.py[t + r * G]));
+      if (mode == COL_REGULAR) fft_rv<N, true, PAD>(x, lds, twt, t);
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int r = 0; r < V; ++r) lds[rslot + r * (PAD ? G + G / 8 : G)] = x[r];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = threadIdx.x + q * THREADS;
+      cur_wp[(size_t)(e / CT) * a.nx + cur_x0 + e % CT] = cols[tslot + q * TSTEP];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Time stage: FP64 frame mean + subtraction, time FFT, |.|^2 / F^2
 // ---------------------------------------------------------------------------
 constexpr int TIME_G = 64;        // threads per k column (one wavefront)
@@ -1060,6 +1356,44 @@ static hipError_t row_r8_launch(PassTable& t, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int N>
+static hipError_t row_rv_launch(PassTable& t, hipStream_t s) {
+  constexpr int rows_per_block = 4 * RV<N>::RPW;
+  constexpr long max_blocks = 2048;
+  long rows[MAX_LANES], total = 0;
+  for (int i = 0; i < t.n; ++i) {
+    const PassArgs& a = t.l[i].a;
+    rows[i] = (long)a.n_probes * a.fb * a.ny;
+    if (rows[i] + 4 * max_blocks * rows_per_block >= (1L << 31)) return hipErrorInvalidValue;
+    total += rows[i];
+  }
+  const long need = (total + rows_per_block - 1) / rows_per_block;
+  int blocks = 0;
+  for (int i = 0; i < t.n; ++i) {
+    const long own = (rows[i] + rows_per_block - 1) / rows_per_block;
+    const long b = need <= max_blocks ? own : std::max(1L, std::min(own, rows[i] * max_blocks / total));
+    t.l[i].block_start = blocks;
+    blocks += (int)b;
+  }
+  TACAW_LAUNCH((k_row_rv<N>), dim3(blocks), dim3(256), 0, s, t);
+  return hipGetLastError();
+}
+
+template <int N>
+static hipError_t col_rv_launch(PassTable& t, hipStream_t s) {
+  constexpr int CT = CV<N>::CT;
+  int tiles = 0;
+  for (int i = 0; i < t.n; ++i) {
+    const PassArgs& a = t.l[i].a;
+    if (a.nx % CT != 0) return hipErrorInvalidValue;
+    t.l[i].block_start = tiles;
+    tiles += a.n_probes * a.fb * (a.nx / CT);
+  }
+  const int grid = std::min(tiles, 2048);
+  TACAW_LAUNCH((k_col_rv<N>), dim3(grid), dim3(CV<N>::THREADS), 0, s, t, tiles);
+  return hipGetLastError();
+}
+
 hipError_t launch_row_lanes(const PassLane* lanes, int n, int variant, hipStream_t s) {
   if (n < 1 || n > MAX_LANES || !same_grid(lanes, n)) return hipErrorInvalidValue;
   PassTable t{};
@@ -1072,6 +1406,9 @@ hipError_t launch_row_lanes(const PassLane* lanes, int n, int variant, hipStream
       case 256: return deep ? row_r8_launch<256, 2>(t, s) : row_r8_launch<256, 1>(t, s);
       case 128: return deep ? row_r8_launch<128, 2>(t, s) : row_r8_launch<128, 1>(t, s);
       case 64: return deep ? row_r8_launch<64, 2>(t, s) : row_r8_launch<64, 1>(t, s);
+      case 384: return row_rv_launch<384>(t, s);
+      case 768: return row_rv_launch<768>(t, s);
+      case 1024: return row_rv_launch<1024>(t, s);
       default: variant = 1;
     }
   }
@@ -1125,6 +1462,9 @@ hipError_t launch_col_lanes(const PassLane* lanes, int n, int variant, hipStream
     if (ny == 256 && nx % C8<256, 0>::CT == 0) return col_r8_launch<256, 0>(t, s);
     if (ny == 128 && nx % C8<128, 0>::CT == 0) return col_r8_launch<128, 0>(t, s);
     if (ny == 64 && nx % C8<64, 0>::CT == 0) return col_r8_launch<64, 0>(t, s);
+    if (ny == 384 && nx % CV<384>::CT == 0) return col_rv_launch<384>(t, s);
+    if (ny == 768 && nx % CV<768>::CT == 0) return col_rv_launch<768>(t, s);
+    if (ny == 1024 && nx % CV<1024>::CT == 0) return col_rv_launch<1024>(t, s);
     variant = 0;
   }
   switch (lanes[0].a.ny) {

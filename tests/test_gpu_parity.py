@@ -90,8 +90,12 @@ SMALL = [
          aperture_mrad=30.0, n_probes=2, voltage_V=100e3),
     dict(seed=35, nx=128, ny=128, n_slices=2, n_frames=6, cell=(30.0, 27.0, 4.0), aperture_mrad=25.0,
          n_probes=3, voltage_V=60e3, pot_grid=(300, 270), two_sided=True),
-    # the serving mix's large grid (LDS Stockham kernels for 1024)
+    # 12- and 16-value register kernels: 384, 768 and the serving mix's 1024
     dict(seed=36, nx=1024, ny=1024, n_slices=2, n_frames=4, cell=(110.0, 110.0, 3.0), n_atoms=40),
+    dict(seed=37, nx=384, ny=384, n_slices=3, n_frames=5, cell=(40.0, 40.0, 4.0), n_atoms=25),
+    dict(seed=38, nx=768, ny=384, n_slices=2, n_frames=4, cell=(80.0, 40.0, 3.0), n_atoms=30),
+    dict(seed=39, nx=384, ny=768, n_slices=2, n_frames=4, cell=(40.0, 80.0, 3.0), n_atoms=30,
+         aperture_mrad=30.0, n_probes=2, voltage_V=100e3),
 ]
 
 
