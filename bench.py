@@ -312,8 +312,11 @@ def main():
     if timed:
         dom = max(timed, key=lambda k: timed[k][0])
         ms, n = timed[dom]
-        # every launch of a pass advances one frame batch by one slice
-        units = job.nx * job.ny * job.n_probes * j.plan()[0]
+        # every launch of a pass advances one frame batch by one slice; the
+        # last batch may be shorter, so take the mean batch of the step
+        fb = j.plan()[0]
+        n_batches = -(-job.n_frames // fb)
+        units = job.nx * job.ny * job.n_probes * job.n_frames / n_batches
         avg_ms = ms / n
         achieved = BYTES_PER_UNIT[dom] * units / (avg_ms * 1e-3) / 1e9
         # counter-measured HBM bytes per launch, when they were taken for this
@@ -323,9 +326,10 @@ def main():
         if os.path.exists(tpath):
             tr = json.load(open(tpath))
             if (tr.get("source_hash") == kernel_source_hash() and dom in tr.get("per_launch_bytes", {})
-                    and tr.get("grid") == [job.nx, job.ny] and tr.get("frame_batch") == j.plan()[0]
+                    and tr.get("grid") == [job.nx, job.ny] and tr.get("frame_batch") == fb
                     and tr.get("probes") == job.n_probes):
-                traffic = tr["per_launch_bytes"][dom]
+                # measured on full batches; scaled to the mean batch like `units`
+                traffic = tr["per_launch_bytes"][dom] * (job.n_frames / n_batches) / fb
         roofline = {"bound": "hbm", "kernel": f"{dom} pass", "achieved": round(achieved, 1),
                     "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
                     "traffic": traffic, "avg_launch_ms": round(avg_ms, 4), "launches": n,
