@@ -218,6 +218,33 @@ tacaw_status tacaw_get_exit_waves(tacaw_job* job, void* dst_c64, size_t n, int d
  * NULL. */
 tacaw_status tacaw_axes(const tacaw_job_desc* desc, double* kx, double* ky, double* f_THz);
 
+/* ---- spectrum analysis ----------------------------------------------------
+ * Reductions of the job's resident spectrum I[p][m][ky][kx] (Methods 2.1,
+ * "Data Structure Design": dispersion along reciprocal-space paths,
+ * momentum-resolved intensity at a frequency, position-resolved maps over a
+ * probe scan; Supplement MWE: dispersion(kx, ky), spectral_diffraction(15.0),
+ * spectrum_image(15.0)).  The frequency f_THz selects the kept bin nearest to
+ * it (lowest index on ties; EINVAL more than half a bin outside the kept
+ * range).  Sums run on the device in FP64 in a fixed order; results are
+ * float64, copied to a host pointer or (dst_on_device != 0) a device pointer.
+ * ENOTREADY before a run, EBUSY while serving, ECANCELLED after a cancel. */
+
+/* D[ky][kx] = sum over probes of I[p][m][ky][kx]; n = ny * nx. */
+tacaw_status tacaw_spectral_diffraction(tacaw_job* job, double f_THz, double* dst, size_t n, int dst_on_device);
+
+/* S[p] = sum of I[p][m][k] over the k-nodes with k_inner <= |k| < k_outer
+ * (cycles/A; k_outer <= 0: no outer bound), one value per probe position in
+ * probe_xy order (a virtual detector); n = n_probes. */
+tacaw_status tacaw_spectrum_image(tacaw_job* job, double f_THz, double k_inner, double k_outer, double* dst,
+                                  size_t n, int dst_on_device);
+
+/* D[i][m] = sum over probes of I[p][m] at the grid node nearest to the path
+ * point (kx[i], ky[i]) (cycles/A; node index round(k L) mod N with L = N d
+ * the wave grid's extent, fftfreq order), for every kept bin m; kx, ky are host arrays of n_points;
+ * n = n_points * M. */
+tacaw_status tacaw_dispersion(tacaw_job* job, const double* kx, const double* ky, int32_t n_points, double* dst,
+                              size_t n, int dst_on_device);
+
 /* Slice index of every atom (n_atoms int32, host), as the planner binned it. */
 tacaw_status tacaw_job_slices(const tacaw_job* job, int32_t* slice_of_atom, size_t n);
 

@@ -311,3 +311,45 @@ def run_job(job, frames=None):
     """Exit waves and spectrum of a whole job (frames subset allowed)."""
     ex = exit_waves(job, frames=frames)
     return ex, tacaw_spectrum(ex, two_sided=job.two_sided)
+
+
+# ---------------------------------------------------------------------------
+# Analysis of the spectrum (Methods 2.1, "Data Structure Design": dispersion
+# along k-space paths, momentum-resolved intensity at a frequency, position-
+# resolved maps over a probe scan; Supplement MWE: dispersion(kx, ky),
+# spectral_diffraction(15.0), spectrum_image(15.0)).  Readings: the frequency
+# is the kept bin nearest to f (lowest index on ties); a k-space point is the
+# nearest grid node (index round(k L) mod N, fftfreq order); probes are summed
+# for dispersion and spectral diffraction; a spectrum image sums the k-nodes
+# with k_inner <= |k| < k_outer (k_outer <= 0: no outer bound).
+# ---------------------------------------------------------------------------
+def frequency_bin(f_THz: float, n_frames: int, dt_fs: float, two_sided: bool = False) -> int:
+    """Index of the kept frequency bin nearest to f_THz."""
+    f = freq_axis_THz(n_frames, dt_fs, two_sided)
+    return int(np.argmin(np.abs(f - f_THz)))
+
+
+def spectral_diffraction(spec: np.ndarray, m: int) -> np.ndarray:
+    """D[ky, kx] = sum over probes of I[p, m, ky, kx] (spec: [P, M, ny, nx])."""
+    return spec[:, m].astype(np.float64).sum(axis=0)
+
+
+def spectrum_image(spec: np.ndarray, m: int, kx: np.ndarray, ky: np.ndarray,
+                   k_inner: float = 0.0, k_outer: float = 0.0) -> np.ndarray:
+    """S[p] = sum of I[p, m, k] over the k-nodes with k_inner <= |k| < k_outer."""
+    kk = np.sqrt(kx[None, :] ** 2 + ky[:, None] ** 2)
+    mask = kk >= k_inner
+    if k_outer > 0:
+        mask &= kk < k_outer
+    return np.array([spec[p, m].astype(np.float64)[mask].sum() for p in range(spec.shape[0])])
+
+
+def dispersion(spec: np.ndarray, kx_path: np.ndarray, ky_path: np.ndarray, lx: float, ly: float) -> np.ndarray:
+    """D[i, m] = sum over probes of I[p, m] at the grid node nearest (kx_i, ky_i)."""
+    ny, nx = spec.shape[2], spec.shape[3]
+    out = np.zeros((len(kx_path), spec.shape[1]))
+    for i, (kx, ky) in enumerate(zip(kx_path, ky_path)):
+        ix = int(np.floor(kx * lx + 0.5)) % nx
+        iy = int(np.floor(ky * ly + 0.5)) % ny
+        out[i] = spec[:, :, iy, ix].astype(np.float64).sum(axis=0)
+    return out

@@ -1,0 +1,193 @@
+// Spectrum analysis on the device: spectral diffraction at a frequency,
+// spectrum images over a probe scan, dispersion along a k-space path (Methods
+// 2.1, "Data Structure Design": dispersion along reciprocal-space paths,
+// momentum-resolved intensity at a frequency, position-resolved vibrational
+// maps; Supplement MWE: dispersion(kx, ky), spectral_diffraction(15.0),
+// spectrum_image(15.0)).  Each call reduces the job's resident spectrum
+// I[p][m][ky][kx] with one kernel in FP64 and copies the result out.
+#include <math.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "runtime.h"
+
+using namespace tacaw;
+
+namespace {
+
+#define A_TRY(call)                                                         \
+  do {                                                                      \
+    hipError_t e_ = (call);                                                 \
+    if (e_ != hipSuccess) {                                                 \
+      set_error("%s failed: %s", #call, hipGetErrorString(e_));             \
+      return TACAW_EDEVICE;                                                 \
+    }                                                                       \
+  } while (0)
+
+// the job must hold a spectrum
+tacaw_status check_ready(const tacaw_job* job) {
+  if (!job) {
+    set_error("job is NULL");
+    return TACAW_EINVAL;
+  }
+  const int ss = job->serve_state.load();
+  if (ss == 1 || ss == 2) {
+    set_error("job is still in the serving loop");
+    return TACAW_EBUSY;
+  }
+  if (ss == 4) {
+    set_error("job was cancelled");
+    return TACAW_ECANCELLED;
+  }
+  if (!job->has_result || !job->d_spec) {
+    set_error("job has not been run");
+    return TACAW_ENOTREADY;
+  }
+  return TACAW_OK;
+}
+
+// f_m = m / (F dt) for the kept bins: one-sided m < F/2, two-sided fftfreq order
+double bin_freq(const tacaw_job* job, int m) {
+  const int F = job->hp.F;
+  const double dt_ps = job->desc.dt_fs * 1e-3;
+  const int mm = (job->desc.flags & TACAW_TWO_SIDED) && m >= (F + 1) / 2 ? m - F : m;
+  return mm / (F * dt_ps);
+}
+
+// kept bin nearest to f (lowest index on ties); EINVAL beyond half a bin
+// outside the kept range
+tacaw_status nearest_bin(const tacaw_job* job, double f, int* m_out) {
+  const int M = job->hp.M;
+  int best = 0;
+  double dbest = fabs(bin_freq(job, 0) - f), fmin = bin_freq(job, 0), fmax = fmin;
+  for (int m = 1; m < M; ++m) {
+    const double fm = bin_freq(job, m);
+    fmin = std::min(fmin, fm);
+    fmax = std::max(fmax, fm);
+    if (fabs(fm - f) < dbest) {
+      dbest = fabs(fm - f);
+      best = m;
+    }
+  }
+  const double half = 0.5 / (job->hp.F * job->desc.dt_fs * 1e-3);
+  if (!(f >= fmin - half && f <= fmax + half)) {
+    set_error("frequency %g THz outside the kept bins [%g, %g] THz", f, fmin, fmax);
+    return TACAW_EINVAL;
+  }
+  *m_out = best;
+  return TACAW_OK;
+}
+
+// device scratch of the analysis calls, freed on return
+struct DevBuf {
+  void* p = nullptr;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+tacaw_status finish_copy(tacaw_job* job, hipStream_t s, double* dst, const double* src, size_t n, int on_device) {
+  if (on_device) {
+    A_TRY(hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    A_TRY(hipStreamSynchronize(s));
+  } else {
+    A_TRY(hipStreamSynchronize(s));
+    A_TRY(hipMemcpy(dst, src, n * sizeof(double), hipMemcpyDeviceToHost));
+  }
+  (void)job;
+  return TACAW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tacaw_status tacaw_spectral_diffraction(tacaw_job* job, double f_THz, double* dst, size_t n, int dst_on_device) {
+  clear_error();
+  tacaw_status st = check_ready(job);
+  if (st != TACAW_OK) return st;
+  if (!dst || n != (size_t)job->hp.nx * job->hp.ny) {
+    set_error("dst must hold ny * nx = %d values", job->hp.nx * job->hp.ny);
+    return TACAW_EINVAL;
+  }
+  int m = 0;
+  if ((st = nearest_bin(job, f_THz, &m)) != TACAW_OK) return st;
+  A_TRY(hipSetDevice(job->ctx->device));
+  hipStream_t s = job->last_stream;
+  DevBuf out;
+  A_TRY(hipMalloc(&out.p, n * sizeof(double)));
+  A_TRY(launch_spectral_diffraction(job->d_spec, (double*)out.p, job->hp.P, job->hp.M, (int)n, m, s));
+  return finish_copy(job, s, dst, (const double*)out.p, n, dst_on_device);
+}
+
+tacaw_status tacaw_spectrum_image(tacaw_job* job, double f_THz, double k_inner, double k_outer, double* dst,
+                                  size_t n, int dst_on_device) {
+  clear_error();
+  tacaw_status st = check_ready(job);
+  if (st != TACAW_OK) return st;
+  if (!dst || n != (size_t)job->hp.P) {
+    set_error("dst must hold one value per probe (%d)", job->hp.P);
+    return TACAW_EINVAL;
+  }
+  if (!(k_inner >= 0.0) || !(k_outer <= 0.0 || k_outer > k_inner)) {
+    set_error("need 0 <= k_inner and (k_outer <= 0 or k_outer > k_inner)");
+    return TACAW_EINVAL;
+  }
+  int m = 0;
+  if ((st = nearest_bin(job, f_THz, &m)) != TACAW_OK) return st;
+  const HostPlan& hp = job->hp;
+  // unshifted axes k = fftfreq(N, d)
+  std::vector<double> ax(hp.nx + hp.ny);
+  for (int i = 0; i < hp.nx; ++i) ax[i] = (i < (hp.nx + 1) / 2 ? i : i - hp.nx) / (hp.nx * hp.dx);
+  for (int i = 0; i < hp.ny; ++i) ax[hp.nx + i] = (i < (hp.ny + 1) / 2 ? i : i - hp.ny) / (hp.ny * hp.dy);
+  A_TRY(hipSetDevice(job->ctx->device));
+  hipStream_t s = job->last_stream;
+  DevBuf out, axes;
+  A_TRY(hipMalloc(&out.p, n * sizeof(double)));
+  A_TRY(hipMalloc(&axes.p, ax.size() * sizeof(double)));
+  A_TRY(hipMemcpyAsync(axes.p, ax.data(), ax.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  const double* kx = (const double*)axes.p;
+  A_TRY(launch_spectrum_image(job->d_spec, (double*)out.p, hp.P, hp.M, hp.nx, hp.ny, m, kx, kx + hp.nx,
+                              k_inner * k_inner, k_outer > 0.0 ? k_outer * k_outer : 0.0, s));
+  return finish_copy(job, s, dst, (const double*)out.p, n, dst_on_device);
+}
+
+tacaw_status tacaw_dispersion(tacaw_job* job, const double* kx, const double* ky, int32_t n_points, double* dst,
+                              size_t n, int dst_on_device) {
+  clear_error();
+  tacaw_status st = check_ready(job);
+  if (st != TACAW_OK) return st;
+  const HostPlan& hp = job->hp;
+  if (!kx || !ky || n_points < 1 || (long long)n_points * hp.M > (1LL << 30) || !dst ||
+      n != (size_t)n_points * hp.M) {
+    set_error("need 1 <= n_points, n_points * M <= 2^30 and dst of n_points * M = %lld values",
+              (long long)n_points * hp.M);
+    return TACAW_EINVAL;
+  }
+  // nearest grid node: index round(k L) mod N, L = N d the extent of the wave
+  // grid (the window's when the probe sees a window of the potential grid)
+  const double wx = hp.nx * hp.dx, wy = hp.ny * hp.dy;
+  std::vector<int> node(n_points);
+  for (int i = 0; i < n_points; ++i) {
+    if (!isfinite(kx[i]) || !isfinite(ky[i])) {
+      set_error("path point %d is not finite", i);
+      return TACAW_EINVAL;
+    }
+    long ix = (long)floor(kx[i] * wx + 0.5) % hp.nx;
+    long iy = (long)floor(ky[i] * wy + 0.5) % hp.ny;
+    if (ix < 0) ix += hp.nx;
+    if (iy < 0) iy += hp.ny;
+    node[i] = (int)(iy * hp.nx + ix);
+  }
+  A_TRY(hipSetDevice(job->ctx->device));
+  hipStream_t s = job->last_stream;
+  DevBuf out, nodes;
+  A_TRY(hipMalloc(&out.p, n * sizeof(double)));
+  A_TRY(hipMalloc(&nodes.p, node.size() * sizeof(int)));
+  A_TRY(hipMemcpyAsync(nodes.p, node.data(), node.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  A_TRY(launch_dispersion(job->d_spec, (double*)out.p, hp.P, hp.M, hp.nx * hp.ny, (const int*)nodes.p, n_points, s));
+  return finish_copy(job, s, dst, (const double*)out.p, n, dst_on_device);
+}
+
+}  // extern "C"

@@ -1279,6 +1279,55 @@ __global__ void __launch_bounds__((TimeCfg<F>::THREADS)) k_time_ct(TimeArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Spectrum analysis: reductions of I[p][m][k] at one frequency bin or along a
+// list of k-nodes, accumulated in FP64 in a fixed order.
+// ---------------------------------------------------------------------------
+// D[k] = sum_p I[p][m][k]
+__global__ void __launch_bounds__(256) k_spectral_diffraction(const float* spec, double* out, int n_probes,
+                                                              int n_bins, int n_k, int m) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_k) return;
+  double acc = 0.0;
+  for (int p = 0; p < n_probes; ++p) acc += (double)spec[((size_t)p * n_bins + m) * n_k + k];
+  out[k] = acc;
+}
+
+// S[p] = sum over k-nodes with k_in^2 <= |k|^2 < k_out^2 of I[p][m][k]; one
+// workgroup per probe, strided partial sums, then a fixed-order tree.
+__global__ void __launch_bounds__(256) k_spectrum_image(const float* spec, double* out, int n_bins, int nx,
+                                                        int ny, int m, const double* kx, const double* ky,
+                                                        double k_in2, double k_out2) {
+  __shared__ double part[256];
+  const int p = blockIdx.x;
+  const int n_k = nx * ny;
+  const float* src = spec + ((size_t)p * n_bins + m) * n_k;
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < n_k; k += blockDim.x) {
+    const int iy = k / nx, ix = k - iy * nx;
+    const double k2 = kx[ix] * kx[ix] + ky[iy] * ky[iy];
+    if (k2 >= k_in2 && (k_out2 <= 0.0 || k2 < k_out2)) acc += (double)src[k];
+  }
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[p] = part[0];
+}
+
+// D[i][m] = sum_p I[p][m][node_i]
+__global__ void __launch_bounds__(256) k_dispersion(const float* spec, double* out, int n_probes, int n_bins,
+                                                    int n_k, const int* node, int n_points) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_points * n_bins) return;
+  const int i = e / n_bins, m = e - i * n_bins;
+  double acc = 0.0;
+  for (int p = 0; p < n_probes; ++p) acc += (double)spec[((size_t)p * n_bins + m) * n_k + node[i]];
+  out[e] = acc;
+}
+
+// ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
 #define TACAW_SIZES(X) X(16) X(32) X(48) X(64) X(96) X(128) X(160) X(192) X(256) X(320) X(384) X(512) \
@@ -1596,4 +1645,26 @@ hipError_t launch_probe_fill(float2* out, const double* rloc, const int* count, 
   return hipGetLastError();
 }
 
+}  // namespace tacaw
+
+namespace tacaw {
+hipError_t launch_spectral_diffraction(const float* spec, double* out, int n_probes, int n_bins, int n_k, int m,
+                                       hipStream_t s) {
+  hipLaunchKernelGGL(k_spectral_diffraction, dim3((n_k + 255) / 256), dim3(256), 0, s, spec, out, n_probes,
+                     n_bins, n_k, m);
+  return hipGetLastError();
+}
+hipError_t launch_spectrum_image(const float* spec, double* out, int n_probes, int n_bins, int nx, int ny, int m,
+                                 const double* kx, const double* ky, double k_in2, double k_out2, hipStream_t s) {
+  hipLaunchKernelGGL(k_spectrum_image, dim3(n_probes), dim3(256), 0, s, spec, out, n_bins, nx, ny, m, kx, ky,
+                     k_in2, k_out2);
+  return hipGetLastError();
+}
+hipError_t launch_dispersion(const float* spec, double* out, int n_probes, int n_bins, int n_k, const int* node,
+                             int n_points, hipStream_t s) {
+  const long n = (long)n_points * n_bins;
+  hipLaunchKernelGGL(k_dispersion, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, spec, out, n_probes, n_bins,
+                     n_k, node, n_points);
+  return hipGetLastError();
+}
 }  // namespace tacaw

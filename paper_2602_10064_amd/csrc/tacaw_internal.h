@@ -113,4 +113,12 @@ hipError_t launch_probe_fill(float2* out, const double* rloc /*[P][2]*/, const i
                              int nx, int ny, double dx, double dy, double lam, double alpha,
                              hipStream_t s);
 
+// Spectrum analysis reductions (FP64 sums of I[p][m][k]).
+hipError_t launch_spectral_diffraction(const float* spec, double* out, int n_probes, int n_bins, int n_k, int m,
+                                       hipStream_t s);
+hipError_t launch_spectrum_image(const float* spec, double* out, int n_probes, int n_bins, int nx, int ny, int m,
+                                 const double* kx, const double* ky, double k_in2, double k_out2, hipStream_t s);
+hipError_t launch_dispersion(const float* spec, double* out, int n_probes, int n_bins, int n_k, const int* node,
+                             int n_points, hipStream_t s);
+
 }  // namespace tacaw

@@ -62,6 +62,7 @@ EXPORTED = [
     "tacaw_get_exit_waves", "tacaw_axes", "tacaw_job_slices", "tacaw_job_destroy", "tacaw_last_error",
     "tacaw_timing_enable", "tacaw_timing_select", "tacaw_timing_get", "tacaw_version", "tacaw_job_latency",
     "tacaw_run_batch", "tacaw_autotune", "tacaw_job_plan",
+    "tacaw_spectral_diffraction", "tacaw_spectrum_image", "tacaw_dispersion",
 ]
 
 
@@ -98,6 +99,9 @@ def lib() -> ctypes.CDLL:
         "tacaw_run_batch": [P(vp), ctypes.c_int, vp],
         "tacaw_autotune": [vp, vp, P(ctypes.c_int), P(ctypes.c_int)],
         "tacaw_job_plan": [vp, P(i32), P(i32)],
+        "tacaw_spectral_diffraction": [vp, dp, vp, sz, ctypes.c_int],
+        "tacaw_spectrum_image": [vp, dp, dp, dp, vp, sz, ctypes.c_int],
+        "tacaw_dispersion": [vp, P(dp), P(dp), i32, vp, sz, ctypes.c_int],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -298,6 +302,30 @@ class TacawJob:
         n = int(self._d.desc.n_atoms)
         out = np.empty(n, dtype=np.int32)
         _check(lib().tacaw_job_slices(self.handle, _ptr(out, ctypes.c_int32), n))
+        return out
+
+    def spectral_diffraction(self, f_THz: float) -> np.ndarray:
+        """Sum over probes of I at the kept frequency bin nearest f_THz: [ny, nx] float64."""
+        out = np.empty((self.ny, self.nx), dtype=np.float64)
+        _check(lib().tacaw_spectral_diffraction(self.handle, float(f_THz), out.ctypes.data, out.size, 0))
+        return out
+
+    def spectrum_image(self, f_THz: float, k_inner: float = 0.0, k_outer: float = 0.0) -> np.ndarray:
+        """Per probe: sum of I at the bin nearest f_THz over k_inner <= |k| < k_outer."""
+        out = np.empty(self.n_probes, dtype=np.float64)
+        _check(lib().tacaw_spectrum_image(self.handle, float(f_THz), float(k_inner), float(k_outer),
+                                          out.ctypes.data, out.size, 0))
+        return out
+
+    def dispersion(self, kx, ky) -> np.ndarray:
+        """Sum over probes of I at the grid nodes nearest (kx[i], ky[i]): [n_points, M] float64."""
+        kx = np.ascontiguousarray(kx, dtype=np.float64)
+        ky = np.ascontiguousarray(ky, dtype=np.float64)
+        if kx.shape != ky.shape or kx.ndim != 1:
+            raise ValueError("kx and ky must be 1-D arrays of one length")
+        out = np.empty((kx.size, self.spectrum_shape[1]), dtype=np.float64)
+        _check(lib().tacaw_dispersion(self.handle, _ptr(kx, ctypes.c_double), _ptr(ky, ctypes.c_double),
+                                      int(kx.size), out.ctypes.data, out.size, 0))
         return out
 
     def plan(self) -> tuple:
