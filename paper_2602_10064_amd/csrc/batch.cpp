@@ -1,16 +1,21 @@
 // Batched execution of uneven jobs, the autotuner, and HIP-graph replay of a
 // job's launch sequence.
 //
-// Batched form: jobs are grouped by grid size; inside a group a launch
-// advances up to MAX_LANES lanes by one pass, a lane being one frame batch of
-// one job at its own slice (each lane has its own potentials, exit store,
-// tables and mode).  When a lane finishes its last slice the next frame batch
+// Batched form: jobs whose frame batches hold at least TACAW_BATCH_LARGE_MB of
+// waves run one after another on the first stream, one frame batch per round,
+// exactly as the plain form runs them.  The smaller jobs are grouped by grid
+// size; inside a group a launch advances up to MAX_LANES lanes by one pass, a
+// lane being one frame batch of one job at its own slice (each lane has its
+// own potentials, exit store, tables and mode).  A lane at the start of one of
+// its job's slice groups builds that group's potential slices in the shared
+// potential launch.  When a lane finishes its last slice the next frame batch
 // (of the same or another job) takes its place, so slice steps of different
 // jobs are batched continuously.  A job has at most one lane in flight (its
-// potential buffer holds one slice of one frame batch).  Groups run on their
-// own streams, joined back to the caller's stream.  Every wave is computed by
-// the same per-row and per-column arithmetic as in tacaw_run, so results are
-// bitwise those of the plain form.
+// potential buffer belongs to one frame batch), and lanes are admitted while
+// their waves and potentials fit TACAW_BATCH_LANE_MB.  Groups and the large
+// jobs are enqueued round-robin on up to four streams, joined back to the
+// caller's stream.  Every wave is computed by the same per-row and per-column
+// arithmetic as in tacaw_run, so results are bitwise those of the plain form.
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
