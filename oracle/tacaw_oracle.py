@@ -35,11 +35,24 @@ Readings taken where the paper is silent, garbled or inconsistent:
             exp(-2 pi i k.r_j) phase of the structure-factor sum), 2D transforms
             with norm="ortho", so a plane wave of unit norm stays of unit norm.
   R-probe   Plane wave psi0 = 1/sqrt(Nx Ny).  A convergent probe is a hard
-            aperture A(k) = 1 for lambda |k| <= alpha (edge inclusive), no
-            aberrations, times exp(-2 pi i k.r_p), inverse-transformed and
-            normalised to unit norm.  Windowed probes use a window of the wave
+            aperture A(k) = 1 for lambda |k| <= alpha (edge inclusive), times
+            exp(-i chi(k)) when aberrations are given (R-aberr), times
+            exp(-2 pi i k.r_p), inverse-transformed and normalised to unit norm.  Windowed probes use a window of the wave
             grid cropped (periodic wrap) from the full-cell potential, with origin
             pixel floor(r_p/dx) - N/2; the probe sits at r_p relative to it.
+  R-aberr   "Beyond Vibrational Spectroscopy" names the standard aberration
+            function (defocus, astigmatism, coma, spherical and higher orders)
+            applied at probe formation.  We take the polar-coefficient form
+            chi(k) = (2 pi / lambda) sum_nm C_nm alpha^(n+1) / (n+1)
+            cos(m (phi - phi_nm)), alpha = lambda |k|, phi = atan2(ky, kx),
+            over the 14 coefficients of orders 1..5 listed in ABERRATIONS,
+            and the probe factor exp(-i chi).  C10 = z is then the same as
+            propagating the focused probe over z with the Fresnel propagator.
+  R-adf     ADF/HAADF (HAADFData in Methods 2.1 and "Beyond Vibrational
+            Spectroscopy"): the frame-averaged diffraction pattern
+            D[p](k) = (1/F) sum_f |psi(p, f, k)|^2 (frozen-phonon average of the
+            exit-wave intensities), summed over the detector annulus
+            inner <= lambda |k| < outer (angles in mrad, small-angle).
   R-time    Arithmetic mean over all frames per (probe, k); no window; forward
             numpy sign with 1/F normalisation; I_m for m = 0..F/2-1 (one-sided),
             or all F bins when two-sided output is asked for.
@@ -207,14 +220,36 @@ def plane_wave(nx: int, ny: int) -> np.ndarray:
     return np.full((ny, nx), 1.0 / math.sqrt(nx * ny), dtype=np.complex128)
 
 
+# (n, m) of the polar aberration coefficients C_nm, orders 1..5 (reading R-aberr):
+# defocus C10, two-fold astigmatism C12, coma C21, three-fold C23, spherical C30,
+# star C32, four-fold C34, C41, C43, C45, fifth-order spherical C50, C52, C54, C56
+ABERRATIONS = [(1, 0), (1, 2), (2, 1), (2, 3), (3, 0), (3, 2), (3, 4),
+               (4, 1), (4, 3), (4, 5), (5, 0), (5, 2), (5, 4), (5, 6)]
+
+
+def aberration_chi(kx: np.ndarray, ky: np.ndarray, lam: float, c_A, phi_rad) -> np.ndarray:
+    """chi(k) [rad] on the [ky, kx] grid: (2 pi / lambda) sum C_nm alpha^(n+1)/(n+1)
+    cos(m (phi - phi_nm)), alpha = lambda |k|, phi = atan2(ky, kx)."""
+    kxx, kyy = np.meshgrid(kx, ky)
+    alpha = lam * np.sqrt(kxx ** 2 + kyy ** 2)
+    phi = np.arctan2(kyy, kxx)
+    chi = np.zeros_like(alpha)
+    for (n, m), c, a in zip(ABERRATIONS, c_A, phi_rad):
+        chi += c * alpha ** (n + 1) / (n + 1) * np.cos(m * (phi - a))
+    return 2.0 * math.pi / lam * chi
+
+
 def probe_wave(nx: int, ny: int, dx: float, dy: float, lam: float, alpha_rad: float,
-               rx: float, ry: float) -> np.ndarray:
-    """Hard-aperture probe centred at (rx, ry) on an nx*ny grid of pixel (dx, dy)."""
+               rx: float, ry: float, aberrations=None) -> np.ndarray:
+    """Hard-aperture probe centred at (rx, ry) on an nx*ny grid of pixel (dx, dy);
+    aberrations: None or (C_nm [A], phi_nm [rad]), 14 each in ABERRATIONS order."""
     kx = k_axis(nx, dx)
     ky = k_axis(ny, dy)
     kk = np.sqrt(ky[:, None] ** 2 + kx[None, :] ** 2)
     aperture = (lam * kk <= alpha_rad).astype(np.float64)
     phase = np.exp(-2j * math.pi * (kx[None, :] * rx + ky[:, None] * ry))
+    if aberrations is not None:
+        phase = phase * np.exp(-1j * aberration_chi(kx, ky, lam, aberrations[0], aberrations[1]))
     psi = np.fft.ifft2(aperture * phase, norm="ortho")
     return psi / math.sqrt(np.sum(np.abs(psi) ** 2))
 
@@ -249,6 +284,7 @@ def exit_waves(job, frames=None, probes=None) -> np.ndarray:
     n_p = 1 if plane else job.probe_xy.shape[0]
     probes = range(n_p) if probes is None else list(probes)
     windowed = (pot_nx, pot_ny) != (job.nx, job.ny)
+    aberr = getattr(job, "aberrations", None)
     out = np.zeros((len(probes), len(frames), job.ny, job.nx), dtype=np.complex128)
     for fi, f in enumerate(frames):
         pots = frame_potentials(job.positions[f], job.atom_species, slice_of, job.gauss_a,
@@ -265,11 +301,11 @@ def exit_waves(job, frames=None, probes=None) -> np.ndarray:
                     ix = (ox + np.arange(job.nx)) % pot_nx
                     win = pots[:, iy][:, :, ix]
                     psi0 = probe_wave(job.nx, job.ny, dx, dy, lam, job.aperture_mrad * 1e-3,
-                                      rx - ox * dx, ry - oy * dy)
+                                      rx - ox * dx, ry - oy * dy, aberr)
                 else:
                     win = pots
                     psi0 = probe_wave(job.nx, job.ny, dx, dy, lam, job.aperture_mrad * 1e-3,
-                                      rx, ry)
+                                      rx, ry, aberr)
             out[pi, fi] = multislice(psi0, win, sig, prop)
     return out
 
@@ -353,3 +389,20 @@ def dispersion(spec: np.ndarray, kx_path: np.ndarray, ky_path: np.ndarray, lx: f
         iy = int(np.floor(ky * ly + 0.5)) % ny
         out[i] = spec[:, :, iy, ix].astype(np.float64).sum(axis=0)
     return out
+
+
+# ---------------------------------------------------------------------------
+# Conventional STEM from the same exit waves (Methods 2.1 HAADFData; "Beyond
+# Vibrational Spectroscopy"; reading R-adf)
+# ---------------------------------------------------------------------------
+def mean_diffraction(exit_k: np.ndarray) -> np.ndarray:
+    """D[p, ky, kx] = (1/F) sum_f |psi(p, f, k)|^2 (exit_k: [P, F, ny, nx])."""
+    return (np.abs(exit_k.astype(np.complex128)) ** 2).mean(axis=1)
+
+
+def adf(mean_diff: np.ndarray, kx: np.ndarray, ky: np.ndarray, lam: float,
+        inner_mrad: float, outer_mrad: float) -> np.ndarray:
+    """A[p] = sum of D[p, k] over the nodes with inner <= lambda |k| < outer (mrad)."""
+    theta_mrad = 1e3 * lam * np.sqrt(kx[None, :] ** 2 + ky[:, None] ** 2)
+    mask = (theta_mrad >= inner_mrad) & (theta_mrad < outer_mrad)
+    return np.array([mean_diff[p][mask].sum() for p in range(mean_diff.shape[0])])

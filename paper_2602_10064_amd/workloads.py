@@ -52,6 +52,9 @@ class Job:
     pot_ny: int = 0
     two_sided: bool = False
     keep_exit_waves: bool = True
+    # probe aberrations: None, or (2, 14) = (C_nm [A], phi_nm [rad]) for
+    # (n, m) = 10, 12, 21, 23, 30, 32, 34, 41, 43, 45, 50, 52, 54, 56
+    aberrations: Optional[np.ndarray] = None
     name: str = ""
 
     @property
