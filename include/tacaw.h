@@ -153,6 +153,25 @@ tacaw_status tacaw_job_create(tacaw_ctx* ctx, const tacaw_job_desc* desc,
                               const int32_t* atom_species, const double* positions,
                               tacaw_job** out);
 
+/* ---- probe aberrations ------------------------------------------------------
+ * ("Beyond Vibrational Spectroscopy": the standard aberration function with
+ * defocus, astigmatism, coma, spherical aberration and higher orders, applied
+ * at probe formation.)  The incident probe in reciprocal space becomes
+ * A(k) exp(-i chi(k)) exp(-2 pi i k.r_p), with
+ *   chi(k) = (2 pi / lambda) sum_nm C_nm alpha^(n+1) / (n+1) cos(m (phi - phi_nm)),
+ * alpha = lambda |k|, phi = atan2(ky, kx), over the TACAW_N_ABERRATIONS polar
+ * coefficients in this order of (n, m): 10 (defocus; C10 = z is a Fresnel
+ * propagation of the focused probe over z), 12 (two-fold astigmatism), 21
+ * (coma), 23, 30 (spherical, Cs), 32, 34, 41, 43, 45, 50 (C5), 52, 54, 56.
+ * c_angstrom: TACAW_N_ABERRATIONS magnitudes in A (host; NULL clears every
+ * aberration); phi_rad: as many angles in rad (host; NULL means all 0; ignored
+ * for m = 0).  The values are copied.  Takes effect from the next run (a job
+ * that already holds its incident probes rebuilds them at once, synchronously).
+ * EINVAL for a plane-wave job or a non-finite value; EBUSY while the job is in
+ * the serving loop. */
+#define TACAW_N_ABERRATIONS 14
+tacaw_status tacaw_job_set_aberrations(tacaw_job* job, const double* c_angstrom, const double* phi_rad);
+
 /* Plain per-job form: enqueue the whole hot path (potentials, multislice over
  * every (probe, frame) wave, exit-wave capture, FP64 frame mean, time FFT and
  * |.|^2) on `hip_stream` (a hipStream_t, or NULL for the default stream) and
@@ -244,6 +263,27 @@ tacaw_status tacaw_spectrum_image(tacaw_job* job, double f_THz, double k_inner, 
  * n = n_points * M. */
 tacaw_status tacaw_dispersion(tacaw_job* job, const double* kx, const double* ky, int32_t n_points, double* dst,
                               size_t n, int dst_on_device);
+
+/* ---- conventional STEM from the same exit waves ----------------------------
+ * ("Beyond Vibrational Spectroscopy": ADF/HAADF images integrate the scattered
+ * intensity over a range of collection angles, from the stored exit waves;
+ * Methods 2.1: HAADFData over the x, y, kx, ky dataset.)  Both calls need a
+ * job created with TACAW_KEEP_EXIT_WAVES (EINVAL otherwise) that has run;
+ * ENOTREADY / EBUSY / ECANCELLED as for the spectrum analysis.  Results are
+ * float64, computed in FP64 on the device, copied to a host pointer or
+ * (dst_on_device != 0) a device pointer. */
+
+/* D[p][ky][kx] = (1/F) sum_f |psi[p][f][ky][kx]|^2: the frame-averaged
+ * (frozen-phonon) diffraction pattern of every probe, the 4D-STEM dataset;
+ * n = n_probes * ny * nx. */
+tacaw_status tacaw_mean_diffraction(tacaw_job* job, double* dst, size_t n, int dst_on_device);
+
+/* A[p] = sum of D[p][k] over the k-nodes with inner_mrad <= 1e3 lambda |k| <
+ * outer_mrad (small-angle scattering angle; 0 <= inner < outer, else EINVAL),
+ * one value per probe in probe_xy order: an annular detector image (HAADF for
+ * inner angles of 50-80 mrad, bright field from 0); n = n_probes. */
+tacaw_status tacaw_adf(tacaw_job* job, double inner_mrad, double outer_mrad, double* dst, size_t n,
+                       int dst_on_device);
 
 /* Slice index of every atom (n_atoms int32, host), as the planner binned it. */
 tacaw_status tacaw_job_slices(const tacaw_job* job, int32_t* slice_of_atom, size_t n);

@@ -1,3 +1,7 @@
+// Conventional STEM from the kept exit waves (Methods 2.1 HAADFData; "Beyond
+// Vibrational Spectroscopy"): frame-averaged diffraction patterns and ADF
+// detector sums over an annulus of scattering angles.
+//
 // Spectrum analysis on the device: spectral diffraction at a frequency,
 // spectrum images over a probe scan, dispersion along a k-space path (Methods
 // 2.1, "Data Structure Design": dispersion along reciprocal-space paths,
@@ -99,9 +103,82 @@ tacaw_status finish_copy(tacaw_job* job, hipStream_t s, double* dst, const doubl
   return TACAW_OK;
 }
 
+// unshifted axes kx then ky, k = fftfreq(N, d): i * (1 / (N d)), i wrapped to
+// negative values from (N + 1) / 2 on
+std::vector<double> k_axes(const HostPlan& hp) {
+  std::vector<double> ax(hp.nx + hp.ny);
+  const double fx = 1.0 / (hp.nx * hp.dx), fy = 1.0 / (hp.ny * hp.dy);
+  for (int i = 0; i < hp.nx; ++i) ax[i] = (i < (hp.nx + 1) / 2 ? i : i - hp.nx) * fx;
+  for (int i = 0; i < hp.ny; ++i) ax[hp.nx + i] = (i < (hp.ny + 1) / 2 ? i : i - hp.ny) * fy;
+  return ax;
+}
+
+// the job must hold its exit waves
+tacaw_status check_exit(const tacaw_job* job) {
+  tacaw_status st = check_ready(job);
+  if (st != TACAW_OK) return st;
+  if (!(job->desc.flags & TACAW_KEEP_EXIT_WAVES) || !job->d_exit) {
+    set_error("job was created without TACAW_KEEP_EXIT_WAVES");
+    return TACAW_EINVAL;
+  }
+  return TACAW_OK;
+}
+
+// frame-averaged diffraction patterns into a fresh device buffer
+tacaw_status mean_diffraction_dev(tacaw_job* job, hipStream_t s, DevBuf& out) {
+  const HostPlan& hp = job->hp;
+  A_TRY(hipMalloc(&out.p, (size_t)hp.P * hp.nx * hp.ny * sizeof(double)));
+  A_TRY(launch_mean_diffraction(job->d_exit, (double*)out.p, hp.P, hp.F, hp.nx * hp.ny, s));
+  return TACAW_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+tacaw_status tacaw_mean_diffraction(tacaw_job* job, double* dst, size_t n, int dst_on_device) {
+  clear_error();
+  tacaw_status st = check_exit(job);
+  if (st != TACAW_OK) return st;
+  const HostPlan& hp = job->hp;
+  if (!dst || n != (size_t)hp.P * hp.nx * hp.ny) {
+    set_error("dst must hold n_probes * ny * nx = %zu values", (size_t)hp.P * hp.nx * hp.ny);
+    return TACAW_EINVAL;
+  }
+  A_TRY(hipSetDevice(job->ctx->device));
+  hipStream_t s = job->last_stream;
+  DevBuf d;
+  if ((st = mean_diffraction_dev(job, s, d)) != TACAW_OK) return st;
+  return finish_copy(job, s, dst, (const double*)d.p, n, dst_on_device);
+}
+
+tacaw_status tacaw_adf(tacaw_job* job, double inner_mrad, double outer_mrad, double* dst, size_t n,
+                       int dst_on_device) {
+  clear_error();
+  tacaw_status st = check_exit(job);
+  if (st != TACAW_OK) return st;
+  const HostPlan& hp = job->hp;
+  if (!dst || n != (size_t)hp.P) {
+    set_error("dst must hold one value per probe (%d)", hp.P);
+    return TACAW_EINVAL;
+  }
+  if (!(inner_mrad >= 0.0) || !(outer_mrad > inner_mrad)) {
+    set_error("need 0 <= inner_mrad < outer_mrad");
+    return TACAW_EINVAL;
+  }
+  const std::vector<double> ax = k_axes(hp);
+  A_TRY(hipSetDevice(job->ctx->device));
+  hipStream_t s = job->last_stream;
+  DevBuf d, out, axes;
+  if ((st = mean_diffraction_dev(job, s, d)) != TACAW_OK) return st;
+  A_TRY(hipMalloc(&out.p, n * sizeof(double)));
+  A_TRY(hipMalloc(&axes.p, ax.size() * sizeof(double)));
+  A_TRY(hipMemcpyAsync(axes.p, ax.data(), ax.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  const double* kx = (const double*)axes.p;
+  A_TRY(launch_adf((const double*)d.p, (double*)out.p, hp.P, hp.nx, hp.ny, kx, kx + hp.nx, hp.lam, inner_mrad,
+                   outer_mrad, s));
+  return finish_copy(job, s, dst, (const double*)out.p, n, dst_on_device);
+}
 
 tacaw_status tacaw_spectral_diffraction(tacaw_job* job, double f_THz, double* dst, size_t n, int dst_on_device) {
   clear_error();
@@ -137,10 +214,7 @@ tacaw_status tacaw_spectrum_image(tacaw_job* job, double f_THz, double k_inner, 
   int m = 0;
   if ((st = nearest_bin(job, f_THz, &m)) != TACAW_OK) return st;
   const HostPlan& hp = job->hp;
-  // unshifted axes k = fftfreq(N, d)
-  std::vector<double> ax(hp.nx + hp.ny);
-  for (int i = 0; i < hp.nx; ++i) ax[i] = (i < (hp.nx + 1) / 2 ? i : i - hp.nx) / (hp.nx * hp.dx);
-  for (int i = 0; i < hp.ny; ++i) ax[hp.nx + i] = (i < (hp.ny + 1) / 2 ? i : i - hp.ny) / (hp.ny * hp.dy);
+  const std::vector<double> ax = k_axes(hp);
   A_TRY(hipSetDevice(job->ctx->device));
   hipStream_t s = job->last_stream;
   DevBuf out, axes;

@@ -318,6 +318,26 @@ tacaw_status run_time_stage(tacaw_job* job, hipStream_t s) {
 
 // Allocate the job's device buffers, upload its inputs and build its tables
 // and incident probes.  Synchronous.
+// Incident probes in real space: aperture (and aberration phase) filled in
+// reciprocal space, then brought to real space by the inverse-only passes.
+hipError_t build_probe(tacaw_job* j, hipStream_t s0) {
+  const HostPlan& hp = j->hp;
+  hipError_t e;
+  if ((e = hipMemsetAsync(j->d_count, 0, sizeof(int), s0)) != hipSuccess) return e;
+  if ((e = launch_aperture_count(j->d_count, hp.nx, hp.ny, hp.dx, hp.dy, hp.lam, hp.alpha, s0)) != hipSuccess)
+    return e;
+  if ((e = launch_probe_fill(j->d_probe0, j->d_rloc, j->d_count, hp.P, hp.nx, hp.ny, hp.dx, hp.dy, hp.lam,
+                             hp.alpha, j->aberr, s0)) != hipSuccess)
+    return e;
+  PassArgs a = pass_args(j);
+  a.exit = j->d_probe0;
+  a.n_frames = 1;
+  a.f0 = 0;
+  a.fb = 1;
+  if ((e = launch_col_pass(a, COL_INVERSE_ONLY, s0)) != hipSuccess) return e;
+  return launch_row_pass(a, ROW_INVERSE_ONLY, s0);
+}
+
 tacaw_status materialize(tacaw_job* j, hipStream_t s0) {
   if (j->materialized) return TACAW_OK;
   HIP_TRY(hipSetDevice(j->ctx->device));
@@ -395,21 +415,7 @@ tacaw_status materialize(tacaw_job* j, hipStream_t s0) {
     return fail("prop", e);
   if ((e = launch_prop_factor(j->d_py_last, hp.ny, hp.dy, hp.lam, hp.dz, ly, s0)) != hipSuccess)
     return fail("prop", e);
-  if (!hp.plane) {
-    if ((e = hipMemsetAsync(j->d_count, 0, sizeof(int), s0)) != hipSuccess) return fail("memset", e);
-    if ((e = launch_aperture_count(j->d_count, hp.nx, hp.ny, hp.dx, hp.dy, hp.lam, hp.alpha, s0)) != hipSuccess)
-      return fail("aperture", e);
-    if ((e = launch_probe_fill(j->d_probe0, j->d_rloc, j->d_count, hp.P, hp.nx, hp.ny, hp.dx, hp.dy, hp.lam,
-                               hp.alpha, s0)) != hipSuccess)
-      return fail("probe fill", e);
-    PassArgs a = pass_args(j);
-    a.exit = j->d_probe0;
-    a.n_frames = 1;
-    a.f0 = 0;
-    a.fb = 1;
-    if ((e = launch_col_pass(a, COL_INVERSE_ONLY, s0)) != hipSuccess) return fail("probe iFFT_y", e);
-    if ((e = launch_row_pass(a, ROW_INVERSE_ONLY, s0)) != hipSuccess) return fail("probe iFFT_x", e);
-  }
+  if (!hp.plane && (e = build_probe(j, s0)) != hipSuccess) return fail("incident probe", e);
   if ((e = hipStreamSynchronize(s0)) != hipSuccess) return fail("job setup", e);
   j->materialized = true;
   return TACAW_OK;
@@ -706,6 +712,49 @@ tacaw_status tacaw_job_slices(const tacaw_job* job, int32_t* out, size_t n) {
     return TACAW_EINVAL;
   }
   std::copy(job->hp.slice_of.begin(), job->hp.slice_of.end(), out);
+  return TACAW_OK;
+}
+
+tacaw_status tacaw_job_set_aberrations(tacaw_job* job, const double* c_angstrom, const double* phi_rad) {
+  clear_error();
+  if (!job) {
+    set_error("job is NULL");
+    return TACAW_EINVAL;
+  }
+  if (job->hp.plane) {
+    set_error("a plane-wave job has no probe to aberrate");
+    return TACAW_EINVAL;
+  }
+  const int ss = job->serve_state.load();
+  if (ss == 1 || ss == 2) {
+    set_error("job is still in the serving loop");
+    return TACAW_EBUSY;
+  }
+  Aberrations ab{};
+  if (c_angstrom) {
+    for (int i = 0; i < N_ABERR; ++i) {
+      const double c = c_angstrom[i], a = phi_rad ? phi_rad[i] : 0.0;
+      if (!isfinite(c) || !isfinite(a)) {
+        set_error("aberration coefficient %d is not finite", i);
+        return TACAW_EINVAL;
+      }
+      ab.c[i] = c;
+      ab.phi[i] = a;
+      ab.on |= c != 0.0;
+    }
+  }
+  job->aberr = ab;
+  // a job that already holds its incident probes rebuilds them now; the
+  // current spectrum stays until the next run replaces it
+  if (job->materialized && job->d_probe0) {
+    HIP_TRY(hipSetDevice(job->ctx->device));
+    hipError_t e = build_probe(job, job->last_stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(job->last_stream);
+    if (e != hipSuccess) {
+      set_error("incident probe: %s", hipGetErrorString(e));
+      return TACAW_EDEVICE;
+    }
+  }
   return TACAW_OK;
 }
 

@@ -93,8 +93,25 @@ __global__ void k_aperture_count(int* count, int nx, int ny, double dx, double d
 
 // Reciprocal-space incident probe A(k) exp(-2 pi i k.r) / sqrt(count * nx * ny);
 // an unnormalised inverse 2D FFT of it is the unit-norm real-space probe.
+// chi(k) of the polar aberration coefficients, in radians
+__device__ double aberration_chi(double kx, double ky, double lam, const Aberrations& ab) {
+  constexpr int NM[N_ABERR][2] = {{1, 0}, {1, 2}, {2, 1}, {2, 3}, {3, 0}, {3, 2}, {3, 4},
+                                  {4, 1}, {4, 3}, {4, 5}, {5, 0}, {5, 2}, {5, 4}, {5, 6}};
+  const double alpha = lam * sqrt(kx * kx + ky * ky);
+  const double phi = atan2(ky, kx);
+  double chi = 0.0;
+#pragma unroll
+  for (int i = 0; i < N_ABERR; ++i) {
+    double ap = alpha;   // alpha^(n+1)
+#pragma unroll
+    for (int q = 0; q < NM[i][0]; ++q) ap *= alpha;
+    chi += ab.c[i] * ap / (NM[i][0] + 1) * cos(NM[i][1] * (phi - ab.phi[i]));
+  }
+  return 2.0 * M_PI / lam * chi;
+}
+
 __global__ void k_probe_fill(float2* out, const double* rloc, const int* count, int n_probes, int nx,
-                             int ny, double dx, double dy, double lam, double alpha) {
+                             int ny, double dx, double dy, double lam, double alpha, Aberrations ab) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t per = (size_t)nx * ny;
   if (i >= per * n_probes) return;
@@ -107,6 +124,13 @@ __global__ void k_probe_fill(float2* out, const double* rloc, const int* count, 
     const double amp = 1.0 / sqrt((double)(*count) * (double)nx * (double)ny);
     double s, c;
     sincospi(-2.0 * (kx * rloc[2 * p] + ky * rloc[2 * p + 1]), &s, &c);
+    if (ab.on) {   // times exp(-i chi)
+      double sa, ca;
+      sincos(-aberration_chi(kx, ky, lam, ab), &sa, &ca);
+      const double c2 = c * ca - s * sa;
+      s = s * ca + c * sa;
+      c = c2;
+    }
     v = make_float2((float)(amp * c), (float)(amp * s));
   }
   out[i] = v;
@@ -1638,16 +1662,67 @@ hipError_t launch_aperture_count(int* count, int nx, int ny, double dx, double d
 }
 
 hipError_t launch_probe_fill(float2* out, const double* rloc, const int* count, int n_probes, int nx,
-                             int ny, double dx, double dy, double lam, double alpha, hipStream_t s) {
+                             int ny, double dx, double dy, double lam, double alpha, const Aberrations& ab,
+                             hipStream_t s) {
   const size_t n = (size_t)nx * ny * n_probes;
   hipLaunchKernelGGL(k_probe_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, out, rloc, count,
-                     n_probes, nx, ny, dx, dy, lam, alpha);
+                     n_probes, nx, ny, dx, dy, lam, alpha, ab);
   return hipGetLastError();
 }
 
 }  // namespace tacaw
 
 namespace tacaw {
+// D[p][k] = (1/F) sum_f |psi[p][f][k]|^2, lanes along k (coalesced per frame)
+__global__ void __launch_bounds__(256) k_mean_diffraction(const float2* exit, double* out, int n_frames, int n_k) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int p = blockIdx.y;
+  if (k >= n_k) return;
+  const float2* src = exit + (size_t)p * n_frames * n_k + k;
+  double acc = 0.0;
+  for (int f = 0; f < n_frames; ++f) {
+    const float2 v = src[(size_t)f * n_k];
+    acc += __dadd_rn(__dmul_rn((double)v.x, (double)v.x), __dmul_rn((double)v.y, (double)v.y));
+  }
+  out[(size_t)p * n_k + k] = acc / n_frames;
+}
+
+// A[p] = sum of D[p][k] over inner <= 1e3 lambda |k| < outer; one workgroup
+// per probe, strided partial sums, then a fixed-order tree.  The angle is
+// formed as (1e3 lambda) sqrt(kx^2 + ky^2) with no contraction.
+__global__ void __launch_bounds__(256) k_adf(const double* diff, double* out, int nx, int ny, const double* kx,
+                                             const double* ky, double lam_mrad, double inner, double outer) {
+  __shared__ double part[256];
+  const int p = blockIdx.x;
+  const int n_k = nx * ny;
+  const double* src = diff + (size_t)p * n_k;
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < n_k; k += blockDim.x) {
+    const int iy = k / nx, ix = k - iy * nx;
+    const double th = __dmul_rn(lam_mrad, sqrt(__dadd_rn(__dmul_rn(kx[ix], kx[ix]), __dmul_rn(ky[iy], ky[iy]))));
+    if (th >= inner && th < outer) acc += src[k];
+  }
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[p] = part[0];
+}
+
+hipError_t launch_mean_diffraction(const float2* exit, double* out, int n_probes, int n_frames, int n_k,
+                                   hipStream_t s) {
+  hipLaunchKernelGGL(k_mean_diffraction, dim3((n_k + 255) / 256, n_probes), dim3(256), 0, s, exit, out, n_frames,
+                     n_k);
+  return hipGetLastError();
+}
+hipError_t launch_adf(const double* diff, double* out, int n_probes, int nx, int ny, const double* kx,
+                      const double* ky, double lam, double inner_mrad, double outer_mrad, hipStream_t s) {
+  hipLaunchKernelGGL(k_adf, dim3(n_probes), dim3(256), 0, s, diff, out, nx, ny, kx, ky, 1e3 * lam, inner_mrad,
+                     outer_mrad);
+  return hipGetLastError();
+}
 hipError_t launch_spectral_diffraction(const float* spec, double* out, int n_probes, int n_bins, int n_k, int m,
                                        hipStream_t s) {
   hipLaunchKernelGGL(k_spectral_diffraction, dim3((n_k + 255) / 256), dim3(256), 0, s, spec, out, n_probes,

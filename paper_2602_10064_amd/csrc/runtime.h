@@ -138,6 +138,7 @@ struct tacaw_job {
   float2* d_px_last = nullptr;   // last slice
   float2* d_py_last = nullptr;
   float2* d_probe0 = nullptr;
+  tacaw::Aberrations aberr{};    // probe aberrations (off unless set)
   int32_t* d_origin = nullptr;
   double* d_rloc = nullptr;
   int* d_count = nullptr;

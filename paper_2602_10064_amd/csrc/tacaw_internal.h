@@ -109,9 +109,19 @@ hipError_t launch_prop_factor(float2* out, int n, double d, double lam, double d
                               hipStream_t s);
 hipError_t launch_aperture_count(int* count, int nx, int ny, double dx, double dy, double lam,
                                  double alpha, hipStream_t s);
+// Probe aberrations: polar coefficients C_nm [A] and angles phi_nm [rad] for
+// (n, m) = 10, 12, 21, 23, 30, 32, 34, 41, 43, 45, 50, 52, 54, 56; the probe
+// factor is exp(-i chi(k)), chi = (2 pi / lambda) sum C_nm alpha^(n+1) / (n+1)
+// cos(m (phi - phi_nm)), alpha = lambda |k|.
+constexpr int N_ABERR = 14;
+struct Aberrations {
+  double c[N_ABERR];
+  double phi[N_ABERR];
+  int on;
+};
 hipError_t launch_probe_fill(float2* out, const double* rloc /*[P][2]*/, const int* count, int n_probes,
                              int nx, int ny, double dx, double dy, double lam, double alpha,
-                             hipStream_t s);
+                             const Aberrations& ab, hipStream_t s);
 
 // Spectrum analysis reductions (FP64 sums of I[p][m][k]).
 hipError_t launch_spectral_diffraction(const float* spec, double* out, int n_probes, int n_bins, int n_k, int m,
@@ -120,5 +130,12 @@ hipError_t launch_spectrum_image(const float* spec, double* out, int n_probes, i
                                  const double* kx, const double* ky, double k_in2, double k_out2, hipStream_t s);
 hipError_t launch_dispersion(const float* spec, double* out, int n_probes, int n_bins, int n_k, const int* node,
                              int n_points, hipStream_t s);
+
+// Conventional STEM from kept exit waves: D[p][k] = (1/F) sum_f |psi[p][f][k]|^2
+// in FP64; A[p] = sum of D[p][k] over inner <= 1e3 lambda |k| < outer (mrad).
+hipError_t launch_mean_diffraction(const float2* exit, double* out, int n_probes, int n_frames, int n_k,
+                                   hipStream_t s);
+hipError_t launch_adf(const double* diff, double* out, int n_probes, int nx, int ny, const double* kx,
+                      const double* ky, double lam, double inner_mrad, double outer_mrad, hipStream_t s);
 
 }  // namespace tacaw

@@ -63,6 +63,7 @@ EXPORTED = [
     "tacaw_timing_enable", "tacaw_timing_select", "tacaw_timing_get", "tacaw_version", "tacaw_job_latency",
     "tacaw_run_batch", "tacaw_autotune", "tacaw_job_plan",
     "tacaw_spectral_diffraction", "tacaw_spectrum_image", "tacaw_dispersion",
+    "tacaw_job_set_aberrations", "tacaw_mean_diffraction", "tacaw_adf",
 ]
 
 
@@ -102,6 +103,9 @@ def lib() -> ctypes.CDLL:
         "tacaw_spectral_diffraction": [vp, dp, vp, sz, ctypes.c_int],
         "tacaw_spectrum_image": [vp, dp, dp, dp, vp, sz, ctypes.c_int],
         "tacaw_dispersion": [vp, P(dp), P(dp), i32, vp, sz, ctypes.c_int],
+        "tacaw_job_set_aberrations": [vp, P(dp), P(dp)],
+        "tacaw_mean_diffraction": [vp, vp, sz, ctypes.c_int],
+        "tacaw_adf": [vp, dp, dp, vp, sz, ctypes.c_int],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -229,6 +233,9 @@ class TacawJob:
         self.n_frames = self._d.desc.n_frames
         self.n_bins = self.n_frames if job.two_sided else self.n_frames // 2
         self.nx, self.ny = job.nx, job.ny
+        ab = getattr(job, "aberrations", None)
+        if ab is not None:
+            self.set_aberrations(ab[0], ab[1])
 
     # plain per-job form
     def run(self, stream=None):
@@ -326,6 +333,30 @@ class TacawJob:
         out = np.empty((kx.size, self.spectrum_shape[1]), dtype=np.float64)
         _check(lib().tacaw_dispersion(self.handle, _ptr(kx, ctypes.c_double), _ptr(ky, ctypes.c_double),
                                       int(kx.size), out.ctypes.data, out.size, 0))
+        return out
+
+    def set_aberrations(self, c_angstrom=None, phi_rad=None) -> None:
+        """Probe aberrations: 14 polar coefficients C_nm [A] and angles [rad]
+        for (n, m) = 10, 12, 21, 23, 30, 32, 34, 41, 43, 45, 50, 52, 54, 56."""
+        if c_angstrom is None:
+            _check(lib().tacaw_job_set_aberrations(self.handle, None, None))
+            return
+        c = np.ascontiguousarray(c_angstrom, dtype=np.float64).reshape(-1)
+        a = np.zeros(14) if phi_rad is None else np.ascontiguousarray(phi_rad, dtype=np.float64).reshape(-1)
+        if c.size != 14 or a.size != 14:
+            raise ValueError("need 14 aberration coefficients and 14 angles")
+        _check(lib().tacaw_job_set_aberrations(self.handle, _ptr(c, ctypes.c_double), _ptr(a, ctypes.c_double)))
+
+    def mean_diffraction(self) -> np.ndarray:
+        """Frame-averaged diffraction pattern of every probe: [P, ny, nx] float64."""
+        out = np.empty((self.n_probes, self.ny, self.nx), dtype=np.float64)
+        _check(lib().tacaw_mean_diffraction(self.handle, out.ctypes.data, out.size, 0))
+        return out
+
+    def adf(self, inner_mrad: float, outer_mrad: float) -> np.ndarray:
+        """Annular detector signal per probe over inner <= angle < outer (mrad)."""
+        out = np.empty(self.n_probes, dtype=np.float64)
+        _check(lib().tacaw_adf(self.handle, float(inner_mrad), float(outer_mrad), out.ctypes.data, out.size, 0))
         return out
 
     def plan(self) -> tuple:
