@@ -237,6 +237,43 @@ tacaw_status tacaw_get_exit_waves(tacaw_job* job, void* dst_c64, size_t n, int d
  * NULL. */
 tacaw_status tacaw_axes(const tacaw_job_desc* desc, double* kx, double* ky, double* f_THz);
 
+/* ---- frame ranges, checkpoints, trajectory averaging ----------------------
+ * (Methods 2.1 "Workflow Architecture": exit waves are kept per frame so that
+ * an interrupted simulation restarts without recomputing finished frames, and
+ * analyses run on stored waves; Methods 2.1 "Molecular Dynamics" and the
+ * Supplement's "Trajectory averaging": spectra of independent trajectories or
+ * of trajectory segments are averaged to reduce noise.)
+ *
+ * tacaw_run_frames computes the exit waves of frames [f_begin, f_end) into
+ * the job's exit store, asynchronously on hip_stream, exactly as tacaw_run
+ * computes them (per-frame arithmetic does not depend on the range), and
+ * leaves the spectrum alone.  tacaw_finish runs the time stage once every
+ * frame's exit waves are in the store (from tacaw_run_frames or
+ * tacaw_put_exit_frames; ENOTREADY otherwise) and makes the spectrum ready.
+ * Ranges must be non-empty within [0, n_frames) (EINVAL); EBUSY while the job
+ * is in the serving loop.  A job created without TACAW_KEEP_EXIT_WAVES keeps
+ * its store between these calls in the plain form too. */
+tacaw_status tacaw_run_frames(tacaw_job* job, int32_t f_begin, int32_t f_end, void* hip_stream);
+tacaw_status tacaw_finish(tacaw_job* job, void* hip_stream);
+
+/* Copy frames [f_begin, f_end) of the exit store out (get) or in (put), laid
+ * out [P][f_end - f_begin][ny][nx] complex64 (n = P * frames * ny * nx), for
+ * checkpoints.  Synchronous; host or (on_device != 0) device memory.  get
+ * needs frames that hold exit waves (ENOTREADY otherwise); put marks the
+ * frames as present, so a restarted job computes only the others. */
+tacaw_status tacaw_get_exit_frames(tacaw_job* job, int32_t f_begin, int32_t f_end, void* dst, size_t n,
+                                   int dst_on_device);
+tacaw_status tacaw_put_exit_frames(tacaw_job* job, int32_t f_begin, int32_t f_end, const void* src, size_t n,
+                                   int src_on_device);
+
+/* dst = (1/J) sum_j I_j over n_jobs jobs with spectra of one shape (P, bins,
+ * ny, nx) on one device (EINVAL otherwise), summed in FP64 in job order and
+ * rounded to float32; n = P * bins * ny * nx; host or (dst_on_device != 0)
+ * device destination.  Waits for every job's last run.  Averaging the
+ * segments of one trajectory is the same call over one job per segment. */
+tacaw_status tacaw_average_spectra(tacaw_job* const* jobs, int32_t n_jobs, float* dst, size_t n,
+                                   int dst_on_device);
+
 /* ---- spectrum analysis ----------------------------------------------------
  * Reductions of the job's resident spectrum I[p][m][ky][kx] (Methods 2.1,
  * "Data Structure Design": dispersion along reciprocal-space paths,

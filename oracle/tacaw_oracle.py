@@ -406,3 +406,22 @@ def adf(mean_diff: np.ndarray, kx: np.ndarray, ky: np.ndarray, lam: float,
     theta_mrad = 1e3 * lam * np.sqrt(kx[None, :] ** 2 + ky[:, None] ** 2)
     mask = (theta_mrad >= inner_mrad) & (theta_mrad < outer_mrad)
     return np.array([mean_diff[p][mask].sum() for p in range(mean_diff.shape[0])])
+
+
+# ---------------------------------------------------------------------------
+# Trajectory averaging (Methods 2.1 "Molecular Dynamics"; Supplement
+# "Trajectory averaging"): the spectra of independent trajectories, or of
+# consecutive segments of one trajectory, are averaged with equal weights.
+# ---------------------------------------------------------------------------
+def average_spectra(spectra) -> np.ndarray:
+    """(1/J) sum_j I_j over spectra of one shape."""
+    return np.mean(np.stack([np.asarray(s, dtype=np.float64) for s in spectra]), axis=0)
+
+
+def segment_average_spectrum(exit_k: np.ndarray, n_segments: int, two_sided: bool = False) -> np.ndarray:
+    """Average of the spectra of n_segments consecutive, equal, non-overlapping
+    frame segments (each with its own mean subtraction and transform length)."""
+    n_f = exit_k.shape[1]
+    length = n_f // n_segments
+    return average_spectra(tacaw_spectrum(exit_k[:, s * length:(s + 1) * length], two_sided)
+                           for s in range(n_segments))

@@ -136,6 +136,48 @@ tacaw_status mean_diffraction_dev(tacaw_job* job, hipStream_t s, DevBuf& out) {
 
 extern "C" {
 
+tacaw_status tacaw_average_spectra(tacaw_job* const* jobs, int32_t n_jobs, float* dst, size_t n,
+                                   int dst_on_device) {
+  clear_error();
+  if (!jobs || n_jobs < 1 || !dst) {
+    set_error("need n_jobs >= 1 jobs and a destination");
+    return TACAW_EINVAL;
+  }
+  std::vector<const float*> specs(n_jobs);
+  const tacaw_job* j0 = jobs[0];
+  for (int i = 0; i < n_jobs; ++i) {
+    tacaw_status st = check_ready(jobs[i]);
+    if (st != TACAW_OK) return st;
+    const HostPlan &a = j0->hp, &b = jobs[i]->hp;
+    if (a.P != b.P || a.M != b.M || a.nx != b.nx || a.ny != b.ny || jobs[i]->ctx->device != j0->ctx->device) {
+      set_error("job %d's spectrum shape or device differs from job 0's", i);
+      return TACAW_EINVAL;
+    }
+    specs[i] = jobs[i]->d_spec;
+  }
+  const HostPlan& hp = j0->hp;
+  if (n != (size_t)hp.P * hp.M * hp.nx * hp.ny) {
+    set_error("dst must hold n_probes * bins * ny * nx = %zu values", (size_t)hp.P * hp.M * hp.nx * hp.ny);
+    return TACAW_EINVAL;
+  }
+  A_TRY(hipSetDevice(j0->ctx->device));
+  // every job's last run must be complete before its spectrum is read
+  for (int i = 0; i < n_jobs; ++i) A_TRY(hipStreamSynchronize(jobs[i]->last_stream));
+  hipStream_t s = j0->last_stream;
+  DevBuf ptrs, out;
+  A_TRY(hipMalloc(&ptrs.p, n_jobs * sizeof(const float*)));
+  A_TRY(hipMemcpy(ptrs.p, specs.data(), n_jobs * sizeof(const float*), hipMemcpyHostToDevice));
+  float* o = dst;
+  if (!dst_on_device) {
+    A_TRY(hipMalloc(&out.p, n * sizeof(float)));
+    o = (float*)out.p;
+  }
+  A_TRY(launch_average_spectra((const float* const*)ptrs.p, n_jobs, o, n, s));
+  A_TRY(hipStreamSynchronize(s));
+  if (!dst_on_device) A_TRY(hipMemcpy(dst, o, n * sizeof(float), hipMemcpyDeviceToHost));
+  return TACAW_OK;
+}
+
 tacaw_status tacaw_mean_diffraction(tacaw_job* job, double* dst, size_t n, int dst_on_device) {
   clear_error();
   tacaw_status st = check_exit(job);

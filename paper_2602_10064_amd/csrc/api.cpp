@@ -556,6 +556,8 @@ tacaw_status tacaw_job_create(tacaw_ctx* ctx, const tacaw_job_desc* d, const int
   return TACAW_OK;
 }
 
+static void mark_present(tacaw_job* job, int f_begin, int f_end);
+
 tacaw_status tacaw_run(tacaw_job* job, void* hip_stream) {
   clear_error();
   if (!job) {
@@ -605,7 +607,128 @@ tacaw_status tacaw_run(tacaw_job* job, void* hip_stream) {
   if (st != TACAW_OK) return st;
   st = run_time_stage(job, s);
   if (st != TACAW_OK) return st;
+  mark_present(job, 0, job->hp.F);
   job->has_result = true;
+  return TACAW_OK;
+}
+
+// ---- frame ranges, checkpoints and the deferred time stage ----------------
+static tacaw_status check_idle(tacaw_job* job) {
+  if (!job) {
+    set_error("job is NULL");
+    return TACAW_EINVAL;
+  }
+  const int ss = job->serve_state.load();
+  if (ss == 1 || ss == 2) {
+    set_error("job is in the serving loop");
+    return TACAW_EBUSY;
+  }
+  return TACAW_OK;
+}
+
+static tacaw_status check_range(const tacaw_job* job, int32_t f_begin, int32_t f_end) {
+  if (f_begin < 0 || f_end > job->hp.F || f_begin >= f_end) {
+    set_error("frame range [%d, %d) is empty or outside [0, %d)", f_begin, f_end, job->hp.F);
+    return TACAW_EINVAL;
+  }
+  return TACAW_OK;
+}
+
+static void mark_present(tacaw_job* job, int f_begin, int f_end) {
+  if (job->present.size() != (size_t)job->hp.F) job->present.assign(job->hp.F, 0);
+  for (int f = f_begin; f < f_end; ++f) job->present[f] = 1;
+}
+
+tacaw_status tacaw_run_frames(tacaw_job* job, int32_t f_begin, int32_t f_end, void* hip_stream) {
+  clear_error();
+  tacaw_status st = check_idle(job);
+  if (st != TACAW_OK) return st;
+  if ((st = check_range(job, f_begin, f_end)) != TACAW_OK) return st;
+  HIP_TRY(hipSetDevice(job->ctx->device));
+  if ((st = materialize(job)) != TACAW_OK) return st;
+  hipStream_t s = (hipStream_t)hip_stream;
+  job->last_stream = s;
+  if ((st = run_batch_range(job, s, f_begin, f_end)) != TACAW_OK) return st;
+  mark_present(job, f_begin, f_end);
+  return TACAW_OK;
+}
+
+tacaw_status tacaw_finish(tacaw_job* job, void* hip_stream) {
+  clear_error();
+  tacaw_status st = check_idle(job);
+  if (st != TACAW_OK) return st;
+  int missing = job->hp.F;
+  if (job->present.size() == (size_t)job->hp.F)
+    for (uint8_t v : job->present) missing -= v ? 1 : 0;
+  if (missing > 0 || !job->materialized) {
+    set_error("%d of %d frames have no exit waves yet", missing, job->hp.F);
+    return TACAW_ENOTREADY;
+  }
+  HIP_TRY(hipSetDevice(job->ctx->device));
+  hipStream_t s = (hipStream_t)hip_stream;
+  job->last_stream = s;
+  if ((st = run_time_stage(job, s)) != TACAW_OK) return st;
+  job->has_result = true;
+  return TACAW_OK;
+}
+
+// [P][f_end - f_begin][ny][nx] complex64 of the store's frames, per probe
+static tacaw_status exit_frames_copy(tacaw_job* job, int32_t f_begin, int32_t f_end, void* host_or_dev,
+                                     int on_device, bool to_store) {
+  const HostPlan& hp = job->hp;
+  const size_t nk = (size_t)hp.nx * hp.ny, nf = (size_t)(f_end - f_begin);
+  const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice
+                                       : (to_store ? hipMemcpyHostToDevice : hipMemcpyDeviceToHost);
+  HIP_TRY(hipStreamSynchronize(job->last_stream));
+  for (int p = 0; p < hp.P; ++p) {
+    float2* store = job->d_exit + ((size_t)p * hp.F + f_begin) * nk;
+    float2* user = (float2*)host_or_dev + (size_t)p * nf * nk;
+    if (to_store)
+      HIP_TRY(hipMemcpy(store, user, nf * nk * sizeof(float2), kind));
+    else
+      HIP_TRY(hipMemcpy(user, store, nf * nk * sizeof(float2), kind));
+  }
+  return TACAW_OK;
+}
+
+tacaw_status tacaw_get_exit_frames(tacaw_job* job, int32_t f_begin, int32_t f_end, void* dst, size_t n,
+                                   int dst_on_device) {
+  clear_error();
+  tacaw_status st = check_idle(job);
+  if (st != TACAW_OK) return st;
+  if ((st = check_range(job, f_begin, f_end)) != TACAW_OK) return st;
+  const HostPlan& hp = job->hp;
+  if (!dst || n != (size_t)hp.P * (f_end - f_begin) * hp.nx * hp.ny) {
+    set_error("dst must hold n_probes * frames * ny * nx = %zu complex values",
+              (size_t)hp.P * (f_end - f_begin) * hp.nx * hp.ny);
+    return TACAW_EINVAL;
+  }
+  for (int f = f_begin; f < f_end; ++f)
+    if (!job->has_result && (job->present.size() != (size_t)hp.F || !job->present[f])) {
+      set_error("frame %d has no exit waves yet", f);
+      return TACAW_ENOTREADY;
+    }
+  HIP_TRY(hipSetDevice(job->ctx->device));
+  return exit_frames_copy(job, f_begin, f_end, dst, dst_on_device, false);
+}
+
+tacaw_status tacaw_put_exit_frames(tacaw_job* job, int32_t f_begin, int32_t f_end, const void* src, size_t n,
+                                   int src_on_device) {
+  clear_error();
+  tacaw_status st = check_idle(job);
+  if (st != TACAW_OK) return st;
+  if ((st = check_range(job, f_begin, f_end)) != TACAW_OK) return st;
+  const HostPlan& hp = job->hp;
+  if (!src || n != (size_t)hp.P * (f_end - f_begin) * hp.nx * hp.ny) {
+    set_error("src must hold n_probes * frames * ny * nx = %zu complex values",
+              (size_t)hp.P * (f_end - f_begin) * hp.nx * hp.ny);
+    return TACAW_EINVAL;
+  }
+  HIP_TRY(hipSetDevice(job->ctx->device));
+  if ((st = materialize(job)) != TACAW_OK) return st;
+  if ((st = exit_frames_copy(job, f_begin, f_end, const_cast<void*>(src), src_on_device, true)) != TACAW_OK)
+    return st;
+  mark_present(job, f_begin, f_end);
   return TACAW_OK;
 }
 

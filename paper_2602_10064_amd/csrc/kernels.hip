@@ -1711,6 +1711,22 @@ __global__ void __launch_bounds__(256) k_adf(const double* diff, double* out, in
   if (threadIdx.x == 0) out[p] = part[0];
 }
 
+// I_avg = (1/J) sum_j I_j element by element, FP64 sums in job order
+__global__ void __launch_bounds__(256) k_average_spectra(const float* const* specs, int n_jobs, float* out,
+                                                         size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int j = 0; j < n_jobs; ++j) acc += (double)specs[j][i];
+    out[i] = (float)(acc / n_jobs);
+  }
+}
+
+hipError_t launch_average_spectra(const float* const* specs, int n_jobs, float* out, size_t n, hipStream_t s) {
+  const size_t blocks = std::min<size_t>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_average_spectra, dim3((unsigned)blocks), dim3(256), 0, s, specs, n_jobs, out, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_mean_diffraction(const float2* exit, double* out, int n_probes, int n_frames, int n_k,
                                    hipStream_t s) {
   hipLaunchKernelGGL(k_mean_diffraction, dim3((n_k + 255) / 256, n_probes), dim3(256), 0, s, exit, out, n_frames,

@@ -149,6 +149,9 @@ struct tacaw_job {
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_splat[2] = {nullptr, nullptr}, ev_row[2] = {nullptr, nullptr};
   bool has_result = false;
+  // frames whose exit waves the store holds from tacaw_run_frames or
+  // tacaw_put_exit_frames (one flag per frame), for tacaw_finish
+  std::vector<uint8_t> present;
   // HIP-graph replay of the whole launch sequence (TACAW_USE_GRAPH)
   hipStream_t capture_stream = nullptr;
   hipGraph_t graph = nullptr;

@@ -133,6 +133,9 @@ hipError_t launch_dispersion(const float* spec, double* out, int n_probes, int n
 
 // Conventional STEM from kept exit waves: D[p][k] = (1/F) sum_f |psi[p][f][k]|^2
 // in FP64; A[p] = sum of D[p][k] over inner <= 1e3 lambda |k| < outer (mrad).
+// Trajectory averaging: out[i] = (1/J) sum_j specs[j][i] (FP64 sums in order).
+hipError_t launch_average_spectra(const float* const* specs /*device array of J*/, int n_jobs, float* out,
+                                  size_t n, hipStream_t s);
 hipError_t launch_mean_diffraction(const float2* exit, double* out, int n_probes, int n_frames, int n_k,
                                    hipStream_t s);
 hipError_t launch_adf(const double* diff, double* out, int n_probes, int nx, int ny, const double* kx,

@@ -64,6 +64,8 @@ EXPORTED = [
     "tacaw_run_batch", "tacaw_autotune", "tacaw_job_plan",
     "tacaw_spectral_diffraction", "tacaw_spectrum_image", "tacaw_dispersion",
     "tacaw_job_set_aberrations", "tacaw_mean_diffraction", "tacaw_adf",
+    "tacaw_run_frames", "tacaw_finish", "tacaw_get_exit_frames", "tacaw_put_exit_frames",
+    "tacaw_average_spectra",
 ]
 
 
@@ -106,6 +108,11 @@ def lib() -> ctypes.CDLL:
         "tacaw_job_set_aberrations": [vp, P(dp), P(dp)],
         "tacaw_mean_diffraction": [vp, vp, sz, ctypes.c_int],
         "tacaw_adf": [vp, dp, dp, vp, sz, ctypes.c_int],
+        "tacaw_run_frames": [vp, i32, i32, vp],
+        "tacaw_finish": [vp, vp],
+        "tacaw_get_exit_frames": [vp, i32, i32, vp, sz, ctypes.c_int],
+        "tacaw_put_exit_frames": [vp, i32, i32, vp, sz, ctypes.c_int],
+        "tacaw_average_spectra": [P(vp), i32, vp, sz, ctypes.c_int],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -335,6 +342,29 @@ class TacawJob:
                                       int(kx.size), out.ctypes.data, out.size, 0))
         return out
 
+    # frame ranges and checkpoints
+    def run_frames(self, f_begin: int, f_end: int, stream=None) -> None:
+        """Exit waves of frames [f_begin, f_end) only; the spectrum waits for finish()."""
+        _check(lib().tacaw_run_frames(self.handle, int(f_begin), int(f_end), _stream_handle(stream)))
+
+    def finish(self, stream=None) -> None:
+        """Time stage over the complete exit store."""
+        _check(lib().tacaw_finish(self.handle, _stream_handle(stream)))
+
+    def exit_frames(self, f_begin: int, f_end: int) -> np.ndarray:
+        """Frames [f_begin, f_end) of the exit store: [P, frames, ny, nx] complex64."""
+        out = np.empty((self.n_probes, f_end - f_begin, self.ny, self.nx), dtype=np.complex64)
+        _check(lib().tacaw_get_exit_frames(self.handle, int(f_begin), int(f_end), out.ctypes.data, out.size, 0))
+        return out
+
+    def put_exit_frames(self, f_begin: int, waves: np.ndarray) -> None:
+        """Restore frames [f_begin, f_begin + waves.shape[1]) of the exit store."""
+        w = np.ascontiguousarray(waves, dtype=np.complex64)
+        if w.ndim != 4 or w.shape[0] != self.n_probes or w.shape[2:] != (self.ny, self.nx):
+            raise ValueError(f"need [{self.n_probes}, frames, {self.ny}, {self.nx}] exit waves")
+        _check(lib().tacaw_put_exit_frames(self.handle, int(f_begin), int(f_begin + w.shape[1]), w.ctypes.data,
+                                           w.size, 0))
+
     def set_aberrations(self, c_angstrom=None, phi_rad=None) -> None:
         """Probe aberrations: 14 polar coefficients C_nm [A] and angles [rad]
         for (n, m) = 10, 12, 21, 23, 30, 32, 34, 41, 43, 45, 50, 52, 54, 56."""
@@ -404,3 +434,14 @@ def axes(job):
 
 def version() -> str:
     return lib().tacaw_version().decode()
+
+
+def average_spectra(jobs) -> np.ndarray:
+    """(1/J) sum_j I_j over jobs with spectra of one shape, on the device: float32."""
+    jobs = list(jobs)
+    if not jobs:
+        raise ValueError("need at least one job")
+    arr = (ctypes.c_void_p * len(jobs))(*[j.handle.value for j in jobs])
+    out = np.empty(jobs[0].spectrum_shape, dtype=np.float32)
+    _check(lib().tacaw_average_spectra(arr, len(jobs), out.ctypes.data, out.size, 0))
+    return out

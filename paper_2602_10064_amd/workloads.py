@@ -373,3 +373,14 @@ def random_small_job(seed: int, nx: int = 16, ny: int = 16, n_slices: int = 3,
                aperture_mrad=aperture_mrad, dt_fs=5.0, positions=pos, atom_species=sp,
                species_Z=zs, gauss_a=ga, gauss_b=gb, probe_xy=probes, pot_nx=pnx,
                pot_ny=pny, two_sided=two_sided, name=f"random{seed}")
+
+
+def frame_segments(job: Job, n_segments: int) -> List[Job]:
+    """Consecutive, equal, non-overlapping frame segments of a job's trajectory,
+    one job each (frames beyond n_segments * (F // n_segments) are dropped)."""
+    length = job.n_frames // n_segments
+    if length < 2:
+        raise ValueError("segments need at least two frames")
+    return [dataclasses.replace(job, positions=job.positions[s * length:(s + 1) * length].copy(),
+                                name=f"{job.name}_seg{s}")
+            for s in range(n_segments)]
