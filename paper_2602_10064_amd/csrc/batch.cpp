@@ -194,7 +194,7 @@ void load_tune_cache(tacaw_ctx* c) {
     int nx = 0, ny = 0, r = 0, cc = 0;
     if (sscanf(line.c_str(), "{\"nx\": %d, \"ny\": %d, \"row_variant\": %d, \"col_variant\": %d}", &nx, &ny, &r,
                &cc) == 4 &&
-        nx > 0 && nx < 2048 && ny > 0 && ny < 2048 && r >= 0 && r <= 3 && cc >= 0 && cc <= 3) {
+        nx > 0 && nx < 2048 && ny > 0 && ny < 2048 && r >= 0 && r <= 3 && cc >= 0 && cc <= 5) {
       c->row_variant[nx] = r + 1;
       c->col_variant[ny] = cc + 1;
     }
@@ -344,18 +344,20 @@ tacaw_status tacaw_autotune(tacaw_job* job, void* hip_stream, int* row_variant, 
   const HostPlan& hp = job->hp;
   const int fb = std::min(hp.fb, hp.F);
   // row variants: 0, 1 (LDS rows), 2, 3 (register FFT with one or two rows
-  // in flight, grids 64-512);
+  // in flight, grids 64-1024);
   // column variants: 0, 1 (LDS columns), 2 (register FFT on 8-32 column
-  // tiles, ny 64-512), 3 (16-column tiles, ny 512)
+  // tiles, ny 64-1024), 3 (16-column tiles, ny 512), 5 (six-step, ny 512)
   auto reg = [](int n) { return n == 64 || n == 128 || n == 256 || n == 384 || n == 512 || n == 768 || n == 1024; };
+  const int row_cand[4] = {0, 1, 2, 3};
+  const int col_cand[5] = {0, 1, 2, 3, 5};
   const int n_row_var = reg(hp.nx) ? 4 : 2;
-  const int n_col_var = hp.ny == 512 ? 4 : reg(hp.ny) ? 3 : 2;
+  const int n_col_var = hp.ny == 512 ? 5 : reg(hp.ny) ? 3 : 2;
   const int n_var = std::max(n_row_var, n_col_var);
-  double best_row[4] = {1e30, 1e30, 1e30, 1e30}, best_col[4] = {1e30, 1e30, 1e30, 1e30};
+  double best_row[5] = {1e30, 1e30, 1e30, 1e30, 1e30}, best_col[5] = {1e30, 1e30, 1e30, 1e30, 1e30};
   const bool was_timing = c->timing;
   for (int v = 0; v < n_var; ++v) {
-    c->row_variant[hp.nx] = std::min(v, n_row_var - 1) + 1;
-    c->col_variant[hp.ny] = std::min(v, n_col_var - 1) + 1;
+    c->row_variant[hp.nx] = row_cand[std::min(v, n_row_var - 1)] + 1;
+    c->col_variant[hp.ny] = col_cand[std::min(v, n_col_var - 1)] + 1;
     for (int rep = 0; rep < 2; ++rep) {   // first repetition warms up
       {
         std::lock_guard<std::mutex> lk(c->mu);
@@ -386,6 +388,8 @@ tacaw_status tacaw_autotune(tacaw_job* job, void* hip_stream, int* row_variant, 
     if (best_row[v] < best_row[rv]) rv = v;
   for (int v = 1; v < n_col_var; ++v)
     if (best_col[v] < best_col[cv]) cv = v;
+  rv = row_cand[rv];
+  cv = col_cand[cv];
   c->row_variant[hp.nx] = rv + 1;
   c->col_variant[hp.ny] = cv + 1;
   if (row_variant) *row_variant = rv;

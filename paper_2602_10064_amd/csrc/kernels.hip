@@ -875,6 +875,140 @@ __global__ void __launch_bounds__((C8<N, WIDE>::THREADS)) k_col_r8(PassTable tab
 }
 
 // ---------------------------------------------------------------------------
+// Column pass for ny = 512 as 512 = 8 x 64 (six-step), tiles of 8 columns.
+// Lanes run along x, so a tile is read and written straight from its rows in
+// 64-byte segments with no LDS transpose:
+//   layout A: column c = lane % 8, r0 = 8 wave + lane / 8, values at rows
+//             r0 + 64 j (j < 8): 8-point transform over j, twiddle
+//             W512^(r0 k1), exchange through LDS to
+//   layout B: k1 = wave, column lane / 8, u = lane % 8, values at r0 = u + 8 q:
+//             8-point transform over q, twiddle W64^(u k2), a wavefront-local
+//             exchange, 8-point transform over u: frequency k1 + 8 u + 64 k3
+//             held as k3 < 8.
+// The propagator is applied in that order, and the inverse retraces the same
+// steps backwards (conjugate twiddles), ending in layout A for the store.  The
+// last slice stores the spectrum straight from layout B.  Per tile: two
+// exchanges across wavefronts and two within one, against two transposes and
+// four exchanges in k_col_r8.  LDS slots: [k1][r0][c ^ (r0 % 8)] for the
+// cross-wavefront exchanges, and, inside wavefront k1's own 512 slots,
+// 64 c + 8 (u ^ (c % 2)) + (k2 ^ u) for the local ones; every 16-lane group of
+// an access hits 16 distinct 8-byte slots modulo 16.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(512) k_col_6s(PassTable tab, int total_tiles) {
+  constexpr int N = 512, CT = 8;
+  __shared__ float2 xs[4096];
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int ca = lane & 7, r0 = 8 * wave + (lane >> 3);   // layout A
+  const int k1 = wave, cb = lane >> 3, u = lane & 7;      // layout B
+  // slots
+  const int sa = 8 * r0 + (ca ^ (r0 & 7));                 // + 512 k1
+  const int sb = 512 * k1 + 8 * u + (cb ^ u);              // + 64 q
+  float2* lw = xs + 512 * k1 + 64 * cb;                    // local exchange region
+  const int lodd = cb & 1;
+  // twiddles, the same for every tile (all lanes of a table have ny = 512)
+  float2 ta[8], tb[8];   // entries 1..7 (entry 0 is 1 and never used)
+  {
+    const float2* tw = tab.l[0].a.tw_y;
+#pragma unroll
+    for (int k = 1; k < 8; ++k) {
+      ta[k] = tw[(r0 * k) & (N - 1)];
+      tb[k] = tw[(8 * u * k) & (N - 1)];
+    }
+  }
+  auto locate = [&](int it, int& L, int& x0, float2*& wp) {
+    const int tile_g = xcd_remap(it, total_tiles);
+    L = find_lane(tab, tile_g);
+    const PassArgs& a = tab.l[L].a;
+    const int tile = tile_g - tab.l[L].block_start;
+    const int tiles_per_wave = a.nx / CT;
+    const int w = tile / tiles_per_wave;
+    x0 = (tile % tiles_per_wave) * CT;
+    const int p = w / a.fb;
+    const int fl = w % a.fb;
+    wp = a.exit + ((size_t)p * a.n_frames + a.f0 + fl) * (size_t)N * a.nx;
+  };
+  float2 pre[8];
+  int L = 0, x0 = 0;
+  float2* wp = nullptr;
+  int it = blockIdx.x;
+  if (it < total_tiles) {
+    locate(it, L, x0, wp);
+    const int nx = tab.l[L].a.nx;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) pre[j] = wp[(size_t)(r0 + 64 * j) * nx + x0 + ca];
+  }
+  for (; it < total_tiles; it += gridDim.x) {
+    const PassArgs& a = tab.l[L].a;
+    const int mode = tab.l[L].mode;
+    const int nx = a.nx;
+    const int cur_x0 = x0;
+    float2* cur_wp = wp;
+    float2 x[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) x[j] = pre[j];
+    // the next tile's loads complete during this tile's arithmetic
+    const int nit = it + gridDim.x;
+    if (nit < total_tiles) {
+      locate(nit, L, x0, wp);
+      const int nnx = tab.l[L].a.nx;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) pre[j] = wp[(size_t)(r0 + 64 * j) * nnx + x0 + ca];
+    }
+    // layout A: 8-point transform over j, twiddle, to LDS
+    dft8<false>(x);
+#pragma unroll
+    for (int k = 1; k < 8; ++k) x[k] = cmul(x[k], ta[k]);
+    __syncthreads();   // the previous tile's reads of the exchange buffer are done
+#pragma unroll
+    for (int k = 0; k < 8; ++k) xs[512 * k + sa] = x[k];
+    __syncthreads();
+    // layout B: 8-point transform over q, twiddle, local exchange, over u
+#pragma unroll
+    for (int q = 0; q < 8; ++q) x[q] = xs[sb + 64 * q];
+    dft8<false>(x);
+#pragma unroll
+    for (int k = 1; k < 8; ++k) x[k] = cmul(x[k], tb[k]);
+    wave_lds_sync();
+#pragma unroll
+    for (int k = 0; k < 8; ++k) lw[8 * (u ^ lodd) + (k ^ u)] = x[k];
+    wave_lds_sync();
+#pragma unroll
+    for (int v = 0; v < 8; ++v) x[v] = lw[8 * (v ^ lodd) + (u ^ v)];
+    dft8<false>(x);   // x[k3] = psi(k1 + 8 u + 64 k3) of column cur_x0 + cb
+    const float2 pxv = a.px[cur_x0 + cb];
+    const bool last = mode == COL_LAST;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[k] = cmul(x[k], cmul(pxv, a.py[k1 + 8 * u + 64 * k]));
+    if (last) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) cur_wp[(size_t)(k1 + 8 * u + 64 * k) * nx + cur_x0 + cb] = x[k];
+      continue;
+    }
+    // inverse, the same steps backwards
+    dft8<true>(x);    // over k3: x[v] at u-index v, this lane's k2 = u
+    wave_lds_sync();
+#pragma unroll
+    for (int v = 0; v < 8; ++v) lw[8 * (v ^ lodd) + (u ^ v)] = x[v];
+    wave_lds_sync();
+    x[0] = lw[8 * (u ^ lodd) + u];
+#pragma unroll
+    for (int k = 1; k < 8; ++k) x[k] = cmulc(lw[8 * (u ^ lodd) + (k ^ u)], tb[k]);
+    dft8<true>(x);    // over k2: x[q] at r0 = u + 8 q
+    wave_lds_sync();
+#pragma unroll
+    for (int q = 0; q < 8; ++q) xs[sb + 64 * q] = x[q];
+    __syncthreads();
+    // layout A: conjugate twiddle, 8-point transform over k1, store
+    x[0] = xs[sa];
+#pragma unroll
+    for (int k = 1; k < 8; ++k) x[k] = cmulc(xs[512 * k + sa], ta[k]);
+    dft8<true>(x);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) cur_wp[(size_t)(r0 + 64 * j) * nx + cur_x0 + ca] = x[j];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Register FFTs with 12 or 16 values per lane (N = 384 and 768: 12 values,
 // radices 6, 4, 4, 4 [, 2]; N = 1024: 16 values, radices 8, 8, 4, 4).  Same
 // layout and wavefront-local exchanges as the 8-value kernels; the stage
@@ -1514,11 +1648,33 @@ static hipError_t col_r8_launch(PassTable& t, hipStream_t s) {
   return hipGetLastError();
 }
 
+static hipError_t col_6s_launch(PassTable& t, hipStream_t s) {
+  int tiles = 0;
+  for (int i = 0; i < t.n; ++i) {
+    const PassArgs& a = t.l[i].a;
+    if (a.ny != 512 || a.nx % 8 != 0) return hipErrorInvalidValue;
+    t.l[i].block_start = tiles;
+    tiles += a.n_probes * a.fb * (a.nx / 8);
+  }
+  const char* ge = getenv("TACAW_COL_GRID");
+  const int cap = ge && atoi(ge) > 0 ? atoi(ge) : 2048;
+  const int grid = std::min(tiles, cap);
+  TACAW_LAUNCH(k_col_6s, dim3(grid), dim3(512), 0, s, t, tiles);
+  return hipGetLastError();
+}
+
 hipError_t launch_col_lanes(const PassLane* lanes, int n, int variant, hipStream_t s) {
   if (n < 1 || n > MAX_LANES || !same_grid(lanes, n)) return hipErrorInvalidValue;
   PassTable t{};
   t.n = n;
   for (int i = 0; i < n; ++i) t.l[i] = lanes[i];
+  if (variant == 5) {
+    // six-step kernel: ny = 512, regular and last-slice modes
+    bool ok = lanes[0].a.ny == 512 && lanes[0].a.nx % 8 == 0;
+    for (int i = 0; i < n; ++i) ok = ok && lanes[i].mode != COL_INVERSE_ONLY;
+    if (ok) return col_6s_launch(t, s);
+    variant = 2;
+  }
   if (variant == 4) {
     const int ny = lanes[0].a.ny, nx = lanes[0].a.nx;
     if (ny == 512 && nx % C8<512, 0>::CT == 0) return col_r8_launch<512, 0, 1>(t, s);

@@ -245,10 +245,10 @@ def test_overlapped_potentials_graph_replay(tacaw, ctx, monkeypatch):
             (x * 2).sum().item()
 
 
-@pytest.mark.parametrize("variant", ["2", "3", "4"])
+@pytest.mark.parametrize("variant", ["2", "3", "4", "5"])
 def test_c2_shape_register_column_kernels(tacaw, ctx, oracle, monkeypatch, variant):
-    # register column pass on 8-column tiles (2), 16-column tiles (3) and
-    # 8-column tiles with two LDS buffers (4)
+    # register column pass on 8-column tiles (2), 16-column tiles (3),
+    # 8-column tiles with two LDS buffers (4) and the six-step kernel (5)
     monkeypatch.setenv("TACAW_COL_VARIANT", variant)
     monkeypatch.setenv("TACAW_FB", "3")
     job = w.c2_plain(n_frames=5)
