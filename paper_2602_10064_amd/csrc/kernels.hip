@@ -1656,8 +1656,10 @@ static hipError_t col_6s_launch(PassTable& t, hipStream_t s) {
     t.l[i].block_start = tiles;
     tiles += a.n_probes * a.fb * (a.nx / 8);
   }
+  // grid stride over the tiles; TACAW_COL_GRID caps the grid (default 1024,
+  // two generations of the two resident workgroups per CU)
   const char* ge = getenv("TACAW_COL_GRID");
-  const int cap = ge && atoi(ge) > 0 ? atoi(ge) : 2048;
+  const int cap = ge && atoi(ge) > 0 ? atoi(ge) : 1024;
   const int grid = std::min(tiles, cap);
   TACAW_LAUNCH(k_col_6s, dim3(grid), dim3(512), 0, s, t, tiles);
   return hipGetLastError();
