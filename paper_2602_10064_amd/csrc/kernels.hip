@@ -317,13 +317,18 @@ __global__ void __launch_bounds__(256) k_splat(SplatTable tab) {
           // node j sits at d = j - u pixels from the atom, u = f - o.  Every
           // node of a tile the term's box reaches gets the exact value (beyond
           // the radius it is below 1e-8 of the peak, or underflows to 0; only
-          // this image reaches the tile), which saves the cutoff test.
-          const float u = fp - (float)(o + nbase);
-          const float ne2 = -e2;
+          // this image reaches the tile), which saves the cutoff test.  The
+          // value amp 2^(-e2 d^2) is 2^(A x^2 + B x + C) with x = j - NPL/2
+          // (centred, so the terms stay small), A = -e2, B = 2 e2 u',
+          // C = log2(amp) - e2 u'^2, u' = u - NPL/2: two FMAs and one exp2
+          // per node.
+          const float up = fp - (float)(o + nbase) - (float)(NPL / 2);
+          const float la = along_y ? c[5] : 0.f;
+          const float qa = -e2, qb = 2.f * e2 * up, qc = fmaf(-e2 * up, up, la);
 #pragma unroll
           for (int x = 0; x < NPL; ++x) {
-            const float d = (float)x - u;
-            dst[x * PS] = amp * __builtin_amdgcn_exp2f(ne2 * d * d);
+            const float xc = (float)(x - NPL / 2);
+            dst[x * PS] = __builtin_amdgcn_exp2f(fmaf(qa, xc * xc, fmaf(qb, xc, qc)));
           }
         } else {
           const int img = along_y ? a.img_y : a.img_x;

@@ -323,6 +323,7 @@ tacaw_status plan_job(const tacaw_job_desc* d, const int32_t* atom_species, cons
       o[2] = (float)(c * hp.dy * hp.dy / M_LN2);
       o[3] = (float)(rci / hp.dx);
       o[4] = (float)(rci / hp.dy);
+      o[5] = (float)log2(cpref * a * M_PI / b);   // amplitudes are positive (validated)
     }
 
   // Candidate (atom, term) pairs per (slice, tile): a term of an atom is listed
