@@ -32,6 +32,9 @@ def uneven_jobs():
         w.random_small_job(44, nx=32, ny=32, n_slices=3, n_frames=12, cell=(10.0, 9.0, 4.0),
                            aperture_mrad=25.0, n_probes=4, pot_grid=(100, 90)),
         w.c2_plain(n_frames=6, grid=256, n_slices=8, reps=(6, 6, 2)),
+        # two jobs of 512 rows share the six-step column kernel's launches
+        w.random_small_job(45, nx=64, ny=512, n_slices=3, n_frames=10, cell=(8.0, 64.0, 4.0), n_atoms=20),
+        w.random_small_job(46, nx=64, ny=512, n_slices=4, n_frames=7, cell=(8.0, 64.0, 4.0), n_atoms=15),
     ]
 
 

@@ -255,6 +255,17 @@ def test_c2_shape_register_column_kernels(tacaw, ctx, oracle, monkeypatch, varia
     check_job(tacaw, ctx, oracle, job)
 
 
+@pytest.mark.parametrize("variant", ["2", "5"])
+def test_512_rows_narrow_grid(tacaw, ctx, oracle, monkeypatch, variant):
+    # 512 rows and 64 columns: the six-step column kernel (default at 512 rows)
+    # and the register kernel, probes included, ragged frame batches
+    monkeypatch.setenv("TACAW_COL_VARIANT", variant)
+    monkeypatch.setenv("TACAW_FB", "4")
+    job = w.random_small_job(47, nx=64, ny=512, n_slices=3, n_frames=10, cell=(8.0, 64.0, 4.0), n_atoms=20,
+                             aperture_mrad=25.0, n_probes=2)
+    check_job(tacaw, ctx, oracle, job)
+
+
 def test_splat_rounds_of_16(tacaw, ctx, oracle, monkeypatch):
     # potentials built in rounds of 16 (atom, term) pairs: same values as
     # rounds of 32 up to the order of the FP32 sums, parity with the oracle
