@@ -34,7 +34,7 @@ def uneven_jobs():
         w.c2_plain(n_frames=6, grid=256, n_slices=8, reps=(6, 6, 2)),
         # two jobs of 512 rows share the six-step column kernel's launches
         w.random_small_job(45, nx=64, ny=512, n_slices=3, n_frames=10, cell=(8.0, 64.0, 4.0), n_atoms=20),
-        w.random_small_job(46, nx=64, ny=512, n_slices=4, n_frames=7, cell=(8.0, 64.0, 4.0), n_atoms=15),
+        w.random_small_job(46, nx=64, ny=512, n_slices=4, n_frames=8, cell=(8.0, 64.0, 4.0), n_atoms=15),
     ]
 
 
