@@ -899,14 +899,9 @@ __global__ void __launch_bounds__((C8<N, WIDE>::THREADS)) k_col_r8(PassTable tab
 // 64 c + 8 (u ^ (c % 2)) + (k2 ^ u) for the local ones; every 16-lane group of
 // an access hits 16 distinct 8-byte slots modulo 16.
 // ---------------------------------------------------------------------------
-// PD tiles are prefetched ahead (1 or 2).  With two, the twiddles are read
-// from a 512-entry table in LDS instead of registers, to stay within 128 VGPRs.
-template <int PD>
 __global__ void __launch_bounds__(512) k_col_6s(PassTable tab, int total_tiles) {
   constexpr int N = 512, CT = 8;
-  static_assert(PD == 1 || PD == 2, "prefetch depth 1 or 2");
   __shared__ float2 xs[4096];
-  __shared__ float2 twl[PD == 2 ? N : 1];
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int ca = lane & 7, r0 = 8 * wave + (lane >> 3);   // layout A
   const int k1 = wave, cb = lane >> 3, u = lane & 7;      // layout B
@@ -921,15 +916,10 @@ __global__ void __launch_bounds__(512) k_col_6s(PassTable tab, int total_tiles) 
     const float2* tw = tab.l[0].a.tw_y;
 #pragma unroll
     for (int k = 1; k < 8; ++k) {
-      if (PD == 1) {
-        ta[k] = tw[(r0 * k) & (N - 1)];
-        tb[k] = tw[(8 * u * k) & (N - 1)];
-      }
+      ta[k] = tw[(r0 * k) & (N - 1)];
+      tb[k] = tw[(8 * u * k) & (N - 1)];
     }
-    if (PD == 2) twl[threadIdx.x] = tw[threadIdx.x];   // 512 threads, 512 entries
   }
-  auto twa = [&](int k) -> float2 { return PD == 1 ? ta[k] : twl[(r0 * k) & (N - 1)]; };
-  auto twb = [&](int k) -> float2 { return PD == 1 ? tb[k] : twl[(8 * u * k) & (N - 1)]; };
   auto locate = [&](int it, int& L, int& x0, float2*& wp) {
     const int tile_g = xcd_remap(it, total_tiles);
     L = find_lane(tab, tile_g);
@@ -942,53 +932,38 @@ __global__ void __launch_bounds__(512) k_col_6s(PassTable tab, int total_tiles) 
     const int fl = w % a.fb;
     wp = a.exit + ((size_t)p * a.n_frames + a.f0 + fl) * (size_t)N * a.nx;
   };
-  // prefetch ring: slot 0 is the next tile to process, slot PD - 1 the last issued
-  float2 pre[PD][8];
-  int Lq[PD], x0q[PD];
-  float2* wpq[PD];
+  float2 pre[8];
+  int L = 0, x0 = 0;
+  float2* wp = nullptr;
+  int it = blockIdx.x;
+  if (it < total_tiles) {
+    locate(it, L, x0, wp);
+    const int nx = tab.l[L].a.nx;
 #pragma unroll
-  for (int d = 0; d < PD; ++d) {
-    Lq[d] = 0;
-    x0q[d] = 0;
-    wpq[d] = nullptr;
-    const int itd = blockIdx.x + d * gridDim.x;
-    if (itd < total_tiles) {
-      locate(itd, Lq[d], x0q[d], wpq[d]);
-      const int nx = tab.l[Lq[d]].a.nx;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) pre[d][j] = wpq[d][(size_t)(r0 + 64 * j) * nx + x0q[d] + ca];
-    }
+    for (int j = 0; j < 8; ++j) pre[j] = wp[(size_t)(r0 + 64 * j) * nx + x0 + ca];
   }
-  for (int it = blockIdx.x; it < total_tiles; it += gridDim.x) {
-    const int L = Lq[0];
+  for (; it < total_tiles; it += gridDim.x) {
     const PassArgs& a = tab.l[L].a;
     const int mode = tab.l[L].mode;
     const int nx = a.nx;
-    const int cur_x0 = x0q[0];
-    float2* cur_wp = wpq[0];
+    const int cur_x0 = x0;
+    float2* cur_wp = wp;
     float2 x[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) x[j] = pre[0][j];
-    if (PD == 2) {
-#pragma unroll
-      for (int j = 0; j < 8; ++j) pre[0][j] = pre[PD - 1][j];
-      Lq[0] = Lq[PD - 1];
-      x0q[0] = x0q[PD - 1];
-      wpq[0] = wpq[PD - 1];
-    }
-    // the loads PD tiles ahead complete during the arithmetic of this one
-    const int nit = it + PD * gridDim.x;
+    for (int j = 0; j < 8; ++j) x[j] = pre[j];
+    // the next tile's loads complete during this tile's arithmetic
+    const int nit = it + gridDim.x;
     if (nit < total_tiles) {
-      locate(nit, Lq[PD - 1], x0q[PD - 1], wpq[PD - 1]);
-      const int nnx = tab.l[Lq[PD - 1]].a.nx;
+      locate(nit, L, x0, wp);
+      const int nnx = tab.l[L].a.nx;
 #pragma unroll
-      for (int j = 0; j < 8; ++j) pre[PD - 1][j] = wpq[PD - 1][(size_t)(r0 + 64 * j) * nnx + x0q[PD - 1] + ca];
+      for (int j = 0; j < 8; ++j) pre[j] = wp[(size_t)(r0 + 64 * j) * nnx + x0 + ca];
     }
     // layout A: 8-point transform over j, twiddle, to LDS
     dft8<false>(x);
-    __syncthreads();   // the previous tile's reads of the exchange buffer are done (and the table is staged)
 #pragma unroll
-    for (int k = 1; k < 8; ++k) x[k] = cmul(x[k], twa(k));
+    for (int k = 1; k < 8; ++k) x[k] = cmul(x[k], ta[k]);
+    __syncthreads();   // the previous tile's reads of the exchange buffer are done
 #pragma unroll
     for (int k = 0; k < 8; ++k) xs[512 * k + sa] = x[k];
     __syncthreads();
@@ -997,7 +972,7 @@ __global__ void __launch_bounds__(512) k_col_6s(PassTable tab, int total_tiles) 
     for (int q = 0; q < 8; ++q) x[q] = xs[sb + 64 * q];
     dft8<false>(x);
 #pragma unroll
-    for (int k = 1; k < 8; ++k) x[k] = cmul(x[k], twb(k));
+    for (int k = 1; k < 8; ++k) x[k] = cmul(x[k], tb[k]);
     wave_lds_sync();
 #pragma unroll
     for (int k = 0; k < 8; ++k) lw[8 * (u ^ lodd) + (k ^ u)] = x[k];
@@ -1022,7 +997,7 @@ __global__ void __launch_bounds__(512) k_col_6s(PassTable tab, int total_tiles) 
     wave_lds_sync();
     x[0] = lw[8 * (u ^ lodd) + u];
 #pragma unroll
-    for (int k = 1; k < 8; ++k) x[k] = cmulc(lw[8 * (u ^ lodd) + (k ^ u)], twb(k));
+    for (int k = 1; k < 8; ++k) x[k] = cmulc(lw[8 * (u ^ lodd) + (k ^ u)], tb[k]);
     dft8<true>(x);    // over k2: x[q] at r0 = u + 8 q
     wave_lds_sync();
 #pragma unroll
@@ -1031,7 +1006,7 @@ __global__ void __launch_bounds__(512) k_col_6s(PassTable tab, int total_tiles) 
     // layout A: conjugate twiddle, 8-point transform over k1, store
     x[0] = xs[sa];
 #pragma unroll
-    for (int k = 1; k < 8; ++k) x[k] = cmulc(xs[512 * k + sa], twa(k));
+    for (int k = 1; k < 8; ++k) x[k] = cmulc(xs[512 * k + sa], ta[k]);
     dft8<true>(x);
 #pragma unroll
     for (int j = 0; j < 8; ++j) cur_wp[(size_t)(r0 + 64 * j) * nx + cur_x0 + ca] = x[j];
@@ -1691,11 +1666,7 @@ static hipError_t col_6s_launch(PassTable& t, hipStream_t s) {
   const char* ge = getenv("TACAW_COL_GRID");
   const int cap = ge && atoi(ge) > 0 ? atoi(ge) : 1024;
   const int grid = std::min(tiles, cap);
-  const char* pe = getenv("TACAW_COL6_DEPTH");
-  if (pe && atoi(pe) == 2)
-    TACAW_LAUNCH((k_col_6s<2>), dim3(grid), dim3(512), 0, s, t, tiles);
-  else
-    TACAW_LAUNCH((k_col_6s<1>), dim3(grid), dim3(512), 0, s, t, tiles);
+  TACAW_LAUNCH(k_col_6s, dim3(grid), dim3(512), 0, s, t, tiles);
   return hipGetLastError();
 }
 
