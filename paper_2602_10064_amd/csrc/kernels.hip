@@ -899,13 +899,11 @@ __global__ void __launch_bounds__((C8<N, WIDE>::THREADS)) k_col_r8(PassTable tab
 // 64 c + 8 (u ^ (c % 2)) + (k2 ^ u) for the local ones; every 16-lane group of
 // an access hits 16 distinct 8-byte slots modulo 16.
 // ---------------------------------------------------------------------------
-// DB: two exchange buffers used by alternate tiles, which removes the barrier
-// that otherwise keeps a tile's first writes behind the previous tile's reads.
-template <int CT, bool DB>
+template <int CT>
 __global__ void __launch_bounds__(64 * CT) k_col_6s(PassTable tab, int total_tiles) {
   constexpr int N = 512, H = CT / 8;       // H column halves of 8
   static_assert(CT == 8 || CT == 16, "tiles of 8 or 16 columns");
-  __shared__ float2 xs_mem[(DB ? 2 : 1) * 4096 * H];
+  __shared__ float2 xs[4096 * H];
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   // layout A: column ca, r0 = (64 / CT) wave + lane / CT
   const int ca = lane % CT, r0 = (64 / CT) * wave + lane / CT;
@@ -917,7 +915,7 @@ __global__ void __launch_bounds__(64 * CT) k_col_6s(PassTable tab, int total_til
   const int ha = ca / 8;
   const int sa = 512 * ha + 8 * (r0 ^ ha) + ((ca & 7) ^ (r0 & 7));   // + 512 H k1
   const int sb = 512 * H * k1 + 512 * hb + 8 * (u ^ hb) + (cbl ^ u);  // + 64 q
-  const int lwo = 512 * H * k1 + 512 * hb + 64 * cbl;                 // local exchange region
+  float2* lw = xs + 512 * H * k1 + 512 * hb + 64 * cbl;               // local exchange region
   const int lodd = cbl & 1;
   // twiddles, the same for every tile (all lanes of a table have ny = 512)
   float2 ta[8], tb[8];   // entries 1..7 (entry 0 is 1 and never used)
@@ -951,14 +949,12 @@ __global__ void __launch_bounds__(64 * CT) k_col_6s(PassTable tab, int total_til
 #pragma unroll
     for (int j = 0; j < 8; ++j) pre[j] = wp[(size_t)(r0 + 64 * j) * nx + x0 + ca];
   }
-  for (int n_done = 0; it < total_tiles; it += gridDim.x, ++n_done) {
+  for (; it < total_tiles; it += gridDim.x) {
     const PassArgs& a = tab.l[L].a;
     const int mode = tab.l[L].mode;
     const int nx = a.nx;
     const int cur_x0 = x0;
     float2* cur_wp = wp;
-    float2* xs = xs_mem + (DB ? (n_done & 1) * 4096 * H : 0);
-    float2* lw = xs + lwo;
     float2 x[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) x[j] = pre[j];
@@ -974,7 +970,7 @@ __global__ void __launch_bounds__(64 * CT) k_col_6s(PassTable tab, int total_til
     dft8<false>(x);
 #pragma unroll
     for (int k = 1; k < 8; ++k) x[k] = cmul(x[k], ta[k]);
-    if (!DB) __syncthreads();   // the previous tile's reads of the exchange buffer are done
+    __syncthreads();   // the previous tile's reads of the exchange buffer are done
 #pragma unroll
     for (int k = 0; k < 8; ++k) xs[512 * H * k + sa] = x[k];
     __syncthreads();
@@ -1678,11 +1674,7 @@ static hipError_t col_6s_launch(PassTable& t, hipStream_t s) {
   const char* ge = getenv("TACAW_COL_GRID");
   const int cap = ge && atoi(ge) > 0 ? atoi(ge) : 8192 / CT;
   const int grid = std::min(tiles, cap);
-  const char* de = getenv("TACAW_COL6_DB");
-  if (de && atoi(de) == 1)
-    TACAW_LAUNCH((k_col_6s<CT, true>), dim3(grid), dim3(64 * CT), 0, s, t, tiles);
-  else
-    TACAW_LAUNCH((k_col_6s<CT, false>), dim3(grid), dim3(64 * CT), 0, s, t, tiles);
+  TACAW_LAUNCH((k_col_6s<CT>), dim3(grid), dim3(64 * CT), 0, s, t, tiles);
   return hipGetLastError();
 }
 
