@@ -899,24 +899,17 @@ __global__ void __launch_bounds__((C8<N, WIDE>::THREADS)) k_col_r8(PassTable tab
 // 64 c + 8 (u ^ (c % 2)) + (k2 ^ u) for the local ones; every 16-lane group of
 // an access hits 16 distinct 8-byte slots modulo 16.
 // ---------------------------------------------------------------------------
-template <int CT>
-__global__ void __launch_bounds__(64 * CT) k_col_6s(PassTable tab, int total_tiles) {
-  constexpr int N = 512, H = CT / 8;       // H column halves of 8
-  static_assert(CT == 8 || CT == 16, "tiles of 8 or 16 columns");
-  __shared__ float2 xs[4096 * H];
+__global__ void __launch_bounds__(512) k_col_6s(PassTable tab, int total_tiles) {
+  constexpr int N = 512, CT = 8;
+  __shared__ float2 xs[4096];
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  // layout A: column ca, r0 = (64 / CT) wave + lane / CT
-  const int ca = lane % CT, r0 = (64 / CT) * wave + lane / CT;
-  // layout B: k1 = wave / H, column cb = 8 h + lane / 8, u = lane % 8
-  const int k1 = wave / H, hb = wave % H, cbl = lane >> 3, cb = 8 * hb + cbl, u = lane & 7;
-  // slots: element (c, k1, r0) at 512 H k1 + 512 h + 8 (r0 ^ h) + (c % 8 ^ r0 % 8),
-  // h = c / 8; wavefront (k1, h) of layout B owns the 512 slots from
-  // 512 H k1 + 512 h
-  const int ha = ca / 8;
-  const int sa = 512 * ha + 8 * (r0 ^ ha) + ((ca & 7) ^ (r0 & 7));   // + 512 H k1
-  const int sb = 512 * H * k1 + 512 * hb + 8 * (u ^ hb) + (cbl ^ u);  // + 64 q
-  float2* lw = xs + 512 * H * k1 + 512 * hb + 64 * cbl;               // local exchange region
-  const int lodd = cbl & 1;
+  const int ca = lane & 7, r0 = 8 * wave + (lane >> 3);   // layout A
+  const int k1 = wave, cb = lane >> 3, u = lane & 7;      // layout B
+  // slots
+  const int sa = 8 * r0 + (ca ^ (r0 & 7));                 // + 512 k1
+  const int sb = 512 * k1 + 8 * u + (cb ^ u);              // + 64 q
+  float2* lw = xs + 512 * k1 + 64 * cb;                    // local exchange region
+  const int lodd = cb & 1;
   // twiddles, the same for every tile (all lanes of a table have ny = 512)
   float2 ta[8], tb[8];   // entries 1..7 (entry 0 is 1 and never used)
   {
@@ -972,7 +965,7 @@ __global__ void __launch_bounds__(64 * CT) k_col_6s(PassTable tab, int total_til
     for (int k = 1; k < 8; ++k) x[k] = cmul(x[k], ta[k]);
     __syncthreads();   // the previous tile's reads of the exchange buffer are done
 #pragma unroll
-    for (int k = 0; k < 8; ++k) xs[512 * H * k + sa] = x[k];
+    for (int k = 0; k < 8; ++k) xs[512 * k + sa] = x[k];
     __syncthreads();
     // layout B: 8-point transform over q, twiddle, local exchange, over u
 #pragma unroll
@@ -1013,7 +1006,7 @@ __global__ void __launch_bounds__(64 * CT) k_col_6s(PassTable tab, int total_til
     // layout A: conjugate twiddle, 8-point transform over k1, store
     x[0] = xs[sa];
 #pragma unroll
-    for (int k = 1; k < 8; ++k) x[k] = cmulc(xs[512 * H * k + sa], ta[k]);
+    for (int k = 1; k < 8; ++k) x[k] = cmulc(xs[512 * k + sa], ta[k]);
     dft8<true>(x);
 #pragma unroll
     for (int j = 0; j < 8; ++j) cur_wp[(size_t)(r0 + 64 * j) * nx + cur_x0 + ca] = x[j];
@@ -1660,21 +1653,20 @@ static hipError_t col_r8_launch(PassTable& t, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int CT>
 static hipError_t col_6s_launch(PassTable& t, hipStream_t s) {
   int tiles = 0;
   for (int i = 0; i < t.n; ++i) {
     const PassArgs& a = t.l[i].a;
-    if (a.ny != 512 || a.nx % CT != 0) return hipErrorInvalidValue;
+    if (a.ny != 512 || a.nx % 8 != 0) return hipErrorInvalidValue;
     t.l[i].block_start = tiles;
-    tiles += a.n_probes * a.fb * (a.nx / CT);
+    tiles += a.n_probes * a.fb * (a.nx / 8);
   }
-  // grid stride over the tiles; TACAW_COL_GRID caps the grid (default 1024
-  // workgroups of 8 columns, 512 of 16)
+  // grid stride over the tiles; TACAW_COL_GRID caps the grid (default 1024,
+  // two generations of the two resident workgroups per CU)
   const char* ge = getenv("TACAW_COL_GRID");
-  const int cap = ge && atoi(ge) > 0 ? atoi(ge) : 8192 / CT;
+  const int cap = ge && atoi(ge) > 0 ? atoi(ge) : 1024;
   const int grid = std::min(tiles, cap);
-  TACAW_LAUNCH((k_col_6s<CT>), dim3(grid), dim3(64 * CT), 0, s, t, tiles);
+  TACAW_LAUNCH(k_col_6s, dim3(grid), dim3(512), 0, s, t, tiles);
   return hipGetLastError();
 }
 
@@ -1683,13 +1675,11 @@ hipError_t launch_col_lanes(const PassLane* lanes, int n, int variant, hipStream
   PassTable t{};
   t.n = n;
   for (int i = 0; i < n; ++i) t.l[i] = lanes[i];
-  if (variant == 5 || variant == 6) {
-    // six-step kernel: ny = 512, regular and last-slice modes; tiles of 16
-    // columns (variant 6: whole 128-byte lines per row) or 8
+  if (variant == 5) {
+    // six-step kernel: ny = 512, regular and last-slice modes
     bool ok = lanes[0].a.ny == 512 && lanes[0].a.nx % 8 == 0;
     for (int i = 0; i < n; ++i) ok = ok && lanes[i].mode != COL_INVERSE_ONLY;
-    if (ok && variant == 6 && lanes[0].a.nx % 16 == 0) return col_6s_launch<16>(t, s);
-    if (ok) return col_6s_launch<8>(t, s);
+    if (ok) return col_6s_launch(t, s);
     variant = 2;
   }
   if (variant == 4) {
