@@ -28,6 +28,8 @@ Readings taken where the paper is silent, garbled or inconsistent:
             (no cutoff).
   R-bin     An atom belongs to slice floor((zbar mod Lz)/dz) (clamped), zbar being
             its FP64 mean z over all frames; slices are half-open [k dz, (k+1) dz).
+            Optionally (slice_by_instant_z) each frame bins by its own z, the
+            literal reading of "atoms within the slice z-bounds".
   R-order   The printed product P_{N-1} t_N ... P_0 t_1 has garbled indices; we
             transmit then propagate in every slice, so N propagators, one after the
             last slice, and the exit wave is taken in reciprocal space after it.
@@ -112,10 +114,12 @@ def freq_axis_THz(n_frames: int, dt_fs: float, two_sided: bool = False) -> np.nd
 # ---------------------------------------------------------------------------
 # Slice binning (Methods 2.2: "atoms within the slice z-bounds"; reading R-bin)
 # ---------------------------------------------------------------------------
-def slice_index(positions: np.ndarray, lz: float, n_slices: int) -> np.ndarray:
-    zbar = positions[:, :, 2].mean(axis=0)
+def slice_index(positions: np.ndarray, lz: float, n_slices: int, instant: bool = False) -> np.ndarray:
+    """Slice of every atom: [A] from the FP64 frame-mean z (reading R-bin), or
+    [F, A] from each frame's own z when instant (the literal per-frame reading)."""
+    z = positions[:, :, 2] if instant else positions[:, :, 2].mean(axis=0)
     dz = lz / n_slices
-    s = np.floor(np.mod(zbar, lz) / dz).astype(np.int64)
+    s = np.floor(np.mod(z, lz) / dz).astype(np.int64)
     return np.clip(s, 0, n_slices - 1)
 
 
@@ -278,7 +282,8 @@ def exit_waves(job, frames=None, probes=None) -> np.ndarray:
     sig = sigma_rad_per_VA(job.voltage_V)
     dz = lz / job.n_slices
     prop = propagator(job.nx, job.ny, dx, dy, lam, dz)
-    slice_of = slice_index(job.positions, lz, job.n_slices)
+    instant = bool(getattr(job, "slice_by_instant_z", False))
+    slice_of = slice_index(job.positions, lz, job.n_slices, instant)
     frames = range(job.n_frames) if frames is None else list(frames)
     plane = job.aperture_mrad == 0
     n_p = 1 if plane else job.probe_xy.shape[0]
@@ -287,7 +292,8 @@ def exit_waves(job, frames=None, probes=None) -> np.ndarray:
     aberr = getattr(job, "aberrations", None)
     out = np.zeros((len(probes), len(frames), job.ny, job.nx), dtype=np.complex128)
     for fi, f in enumerate(frames):
-        pots = frame_potentials(job.positions[f], job.atom_species, slice_of, job.gauss_a,
+        slices_f = slice_of[f] if instant else slice_of
+        pots = frame_potentials(job.positions[f], job.atom_species, slices_f, job.gauss_a,
                                 job.gauss_b, lx, ly, pot_nx, pot_ny, job.n_slices)
         for pi, p in enumerate(probes):
             if plane:

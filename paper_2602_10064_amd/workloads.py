@@ -55,6 +55,8 @@ class Job:
     # probe aberrations: None, or (2, 14) = (C_nm [A], phi_nm [rad]) for
     # (n, m) = 10, 12, 21, 23, 30, 32, 34, 41, 43, 45, 50, 52, 54, 56
     aberrations: Optional[np.ndarray] = None
+    # bin atoms into slices by each frame's own z instead of the frame-mean z
+    slice_by_instant_z: bool = False
     name: str = ""
 
     @property
