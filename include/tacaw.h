@@ -55,6 +55,10 @@ typedef enum {
                                      or admitted by the serving loop                 */
 #define TACAW_USE_GRAPH 8u        /* tacaw_run captures the job's whole launch
                                      sequence into a HIP graph once and replays it   */
+#define TACAW_SLICE_BY_INSTANT_Z 16u /* bin atoms into slices by each frame's own z
+                                     (Methods 2.2: atoms within the slice z-bounds,
+                                     taken frame by frame) instead of the FP64
+                                     frame-mean z; n_slices < 32768               */
 
 typedef struct tacaw_ctx tacaw_ctx;
 typedef struct tacaw_job tacaw_job;

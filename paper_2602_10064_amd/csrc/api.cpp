@@ -50,7 +50,7 @@ void free_job_buffers(tacaw_job* j) {
   void* bufs[] = {j->d_exit,    j->d_spec,   j->d_V,      j->d_pos,     j->d_species,   j->d_tile_start,
                   j->d_tile_atoms, j->d_coef, j->d_tw_x,  j->d_tw_y,    j->d_tw_t,      j->d_px,
                   j->d_py,      j->d_px_last, j->d_py_last, j->d_probe0, j->d_origin,   j->d_rloc,
-                  j->d_count};
+                  j->d_count,   j->d_fslice};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   j->d_exit = nullptr;
@@ -67,6 +67,7 @@ void free_job_buffers(tacaw_job* j) {
   j->d_origin = nullptr;
   j->d_rloc = nullptr;
   j->d_count = nullptr;
+  j->d_fslice = nullptr;
 }
 
 hipEvent_t take_event(tacaw_ctx* c) {
@@ -182,6 +183,7 @@ static SplatArgs splat_args_of(tacaw_job* job, int f0, int fb) {
   const HostPlan& hp = job->hp;
   SplatArgs sa{};
   sa.pos = job->d_pos;
+  sa.fslice = job->d_fslice;
   sa.species = job->d_species;
   sa.tile_start = job->d_tile_start;
   sa.tile_atoms = job->d_tile_atoms;
@@ -357,6 +359,7 @@ tacaw_status materialize(tacaw_job* j, hipStream_t s0) {
   ALLOC(j->d_V, (size_t)hp.fb * (hp.overlap ? 2 : hp.splat_group) * hp.pnx * hp.pny);
   ALLOC(j->d_pos, (size_t)hp.F * hp.A);
   ALLOC(j->d_species, (size_t)hp.A);
+  if (hp.instant_z) ALLOC(j->d_fslice, hp.fslice.size());
   ALLOC(j->d_tile_start, hp.tile_start.size());
   ALLOC(j->d_tile_atoms, hp.tile_atoms.size());
   ALLOC(j->d_coef, hp.coef.size());
@@ -386,6 +389,10 @@ tacaw_status materialize(tacaw_job* j, hipStream_t s0) {
     if ((e = hipMemcpyAsync(j->d_species, hp.sorted_species.data(), hp.A * sizeof(int32_t), hipMemcpyHostToDevice, s0)) !=
         hipSuccess)
       return fail("upload species", e);
+    if (hp.instant_z &&
+        (e = hipMemcpyAsync(j->d_fslice, hp.fslice.data(), hp.fslice.size() * sizeof(int16_t), hipMemcpyHostToDevice,
+                            s0)) != hipSuccess)
+      return fail("upload frame slices", e);
   }
   if ((e = hipMemcpyAsync(j->d_tile_start, hp.tile_start.data(), hp.tile_start.size() * sizeof(int32_t),
                      hipMemcpyHostToDevice, s0)) != hipSuccess)

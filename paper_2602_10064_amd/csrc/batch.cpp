@@ -51,6 +51,7 @@ SplatArgs splat_args(tacaw_job* j, int f0, int fb, int slice) {
   const HostPlan& hp = j->hp;
   SplatArgs sa{};
   sa.pos = j->d_pos;
+  sa.fslice = j->d_fslice;
   sa.species = j->d_species;
   sa.tile_start = j->d_tile_start;
   sa.tile_atoms = j->d_tile_atoms;

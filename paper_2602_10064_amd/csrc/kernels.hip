@@ -286,19 +286,24 @@ __global__ void __launch_bounds__(256) k_splat(SplatTable tab) {
       const int mp4 = (mp + 3) & ~3;
       AtomPos p{};
       const float* c = coef;
+      int at = -1;   // this lane's atom (sorted index)
       if (r < PRE) {
 #pragma unroll
         for (int q = 0; q < PRE; ++q)
           if (q == r) {
             p = pn[q];
             c = coef + coef_r[q];
+            at = atom_r[q];
             if (atom_r[q] >= 0 && k + 1 < nf) pn[q] = a.pos[frame_off + a.n_atoms + atom_r[q]];
           }
       } else if (pr < mp) {
         const int entry = a.tile_atoms[c0 + pr];
-        p = a.pos[frame_off + (entry >> 3)];
-        c = coef + (a.species[entry >> 3] * N_GAUSS + (entry & 7)) * COEF_STRIDE;
+        at = entry >> 3;
+        p = a.pos[frame_off + at];
+        c = coef + (a.species[at] * N_GAUSS + (entry & 7)) * COEF_STRIDE;
       }
+      // per-frame binning: an atom outside this slice in this frame adds nothing
+      const bool gone = a.fslice != nullptr && at >= 0 && a.fslice[frame_off + at] != s;
       wave_lds_sync();  // the previous round's MFMA reads are done
       if (pr < mp) {
         // lanes 0-31 and 32-63 run the same instructions on their own axis
@@ -324,7 +329,7 @@ __global__ void __launch_bounds__(256) k_splat(SplatTable tab) {
           // per node.
           const float up = fp - (float)(o + nbase) - (float)(NPL / 2);
           const float la = along_y ? c[5] : 0.f;
-          const float qa = -e2, qb = 2.f * e2 * up, qc = fmaf(-e2 * up, up, la);
+          const float qa = -e2, qb = 2.f * e2 * up, qc = gone ? -INFINITY : fmaf(-e2 * up, up, la);
 #pragma unroll
           for (int x = 0; x < NPL; ++x) {
             const float xc = (float)(x - NPL / 2);
@@ -332,8 +337,9 @@ __global__ void __launch_bounds__(256) k_splat(SplatTable tab) {
           }
         } else {
           const int img = along_y ? a.img_y : a.img_x;
+          const float amp_f = gone ? 0.f : amp;
           for (int x = 0; x < NPL; ++x)
-            dst[x * PS] = amp * profile(node0 + nbase + x, ip, fp, n_ax, e2, rc, img);
+            dst[x * PS] = amp_f * profile(node0 + nbase + x, ip, fp, n_ax, e2, rc, img);
         }
       } else if (pr < mp4) {
 #pragma unroll

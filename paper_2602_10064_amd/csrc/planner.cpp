@@ -68,6 +68,10 @@ tacaw_status validate_desc(const tacaw_job_desc* d) {
     set_error("grid %dx%d: each side must be a positive product of 2, 3 and 5", d->nx, d->ny);
     return TACAW_EINVAL;
   }
+  if ((d->flags & TACAW_SLICE_BY_INSTANT_Z) && d->n_slices >= 32768) {
+    set_error("per-frame slice binning holds slice indices in 16 bits (n_slices %d)", d->n_slices);
+    return TACAW_EINVAL;
+  }
   if (d->n_slices < 1) {
     set_error("n_slices must be >= 1 (got %d)", d->n_slices);
     return TACAW_EINVAL;
@@ -221,6 +225,7 @@ Footprint footprint_of(const tacaw_job_desc* d, int fb, size_t n_tile_atoms) {
   f.spec = P * M * nk * sizeof(float);
   f.V = (size_t)fb * (overlap_splat() ? 2 : splat_group(d->n_slices, fb, pnx, pny)) * pnx * pny * sizeof(float);
   f.pos = (size_t)d->n_frames * d->n_atoms * sizeof(AtomPos) + (size_t)d->n_atoms * sizeof(int32_t);
+  if (d->flags & TACAW_SLICE_BY_INSTANT_Z) f.pos += (size_t)d->n_frames * d->n_atoms * sizeof(int16_t);
   f.tiles = n_tile_atoms * sizeof(int32_t);
   f.probes = plane ? 0 : P * nk * sizeof(float2) + P * (2 * sizeof(int32_t) + 2 * sizeof(double));
   f.tables = (size_t)(2 * d->nx + 2 * d->ny + d->nx + d->ny + d->n_frames) * sizeof(float2) +
@@ -294,6 +299,35 @@ tacaw_status plan_job(const tacaw_job_desc* d, const int32_t* atom_species, cons
   hp.sorted_species.resize(hp.A);
   for (int j = 0; j < hp.A; ++j) hp.sorted_species[j] = atom_species[hp.order[j]];
 
+  // Per-frame binning (TACAW_SLICE_BY_INSTANT_Z): each frame's own z, the same
+  // half-open clamped slices; an atom is a candidate in every slice it visits,
+  // and the potential kernel skips it in frames where it is elsewhere.
+  hp.instant_z = (d->flags & TACAW_SLICE_BY_INSTANT_Z) != 0;
+  std::vector<std::vector<int32_t>> slice_atoms(hp.ns);   // sorted atom indices per slice
+  if (hp.instant_z) {
+    hp.fslice.assign((size_t)hp.F * hp.A, 0);
+    for (int f = 0; f < hp.F; ++f)
+      for (int j = 0; j < hp.A; ++j) {
+        double zm = fmod(pos[((size_t)f * hp.A + hp.order[j]) * 3 + 2], hp.lz);
+        if (zm != 0.0 && zm < 0.0) zm += hp.lz;
+        long s = (long)floor(zm / hp.dz);
+        if (s < 0) s = 0;
+        if (s > hp.ns - 1) s = hp.ns - 1;
+        hp.fslice[(size_t)f * hp.A + j] = (int16_t)s;
+      }
+    std::vector<int16_t> visited;
+    for (int j = 0; j < hp.A; ++j) {   // atoms in sorted order, so every list stays sorted
+      visited.clear();
+      for (int f = 0; f < hp.F; ++f) visited.push_back(hp.fslice[(size_t)f * hp.A + j]);
+      std::sort(visited.begin(), visited.end());
+      visited.erase(std::unique(visited.begin(), visited.end()), visited.end());
+      for (int16_t s : visited) slice_atoms[s].push_back(j);
+    }
+  } else {
+    for (int s = 0; s < hp.ns; ++s)
+      for (int j = slice_start[s]; j < slice_start[s + 1]; ++j) slice_atoms[s].push_back(j);
+  }
+
   // Truncation radius: exp(-pi^2 r^2 / b) <= 1e-8 for the widest term.
   double bmax = 0.0;
   for (int i = 0; i < hp.S * TACAW_N_GAUSS; ++i) bmax = std::max(bmax, d->gauss_b[i]);
@@ -366,7 +400,7 @@ tacaw_status plan_job(const tacaw_job_desc* d, const int32_t* atom_species, cons
   std::vector<int> txs, tys;
   for (int s = 0; s < hp.ns; ++s) {
     for (auto& b : bucket) b.clear();
-    for (int j = slice_start[s]; j < slice_start[s + 1]; ++j) {
+    for (const int j : slice_atoms[s]) {
       const int oj = hp.order[j];
       const int sp = hp.sorted_species[j];
       for (int i = 0; i < N_GAUSS; ++i) {

@@ -35,7 +35,9 @@ struct HostPlan {
   bool splat_per_slice = true;         // potentials built slice by slice
   bool overlap = true;                 // per-slice potentials built one slice ahead on a side stream
   int splat_group = 1;                 // slices per potential launch (all slices when !splat_per_slice)
-  std::vector<int32_t> slice_of;       // per input atom
+  std::vector<int32_t> slice_of;       // per input atom (frame-mean z)
+  bool instant_z = false;              // TACAW_SLICE_BY_INSTANT_Z
+  std::vector<int16_t> fslice;         // [F][A] sorted order: each frame's own slice (instant_z)
   std::vector<int32_t> order;          // sorted position -> input atom
   std::vector<int32_t> tile_start;     // [ns * tiles + 1]
   std::vector<int32_t> tile_atoms;     // sorted-atom indices
@@ -140,6 +142,7 @@ struct tacaw_job {
   float2* d_probe0 = nullptr;
   tacaw::Aberrations aberr{};    // probe aberrations (off unless set)
   int32_t* d_origin = nullptr;
+  int16_t* d_fslice = nullptr;   // [F][A] per-frame slices (instant-z binning only)
   double* d_rloc = nullptr;
   int* d_count = nullptr;
   std::vector<tacaw::AtomPos> enc;   // encoded positions, kept until the device copy exists

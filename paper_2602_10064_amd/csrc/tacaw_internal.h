@@ -36,6 +36,8 @@ struct SplatArgs {
   int n_atoms, n_species, f0, fb, n_slices, slice0, pnx, pny, tiles_x, tiles_y;
   float rcx, rcy;              // truncation radius in pixels along x and y
   int img_x, img_y;            // periodic images -img..img searched per axis
+  const int16_t* fslice;       // [F][A] each frame's own slice (sorted order), or nullptr:
+                               // a pair adds nothing in frames where its atom is elsewhere
 };
 
 // One row or column pass over a batch of (probe, frame) waves.

@@ -22,6 +22,7 @@ TWO_SIDED = 1
 KEEP_EXIT_WAVES = 2
 DEFER_ALLOC = 4
 USE_GRAPH = 8
+SLICE_BY_INSTANT_Z = 16
 
 K_SPLAT, K_ROW, K_COL, K_TIME, K_OTHER = range(5)
 KERNEL_CLASSES = {"splat": K_SPLAT, "row": K_ROW, "col": K_COL, "time": K_TIME, "other": K_OTHER}
@@ -162,6 +163,8 @@ class _DescHolder:
         d.gauss_b = _ptr(self.gauss_b, ctypes.c_double)
         keep = job.keep_exit_waves if keep_exit_waves is None else keep_exit_waves
         d.flags = (TWO_SIDED if job.two_sided else 0) | (KEEP_EXIT_WAVES if keep else 0)
+        if getattr(job, "slice_by_instant_z", False):
+            d.flags |= SLICE_BY_INSTANT_Z
         self.desc = d
 
 

@@ -285,3 +285,27 @@ def test_splat_slice_groups_bitwise(tacaw, ctx, monkeypatch):
     monkeypatch.setenv("TACAW_FB", "6")
     _, b, _ = run_gpu(tacaw, ctx, job)
     assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
+@pytest.mark.parametrize("probes", [0, 2], ids=["plane", "probes"])
+def test_per_frame_slice_binning(tacaw, ctx, oracle, probes):
+    # atoms oscillating across slice boundaries, binned frame by frame
+    # (TACAW_SLICE_BY_INSTANT_Z), against the oracle's per-frame binning
+    import dataclasses
+    job = w.random_small_job(48, nx=48, ny=40, n_slices=4, n_frames=12, n_atoms=10, cell=(7.0, 6.0, 4.0),
+                             aperture_mrad=25.0 if probes else 0.0, n_probes=max(probes, 1))
+    rng = np.random.default_rng(48)
+    pos = job.positions.copy()
+    t = np.arange(job.n_frames)[:, None]
+    pos[:, :, 2] = rng.integers(1, 4, size=job.n_atoms)[None, :] + 0.3 * np.sin(
+        2 * np.pi * t / job.n_frames + rng.uniform(0, 6, job.n_atoms)[None, :])
+    job = dataclasses.replace(job, positions=pos, slice_by_instant_z=True)
+    with tacaw.TacawJob(ctx, job) as j:
+        j.run()
+        ex, spec = j.exit_waves(), j.spectrum()
+    ref_ex = oracle.exit_waves(job)
+    assert rel_l2(ex, ref_ex) <= EXIT_TOL
+    assert rel_l2(spec, oracle.tacaw_spectrum(ref_ex)) <= SPEC_TOL
+    # the frame-mean binning gives a different result on this trajectory
+    mean = oracle.exit_waves(dataclasses.replace(job, slice_by_instant_z=False), frames=[0, 5])
+    assert rel_l2(ex[:, [0, 5]], mean) > 1e-3
