@@ -292,7 +292,7 @@ def test_per_frame_slice_binning(tacaw, ctx, oracle, probes):
     # atoms oscillating across slice boundaries, binned frame by frame
     # (TACAW_SLICE_BY_INSTANT_Z), against the oracle's per-frame binning
     import dataclasses
-    job = w.random_small_job(48, nx=48, ny=40, n_slices=4, n_frames=12, n_atoms=10, cell=(7.0, 6.0, 4.0),
+    job = w.random_small_job(48, nx=48, ny=32, n_slices=4, n_frames=12, n_atoms=10, cell=(7.0, 5.0, 4.0),
                              aperture_mrad=25.0 if probes else 0.0, n_probes=max(probes, 1))
     rng = np.random.default_rng(48)
     pos = job.positions.copy()
