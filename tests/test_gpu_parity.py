@@ -308,4 +308,4 @@ def test_per_frame_slice_binning(tacaw, ctx, oracle, probes):
     assert rel_l2(spec, oracle.tacaw_spectrum(ref_ex)) <= SPEC_TOL
     # the frame-mean binning gives a different result on this trajectory
     mean = oracle.exit_waves(dataclasses.replace(job, slice_by_instant_z=False), frames=[0, 5])
-    assert rel_l2(ex[:, [0, 5]], mean) > 1e-3
+    assert rel_l2(ex[:, [0, 5]], mean) > 2 * EXIT_TOL
