@@ -264,7 +264,10 @@ def main():
     print(f"[bench] inputs generated in {t_gen:.1f} s", file=sys.stderr, flush=True)
 
     ctx = tacaw.Context(0)
-    j = tacaw.TacawJob(ctx, job, keep_exit_waves=True)
+    torch.cuda.synchronize()
+    t_create = time.perf_counter()
+    j = tacaw.TacawJob(ctx, job, keep_exit_waves=True)   # plans, allocates, uploads (synchronous)
+    t_create = time.perf_counter() - t_create
     stream = torch.cuda.current_stream()
     for _ in range(args.warmup):
         j.run(stream=stream)
@@ -293,6 +296,34 @@ def main():
     torch.cuda.synchronize()
     breakdown = {k: round(ctx.timing_get(k)[0], 3) for k in ("splat", "row", "col", "time")}
     ctx.timing_enable(False)
+
+    # host transfers, outside the timed region (c2 only: the c3 spectrum is
+    # 32 GiB): the spectrum to host memory, and a fresh job from host inputs
+    # to the spectrum in host memory
+    host = None
+    if args.workload == "c2":
+        t = time.perf_counter()
+        spec_host = j.spectrum()
+        d2h = time.perf_counter() - t
+        d2h_bytes = spec_host.nbytes
+        del spec_host
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        j2 = tacaw.TacawJob(ctx, job, keep_exit_waves=False)
+        j2.run(stream=stream)
+        spec2 = j2.spectrum()
+        h2h = time.perf_counter() - t
+        j2.destroy()
+        del spec2
+        host = {"job_create_ms": round(t_create * 1e3, 1),
+                "h2d_bytes": int(job.n_frames * job.n_atoms * 16),
+                "d2h_spectrum_ms": round(d2h * 1e3, 1), "d2h_bytes": int(d2h_bytes),
+                "d2h_GBps": round(d2h_bytes / d2h / 1e9, 2),
+                "host_to_host_ms": round(h2h * 1e3, 1),
+                "note": "job_create: planning on the host, device allocation, upload of the encoded positions "
+                        "(16 B per frame and atom) and tables; host_to_host: a fresh job from host arrays to "
+                        "the spectrum in host memory"}
+        print(f"[bench] host transfers: {host}", file=sys.stderr, flush=True)
 
     if args.copy_calibration:
         a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")      # 1 GiB
@@ -375,6 +406,7 @@ def main():
         "hbm_frac": round(model_bytes / (elapsed / args.steps) / 1e9 / HBM_PEAK_GBPS, 4),
         "kernel_ms_per_step": breakdown,
         "timed_region_kernel_ms_per_step": kernel_ms,
+        "host_transfers": host,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
