@@ -236,6 +236,8 @@ def main():
     ap.add_argument("--timing-every", type=int, default=7,
                     help="time one launch in this many of each timed class (7: coprime with the "
                          "slice count, so the sampled launches rotate over the slices)")
+    ap.add_argument("--no-host", action="store_true",
+                    help="skip the host-transfer figures (profiling runs: they add copy kernels and a run)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for counter calibration)")
     args = ap.parse_args()
@@ -301,7 +303,7 @@ def main():
     # 32 GiB): the spectrum to host memory, and a fresh job from host inputs
     # to the spectrum in host memory
     host = None
-    if args.workload == "c2":
+    if args.workload == "c2" and not args.no_host:
         t = time.perf_counter()
         spec_host = j.spectrum()
         d2h = time.perf_counter() - t
