@@ -201,7 +201,9 @@ __device__ __forceinline__ float profile(int node, int ipos, float fpos, int n, 
 // of the tile's four 16 x 16 quarters (FP32 products and sums).  Positions of
 // the first rounds are prefetched one frame ahead.  Pair order and instruction
 // sequence are fixed, so the result is deterministic.
-template <int MP>
+// IZ: per-frame slice binning (lanes carry a frame-slice table); a separate
+// instantiation keeps the check out of the default kernel.
+template <int MP, bool IZ>
 __global__ void __launch_bounds__(256) k_splat(SplatTable tab) {
   // MP pairs per round (32 or 16).  Lanes split into 64 / MP parts of MP
   // lanes; each part fills NPL = MP nodes of the column (x) or row (y)
@@ -303,7 +305,7 @@ __global__ void __launch_bounds__(256) k_splat(SplatTable tab) {
         c = coef + (a.species[at] * N_GAUSS + (entry & 7)) * COEF_STRIDE;
       }
       // per-frame binning: an atom outside this slice in this frame adds nothing
-      const bool gone = a.fslice != nullptr && at >= 0 && a.fslice[frame_off + at] != s;
+      const bool gone = IZ && a.fslice != nullptr && at >= 0 && a.fslice[frame_off + at] != s;
       wave_lds_sync();  // the previous round's MFMA reads are done
       if (pr < mp) {
         // lanes 0-31 and 32-63 run the same instructions on their own axis
@@ -329,7 +331,8 @@ __global__ void __launch_bounds__(256) k_splat(SplatTable tab) {
           // per node.
           const float up = fp - (float)(o + nbase) - (float)(NPL / 2);
           const float la = along_y ? c[5] : 0.f;
-          const float qa = -e2, qb = 2.f * e2 * up, qc = gone ? -INFINITY : fmaf(-e2 * up, up, la);
+          const float qa = -e2, qb = 2.f * e2 * up;
+          const float qc = IZ && gone ? -INFINITY : fmaf(-e2 * up, up, la);
 #pragma unroll
           for (int x = 0; x < NPL; ++x) {
             const float xc = (float)(x - NPL / 2);
@@ -337,7 +340,7 @@ __global__ void __launch_bounds__(256) k_splat(SplatTable tab) {
           }
         } else {
           const int img = along_y ? a.img_y : a.img_x;
-          const float amp_f = gone ? 0.f : amp;
+          const float amp_f = IZ && gone ? 0.f : amp;
           for (int x = 0; x < NPL; ++x)
             dst[x * PS] = amp_f * profile(node0 + nbase + x, ip, fp, n_ax, e2, rc, img);
         }
@@ -1754,10 +1757,16 @@ hipError_t launch_splat_lanes(const SplatLane* lanes, int n, hipStream_t s) {
   // pairs per round: TACAW_SPLAT_ROUND (16 or 32; default 32)
   const char* re = getenv("TACAW_SPLAT_ROUND");
   const int round = re && atoi(re) == 16 ? 16 : 32;
-  if (round == 16)
-    TACAW_LAUNCH((k_splat<16>), dim3(blocks), dim3(256), 0, s, t);
+  bool iz = false;   // any lane binned frame by frame
+  for (int i = 0; i < n; ++i) iz = iz || lanes[i].a.fslice != nullptr;
+  if (round == 16 && iz)
+    TACAW_LAUNCH((k_splat<16, true>), dim3(blocks), dim3(256), 0, s, t);
+  else if (round == 16)
+    TACAW_LAUNCH((k_splat<16, false>), dim3(blocks), dim3(256), 0, s, t);
+  else if (iz)
+    TACAW_LAUNCH((k_splat<32, true>), dim3(blocks), dim3(256), 0, s, t);
   else
-    TACAW_LAUNCH((k_splat<32>), dim3(blocks), dim3(256), 0, s, t);
+    TACAW_LAUNCH((k_splat<32, false>), dim3(blocks), dim3(256), 0, s, t);
   return hipGetLastError();
 }
 
