@@ -147,3 +147,32 @@ def test_stem_errors(tacaw, ctx):
         j.run()
         with pytest.raises(tacaw.TacawError):
             j.mean_diffraction()                      # exit waves not kept
+
+
+def test_graph_replay_picks_up_new_aberrations(tacaw, ctx):
+    # a captured job rebuilds its probes in place when aberrations change, so
+    # later replays use them; each replay equals the eager run of the same
+    # state, with eager work between replays
+    import torch
+    job = w.random_small_job(87, nx=32, ny=32, n_slices=2, n_frames=6, n_atoms=5, aperture_mrad=25.0,
+                             n_probes=2, cell=(6.0, 6.0, 3.0))
+    ab = aberrations(87)
+    with tacaw.TacawJob(ctx, job) as e:
+        e.run()
+        ref0 = e.spectrum()
+        e.set_aberrations(ab[0], ab[1])
+        e.run()
+        ref1 = e.spectrum()
+    assert not np.array_equal(ref0, ref1)
+    with tacaw.TacawJob(ctx, job, use_graph=True) as g:
+        for rep in range(2):
+            g.run()
+            torch.cuda.synchronize()
+            assert np.array_equal(g.spectrum().view(np.uint32), ref0.view(np.uint32)), rep
+            torch.randn(1 << 18, device="cuda").sum().item()
+        g.set_aberrations(ab[0], ab[1])
+        for rep in range(2):
+            g.run()
+            torch.cuda.synchronize()
+            assert np.array_equal(g.spectrum().view(np.uint32), ref1.view(np.uint32)), rep
+            torch.randn(1 << 18, device="cuda").sum().item()
