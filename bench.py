@@ -39,10 +39,17 @@ WORKLOAD_C3 = ("hexagonal B/N layer stack (a=2.5 A, 40x20 orthohexagonal cells, 
 BYTES_PER_UNIT = {"row": 20.0, "col": 16.0, "splat": 4.0, "time": 10.0}
 
 
+# Sources that decide what each launch reads and writes: the device code and
+# the planner that sizes frame batches and builds the potential kernel's lists.
+# Host orchestration (api, batch, serve, analysis) does not change a launch's
+# traffic.
+KERNEL_SOURCES = ("fft_engine.h", "kernels.hip", "planner.cpp", "runtime.h", "tacaw_internal.h")
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2602_10064_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
+    for name in KERNEL_SOURCES:
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(name.encode())
             h.update(f.read())

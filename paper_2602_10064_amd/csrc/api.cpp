@@ -47,6 +47,7 @@ void drop_graph(tacaw_job* j) {
 
 void free_job_buffers(tacaw_job* j) {
   drop_graph(j);
+  if (j->d_exit) j->present.clear();   // a new exit store holds no frames
   void* bufs[] = {j->d_exit,    j->d_spec,   j->d_V,      j->d_pos,     j->d_species,   j->d_tile_start,
                   j->d_tile_atoms, j->d_coef, j->d_tw_x,  j->d_tw_y,    j->d_tw_t,      j->d_px,
                   j->d_py,      j->d_px_last, j->d_py_last, j->d_probe0, j->d_origin,   j->d_rloc,
@@ -433,7 +434,10 @@ tacaw_status materialize(tacaw_job* j, hipStream_t s0) {
 void release_working(tacaw_job* j) {
   float2* keep_exit = (j->desc.flags & TACAW_KEEP_EXIT_WAVES) ? j->d_exit : nullptr;
   float* keep_spec = j->d_spec;
-  if (!keep_exit && j->d_exit) (void)hipFree(j->d_exit);
+  if (!keep_exit && j->d_exit) {
+    (void)hipFree(j->d_exit);
+    j->present.clear();   // a new exit store holds no frames
+  }
   j->d_exit = nullptr;
   j->d_spec = nullptr;
   free_job_buffers(j);
