@@ -327,7 +327,11 @@ tacaw_status tacaw_mean_diffraction(tacaw_job* job, double* dst, size_t n, int d
 tacaw_status tacaw_adf(tacaw_job* job, double inner_mrad, double outer_mrad, double* dst, size_t n,
                        int dst_on_device);
 
-/* Slice index of every atom (n_atoms int32, host), as the planner binned it. */
+/* ---- job inspection and teardown -------------------------------------------- */
+
+/* Slice index of every atom (n_atoms int32, host) from the FP64 frame-mean z,
+ * as the planner binned it.  With TACAW_SLICE_BY_INSTANT_Z this binning only
+ * orders the atoms; the potentials use each frame's own slice. */
 tacaw_status tacaw_job_slices(const tacaw_job* job, int32_t* slice_of_atom, size_t n);
 
 /* The planner's launch shapes for a job: frames advanced together through
