@@ -612,6 +612,7 @@ tacaw_status tacaw_run(tacaw_job* job, void* hip_stream) {
       HIP_TRY(hipGraphInstantiate(&job->graph_exec, job->graph, nullptr, nullptr, 0));
     }
     HIP_TRY(hipGraphLaunch(job->graph_exec, s));
+    mark_present(job, 0, job->hp.F);
     job->has_result = true;
     return TACAW_OK;
   }
