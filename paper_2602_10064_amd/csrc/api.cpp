@@ -446,6 +446,8 @@ void release_working(tacaw_job* j) {
   j->materialized = false;
 }
 
+void mark_all_present(tacaw_job* j) { j->present.assign(j->hp.F, 1); }
+
 size_t resident_bytes_after_done(const tacaw_job* j) {
   return j->fp.spec + ((j->desc.flags & TACAW_KEEP_EXIT_WAVES) ? j->fp.exit : 0);
 }

@@ -29,6 +29,10 @@
 
 #include "runtime.h"
 
+namespace tacaw {
+void mark_all_present(tacaw_job* j);   // every frame of the exit store holds exit waves
+}
+
 using namespace tacaw;
 
 namespace {
@@ -174,6 +178,7 @@ struct GroupRun {
       } else if (--left[L.job] == 0) {
         st = run_time_stage(L.job, s);
         if (st != TACAW_OK) return st;
+        mark_all_present(L.job);
         L.job->has_result = true;
         L.job->last_stream = s;
       }
@@ -291,6 +296,7 @@ tacaw_status tacaw_run_batch(tacaw_job* const* jobs, int n_jobs, void* hip_strea
     if (lf == j->hp.F) {
       r = run_time_stage(j, s0);
       if (r != TACAW_OK) return r;
+      mark_all_present(j);
       j->has_result = true;
       ++li;
       lf = 0;

@@ -18,6 +18,7 @@
 
 namespace tacaw {
 tacaw_status materialize(tacaw_job* j, hipStream_t s);
+void mark_all_present(tacaw_job* j);
 void release_working(tacaw_job* j);
 size_t resident_bytes_after_done(const tacaw_job* j);
 tacaw_status run_batch_range(tacaw_job* job, hipStream_t s, int f_begin, int f_end);
@@ -50,6 +51,7 @@ void finish(tacaw_ctx* c, Slot& s, int state) {
   (void)hipStreamSynchronize(s.stream);
   size_t keep = 0;
   if (state == ST_DONE) {
+    mark_all_present(j);
     j->has_result = true;
     j->last_stream = nullptr;
     release_working(j);

@@ -43,6 +43,16 @@ def test_frame_ranges_match_the_full_run(tacaw, ctx):
     with tacaw.TacawJob(ctx, job) as j:
         j.run()
         ex, spec = j.exit_waves(), j.spectrum()
+        j.finish()                      # a whole-job run leaves every frame present
+        assert np.array_equal(j.spectrum(), spec)
+    with tacaw.TacawJob(ctx, job, use_graph=True) as j:
+        j.run()
+        j.finish()                      # so does a graph replay
+        assert np.array_equal(j.spectrum(), spec)
+    with tacaw.TacawJob(ctx, job) as j:
+        tacaw.run_batch([j])
+        j.finish()                      # and the batched executor
+        assert np.array_equal(j.spectrum(), spec)
     with tacaw.TacawJob(ctx, job) as j:
         for f0, f1 in [(0, 5), (5, 9), (9, 12)]:
             j.run_frames(f0, f1)
