@@ -162,3 +162,18 @@ def test_window_is_a_shift_when_window_equals_cell(oracle):
         prop = oracle.propagator(16, 16, d, d, lam, job.cell[2] / job.n_slices)
         got = oracle.multislice(psi0, pots_w, sig, prop)
         assert np.max(np.abs(got - psi_shift)) < 1e-12
+
+
+def test_propagator_composition(oracle):
+    # P(a) P(b) = P(a + b): two empty slices of dz take a probe as far as one
+    # empty slice of 2 dz, and the factors compose exactly in FP64
+    nx, ny, dx, dy = 40, 32, 0.12, 0.15
+    lam = oracle.wavelength_A(100e3)
+    psi0 = oracle.probe_wave(nx, ny, dx, dy, lam, 0.025, 1.9, 2.3)
+    sig = oracle.sigma_rad_per_VA(100e3)
+    two = oracle.multislice(psi0, np.zeros((2, ny, nx)), sig, oracle.propagator(nx, ny, dx, dy, lam, 1.7))
+    one = oracle.multislice(psi0, np.zeros((1, ny, nx)), sig, oracle.propagator(nx, ny, dx, dy, lam, 3.4))
+    assert np.allclose(two, one, atol=1e-13)
+    pa = oracle.propagator(nx, ny, dx, dy, lam, 0.8)
+    pb = oracle.propagator(nx, ny, dx, dy, lam, 2.5)
+    assert np.allclose(pa * pb, oracle.propagator(nx, ny, dx, dy, lam, 3.3), atol=1e-13)
