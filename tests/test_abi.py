@@ -87,3 +87,14 @@ def test_footprint_scales_with_frames_and_probes():
     c2 = w.c2_plain(n_frames=2).replace(positions=np.zeros((1024, 1, 3)), atom_species=np.zeros(1, np.int32))
     # exit waves (2 GiB) + one-sided spectrum (512 MiB) dominate the c2 footprint
     assert t.footprint(c2) > (2 << 30) + (512 << 20)
+
+
+def test_per_frame_binning_footprint_and_limit():
+    t = _tacaw()
+    base = w.random_small_job(2, nx=16, ny=16, n_frames=8, n_atoms=12)
+    inst = base.replace(slice_by_instant_z=True)
+    # the per-frame slice table adds 2 bytes per frame and atom
+    assert t.footprint(inst) == t.footprint(base) + 2 * base.n_frames * base.n_atoms
+    with pytest.raises(t.TacawError) as e:
+        t.footprint(inst.replace(n_slices=40000))            # 16-bit slice indices
+    assert e.value.status == 1
