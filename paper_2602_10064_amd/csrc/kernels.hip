@@ -1023,144 +1023,6 @@ __global__ void __launch_bounds__(512) k_col_6s(PassTable tab, int total_tiles) 
 }
 
 // ---------------------------------------------------------------------------
-// Column pass for ny = 256 as 256 = 8 x 32, the second factor as 32 = 8 x 4;
-// tiles of 8 columns, 4 wavefronts.  Same scheme as k_col_6s:
-//   layout A: column c = lane % 8, r0 = 8 wave + lane / 8 (< 32), values at
-//             rows r0 + 32 j: 8-point transform over j, twiddle W256^(r0 k1);
-//   layout B: k1 = 2 wave + lane / 32, column (lane / 4) % 8, u = lane % 4,
-//             values at r0 = u + 4 q: 8-point transform over q, twiddle
-//             W32^(u k2), a local exchange among the 4 lanes of a column, and
-//             two 4-point transforms over u: lane u holds k2 = 2u + e (e < 2)
-//             at k = k1 + 8 k2 + 64 k3, k3 < 4.
-// LDS slots: element (c, k1, r0) at 256 k1 + 8 r0 + (c ^ 4 ((r0 >> 1) & 1));
-// wavefront w owns slots 512 w .. 512 w + 511, and group d = lane / 4 keeps
-// its local exchange at 32 d + 8 (u ^ ((d >> 1) & 1)) + (k2 ^ ((d % 4 + 4 (u >> 1)) % 8)).
-// Every 16-lane group of every access hits 16 distinct 8-byte slots modulo 16.
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_col_6s256(PassTable tab, int total_tiles) {
-  constexpr int N = 256, CT = 8;
-  __shared__ float2 xs[2048];
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  const int ca = lane & 7, r0 = 8 * wave + (lane >> 3);               // layout A
-  const int k1 = 2 * wave + (lane >> 5), cb = (lane >> 2) & 7, u = lane & 3, d = lane >> 2;   // layout B
-  const int sa = 8 * r0 + (ca ^ (4 * ((r0 >> 1) & 1)));              // + 256 k1
-  const int sb = 256 * k1 + 8 * u + (cb ^ (4 * ((u >> 1) & 1)));    // + 32 q
-  float2* lw = xs + 512 * wave + 32 * d;                              // local exchange region
-  const int lg = (d >> 1) & 1, lh = d & 3;
-  auto lslot = [&](int uu, int k2) { return 8 * (uu ^ lg) + (k2 ^ ((lh + 4 * (uu >> 1)) & 7)); };
-  float2 ta[8], tb[8];   // entries 1..7
-  {
-    const float2* tw = tab.l[0].a.tw_y;
-#pragma unroll
-    for (int k = 1; k < 8; ++k) {
-      ta[k] = tw[(r0 * k) & (N - 1)];
-      tb[k] = tw[(8 * u * k) & (N - 1)];
-    }
-  }
-  auto locate = [&](int it, int& L, int& x0, float2*& wp) {
-    const int tile_g = xcd_remap(it, total_tiles);
-    L = find_lane(tab, tile_g);
-    const PassArgs& a = tab.l[L].a;
-    const int tile = tile_g - tab.l[L].block_start;
-    const int tiles_per_wave = a.nx / CT;
-    const int w = tile / tiles_per_wave;
-    x0 = (tile % tiles_per_wave) * CT;
-    const int p = w / a.fb;
-    const int fl = w % a.fb;
-    wp = a.exit + ((size_t)p * a.n_frames + a.f0 + fl) * (size_t)N * a.nx;
-  };
-  float2 pre[8];
-  int L = 0, x0 = 0;
-  float2* wp = nullptr;
-  int it = blockIdx.x;
-  if (it < total_tiles) {
-    locate(it, L, x0, wp);
-    const int nx = tab.l[L].a.nx;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) pre[j] = wp[(size_t)(r0 + 32 * j) * nx + x0 + ca];
-  }
-  for (; it < total_tiles; it += gridDim.x) {
-    const PassArgs& a = tab.l[L].a;
-    const int mode = tab.l[L].mode;
-    const int nx = a.nx;
-    const int cur_x0 = x0;
-    float2* cur_wp = wp;
-    float2 x[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) x[j] = pre[j];
-    const int nit = it + gridDim.x;
-    if (nit < total_tiles) {
-      locate(nit, L, x0, wp);
-      const int nnx = tab.l[L].a.nx;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) pre[j] = wp[(size_t)(r0 + 32 * j) * nnx + x0 + ca];
-    }
-    // layout A: 8-point transform over j, twiddle, to LDS
-    dft8<false>(x);
-#pragma unroll
-    for (int k = 1; k < 8; ++k) x[k] = cmul(x[k], ta[k]);
-    __syncthreads();   // the previous tile's reads of the exchange buffer are done
-#pragma unroll
-    for (int k = 0; k < 8; ++k) xs[256 * k + sa] = x[k];
-    __syncthreads();
-    // layout B: 8-point transform over q, twiddle, local exchange, two 4-point transforms over u
-#pragma unroll
-    for (int q = 0; q < 8; ++q) x[q] = xs[sb + 32 * q];
-    dft8<false>(x);
-#pragma unroll
-    for (int k = 1; k < 8; ++k) x[k] = cmul(x[k], tb[k]);
-    wave_lds_sync();
-#pragma unroll
-    for (int k = 0; k < 8; ++k) lw[lslot(u, k)] = x[k];
-    wave_lds_sync();
-#pragma unroll
-    for (int e = 0; e < 2; ++e)
-#pragma unroll
-      for (int s = 0; s < 4; ++s) x[4 * e + s] = lw[lslot(s, 2 * u + e)];
-    dft4<false>(x);
-    dft4<false>(x + 4);   // x[4 e + k3] = psi(k1 + 8 (2 u + e) + 64 k3) of column cur_x0 + cb
-    const float2 pxv = a.px[cur_x0 + cb];
-#pragma unroll
-    for (int e = 0; e < 2; ++e)
-#pragma unroll
-      for (int k3 = 0; k3 < 4; ++k3)
-        x[4 * e + k3] = cmul(x[4 * e + k3], cmul(pxv, a.py[k1 + 8 * (2 * u + e) + 64 * k3]));
-    if (mode == COL_LAST) {
-#pragma unroll
-      for (int e = 0; e < 2; ++e)
-#pragma unroll
-        for (int k3 = 0; k3 < 4; ++k3)
-          cur_wp[(size_t)(k1 + 8 * (2 * u + e) + 64 * k3) * nx + cur_x0 + cb] = x[4 * e + k3];
-      continue;
-    }
-    // inverse, the same steps backwards
-    dft4<true>(x);
-    dft4<true>(x + 4);    // x[4 e + s] at u-index s, k2 = 2 u + e
-    wave_lds_sync();
-#pragma unroll
-    for (int e = 0; e < 2; ++e)
-#pragma unroll
-      for (int s = 0; s < 4; ++s) lw[lslot(s, 2 * u + e)] = x[4 * e + s];
-    wave_lds_sync();
-    x[0] = lw[lslot(u, 0)];
-#pragma unroll
-    for (int k = 1; k < 8; ++k) x[k] = cmulc(lw[lslot(u, k)], tb[k]);
-    dft8<true>(x);        // over k2: x[q] at r0 = u + 4 q
-    wave_lds_sync();
-#pragma unroll
-    for (int q = 0; q < 8; ++q) xs[sb + 32 * q] = x[q];
-    __syncthreads();
-    // layout A: conjugate twiddle, 8-point transform over k1, store
-    x[0] = xs[sa];
-#pragma unroll
-    for (int k = 1; k < 8; ++k) x[k] = cmulc(xs[256 * k + sa], ta[k]);
-    dft8<true>(x);
-#pragma unroll
-    for (int j = 0; j < 8; ++j) cur_wp[(size_t)(r0 + 32 * j) * nx + cur_x0 + ca] = x[j];
-  }
-}
-
-// ---------------------------------------------------------------------------
 // Register FFTs with 12 or 16 values per lane (N = 384 and 768: 12 values,
 // radices 6, 4, 4, 4 [, 2]; N = 1024: 16 values, radices 8, 8, 4, 4).  Same
 // layout and wavefront-local exchanges as the 8-value kernels; the stage
@@ -1817,31 +1679,16 @@ static hipError_t col_6s_launch(PassTable& t, hipStream_t s) {
   return hipGetLastError();
 }
 
-static hipError_t col_6s256_launch(PassTable& t, hipStream_t s) {
-  int tiles = 0;
-  for (int i = 0; i < t.n; ++i) {
-    const PassArgs& a = t.l[i].a;
-    if (a.ny != 256 || a.nx % 8 != 0) return hipErrorInvalidValue;
-    t.l[i].block_start = tiles;
-    tiles += a.n_probes * a.fb * (a.nx / 8);
-  }
-  const char* ge = getenv("TACAW_COL_GRID");
-  const int cap = ge && atoi(ge) > 0 ? atoi(ge) : 2048;
-  const int grid = std::min(tiles, cap);
-  TACAW_LAUNCH(k_col_6s256, dim3(grid), dim3(256), 0, s, t, tiles);
-  return hipGetLastError();
-}
-
 hipError_t launch_col_lanes(const PassLane* lanes, int n, int variant, hipStream_t s) {
   if (n < 1 || n > MAX_LANES || !same_grid(lanes, n)) return hipErrorInvalidValue;
   PassTable t{};
   t.n = n;
   for (int i = 0; i < n; ++i) t.l[i] = lanes[i];
   if (variant == 5) {
-    // six-step kernels: ny = 512 or 256, regular and last-slice modes
-    bool ok = (lanes[0].a.ny == 512 || lanes[0].a.ny == 256) && lanes[0].a.nx % 8 == 0;
+    // six-step kernel: ny = 512, regular and last-slice modes
+    bool ok = lanes[0].a.ny == 512 && lanes[0].a.nx % 8 == 0;
     for (int i = 0; i < n; ++i) ok = ok && lanes[i].mode != COL_INVERSE_ONLY;
-    if (ok) return lanes[0].a.ny == 512 ? col_6s_launch(t, s) : col_6s256_launch(t, s);
+    if (ok) return col_6s_launch(t, s);
     variant = 2;
   }
   if (variant == 4) {
