@@ -249,8 +249,8 @@ def main():
                     help="also run a plain 1 GiB device copy (for counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; the multi-GPU sharding is a "
-                          "design (independent frames/probes per GPU), not implemented"}))
+        print(json.dumps({"error": "runs on one GPU only: sharding across GPUs (independent frames or "
+                          "probes per GPU) is designed, not implemented"}))
         sys.exit(2)
 
     import torch
