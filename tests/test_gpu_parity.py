@@ -309,3 +309,20 @@ def test_per_frame_slice_binning(tacaw, ctx, oracle, probes):
     # the frame-mean binning gives a different result on this trajectory
     mean = oracle.exit_waves(dataclasses.replace(job, slice_by_instant_z=False), frames=[0, 5])
     assert rel_l2(ex[:, [0, 5]], mean) > 2 * EXIT_TOL
+
+
+def test_integer_pixel_translation_leaves_spectrum(tacaw, ctx):
+    # moving every atom by whole pixels translates each potential exactly on the
+    # periodic grid; the exit wave gains a frame-independent phase in k, which
+    # the mean subtraction and |.|^2 remove, so I(k, w) is unchanged (up to the
+    # rounding of the shifted positions)
+    import dataclasses
+    job = w.random_small_job(49, nx=64, ny=48, n_slices=3, n_frames=16, n_atoms=12, cell=(8.0, 6.0, 4.0))
+    dx, dy = job.cell[0] / job.nx, job.cell[1] / job.ny
+    pos = job.positions.copy()
+    pos[:, :, 0] = np.mod(pos[:, :, 0] + 13 * dx, job.cell[0])
+    pos[:, :, 1] = np.mod(pos[:, :, 1] + 29 * dy, job.cell[1])
+    moved = dataclasses.replace(job, positions=pos)
+    _, a, _ = run_gpu(tacaw, ctx, job)
+    _, b, _ = run_gpu(tacaw, ctx, moved)
+    assert rel_l2(b, a) < 1e-4
