@@ -42,7 +42,7 @@ typedef enum {
   TACAW_EBUSY = 4,         /* the job is queued or running in the serving loop     */
   TACAW_ENOTREADY = 5,     /* no result yet (the job has not been run)             */
   TACAW_ECANCELLED = 6,    /* the job was cancelled before it finished             */
-  TACAW_EUNSUPPORTED = 7   /* valid, but a grid size this build does not provide   */
+  TACAW_EUNSUPPORTED = 7   /* valid, but a grid size the library has no kernel for */
 } tacaw_status;
 
 /* Number of Gaussian terms per species in the form factor. */
@@ -152,7 +152,7 @@ tacaw_status tacaw_job_footprint(const tacaw_job_desc* desc, size_t* bytes);
  * indices into species_Z (host).  positions: n_frames x n_atoms x 3 [A]
  * (host, float64).  Errors: EINVAL (invalid description or species index),
  * ENOMEM (footprint above the context budget), EUNSUPPORTED (grid size
- * without a kernel in this build), EDEVICE. */
+ * without a kernel in the library), EDEVICE. */
 tacaw_status tacaw_job_create(tacaw_ctx* ctx, const tacaw_job_desc* desc,
                               const int32_t* atom_species, const double* positions,
                               tacaw_job** out);

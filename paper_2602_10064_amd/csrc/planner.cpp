@@ -89,7 +89,7 @@ tacaw_status validate_desc(const tacaw_job_desc* d) {
     return TACAW_EINVAL;
   }
   if (d->n_frames > 2048) {
-    set_error("n_frames %d above the 2048 this build's time stage holds in LDS", d->n_frames);
+    set_error("n_frames %d above the 2048 the time stage holds in LDS", d->n_frames);
     return TACAW_EUNSUPPORTED;
   }
   if (d->n_atoms < 0) {
@@ -148,7 +148,7 @@ tacaw_status validate_desc(const tacaw_job_desc* d) {
     return TACAW_EUNSUPPORTED;
   }
   if (!grid_supported(d->nx) || !grid_supported(d->ny)) {
-    set_error("grid %dx%d: this build has kernels for 16, 32, 48, 64, 96, 128, 160, 192, 256, 320, "
+    set_error("grid %dx%d: the library has kernels for 16, 32, 48, 64, 96, 128, 160, 192, 256, 320, "
               "384, 512, 640, 768, 1024",
               d->nx, d->ny);
     return TACAW_EUNSUPPORTED;
