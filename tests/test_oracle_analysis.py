@@ -57,11 +57,13 @@ def test_dispersion_nearest_nodes():
     rng = np.random.default_rng(2)
     nx, ny, lx, ly = 10, 8, 5.0, 4.0
     spec = rng.random((2, 7, ny, nx)).astype(np.float32)
-    # exact grid points, a negative frequency (wraps to the last index) and a
-    # point just below half way to the next node
-    kx = np.array([0.0, 3 / lx, -1 / lx, 2.49 / lx])
-    ky = np.array([0.0, 1 / ly, 0.0, -2 / ly])
+    # exact grid points, a negative frequency (wraps to the last index), a
+    # point just below half way to the next node; points past half way up
+    # (2.6 nodes -> 3) and down (-2.4 nodes -> -2), where rounding and
+    # truncation differ; a tie half way (2.5 nodes) goes to the upper node
+    kx = np.array([0.0, 3 / lx, -1 / lx, 2.49 / lx, 2.6 / lx, -2.4 / lx, 2.5 / lx, 0.0])
+    ky = np.array([0.0, 1 / ly, 0.0, -2 / ly, -2.4 / ly, 2.6 / ly, 0.0, 1.5 / ly])
     d = o.dispersion(spec, kx, ky, lx, ly)
-    want = [(0, 0), (1, 3), (0, nx - 1), (ny - 2, 2)]
+    want = [(0, 0), (1, 3), (0, nx - 1), (ny - 2, 2), (ny - 2, 3), (3, nx - 2), (0, 3), (2, 0)]
     for i, (iy, ix) in enumerate(want):
         assert np.allclose(d[i], spec[0, :, iy, ix] + spec[1, :, iy, ix])

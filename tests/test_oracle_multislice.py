@@ -164,6 +164,58 @@ def test_window_is_a_shift_when_window_equals_cell(oracle):
         assert np.max(np.abs(got - psi_shift)) < 1e-12
 
 
+def _tiled_job(job, tiles):
+    """The same atoms repeated tiles[0] x tiles[1] times in x and y, in a cell
+    that many times larger (every frame's potential is then periodic with the
+    small cell's period)."""
+    tx, ty = tiles
+    lx, ly = job.cell[0], job.cell[1]
+    shifts = np.array([[i * lx, j * ly, 0.0] for j in range(ty) for i in range(tx)])
+    pos = (job.positions[:, None, :, :] + shifts[None, :, None, :]).reshape(job.n_frames, -1, 3)
+    species = np.tile(job.atom_species, tx * ty)
+    cell = np.array([tx * lx, ty * ly, job.cell[2]])
+    return job.replace(cell=cell, positions=pos, atom_species=species,
+                       pot_nx=tx * job.nx, pot_ny=ty * job.ny)
+
+
+def test_windowed_branch_on_a_tiled_cell(oracle):
+    # The potential grid tiles a window-sized cell 3 x 2 times, so a window of
+    # the wave grid cut at origin o (pixels) holds the small cell's potential
+    # cyclically shifted by o.  The window's probe sits at r - o d.  The whole
+    # windowed system is therefore the small cell's system translated by -o d,
+    # and by the Fourier shift theorem
+    #     psi_window(k) = psi_small(k) exp(+2 pi i k . o d),
+    # with the probe at r in the small (periodic) cell.  The origin is the
+    # pixel under the probe minus half the window, so the probe sits at the
+    # window's centre pixel.  Probes near both cell edges make the window wrap.
+    from paper_2602_10064_amd import workloads as w
+    small = w.random_small_job(4, nx=16, ny=12, n_slices=2, n_frames=2, n_atoms=5,
+                               aperture_mrad=80.0, n_probes=1, cell=(4.0, 3.6, 3.0), voltage_V=60e3)
+    big = _tiled_job(small, (3, 2))
+    dx, dy = 0.25, 0.3
+    # (rx, ry) in the big cell [12 x 7.2 A] and the expected origin by hand:
+    # floor(rx / dx) - 8, floor(ry / dy) - 6
+    probes = np.array([[5.93, 3.41],      # 23.72 px, 11.37 px -> origin (15, 5)
+                       [0.10, 0.05],      # wraps below 0 on both axes -> (-8, -6)
+                       [11.95, 7.16],     # wraps past the far edges -> (39, 17)
+                       [2.20, 6.40]])     # -> (0, 15)
+    expect_origin = [(15, 5), (-8, -6), (39, 17), (0, 15)]
+    big = big.replace(probe_xy=probes)
+    got = oracle.exit_waves(big)
+    kx = np.fft.fftfreq(16, dx)
+    ky = np.fft.fftfreq(12, dy)
+    for p, (rx, ry) in enumerate(probes):
+        ox, oy = expect_origin[p]
+        assert oracle.window_origin(rx, ry, dx, dy, 16, 12) == (ox, oy)
+        # the probe lands in the window's centre pixel
+        assert 8 * dx <= rx - ox * dx < 9 * dx and 6 * dy <= ry - oy * dy < 7 * dy
+        ref = oracle.exit_waves(small.replace(probe_xy=np.array([[rx, ry]])))[0]
+        ramp = np.exp(2j * math.pi * (kx[None, :] * ox * dx + ky[:, None] * oy * dy))
+        assert np.max(np.abs(got[p] - ref * ramp[None])) < 1e-12, p
+    # the probes really see different potentials (the comparison is not vacuous)
+    assert np.max(np.abs(got[0] - got[1])) > 1e-3
+
+
 def test_propagator_composition(oracle):
     # P(a) P(b) = P(a + b): two empty slices of dz take a probe as far as one
     # empty slice of 2 dz, and the factors compose exactly in FP64
