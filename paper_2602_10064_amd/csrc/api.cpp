@@ -583,6 +583,7 @@ tacaw_status tacaw_run(tacaw_job* job, void* hip_stream) {
     set_error("job is in the serving loop");
     return TACAW_EBUSY;
   }
+  leave_serving_state(job);
   HIP_TRY(hipSetDevice(job->ctx->device));
   tacaw_status st = materialize(job);
   if (st != TACAW_OK) return st;
@@ -659,6 +660,7 @@ tacaw_status tacaw_run_frames(tacaw_job* job, int32_t f_begin, int32_t f_end, vo
   tacaw_status st = check_idle(job);
   if (st != TACAW_OK) return st;
   if ((st = check_range(job, f_begin, f_end)) != TACAW_OK) return st;
+  leave_serving_state(job);
   HIP_TRY(hipSetDevice(job->ctx->device));
   if ((st = materialize(job)) != TACAW_OK) return st;
   hipStream_t s = (hipStream_t)hip_stream;
@@ -679,6 +681,7 @@ tacaw_status tacaw_finish(tacaw_job* job, void* hip_stream) {
     set_error("%d of %d frames have no exit waves yet", missing, job->hp.F);
     return TACAW_ENOTREADY;
   }
+  leave_serving_state(job);
   HIP_TRY(hipSetDevice(job->ctx->device));
   hipStream_t s = (hipStream_t)hip_stream;
   job->last_stream = s;

@@ -234,6 +234,7 @@ tacaw_status tacaw_run_batch(tacaw_job* const* jobs, int n_jobs, void* hip_strea
         return TACAW_EINVAL;
       }
   }
+  for (int i = 0; i < n_jobs; ++i) leave_serving_state(jobs[i]);
   if (hipSetDevice(c->device) != hipSuccess) {
     set_error("hipSetDevice failed");
     return TACAW_EDEVICE;

@@ -168,3 +168,13 @@ struct tacaw_job {
   size_t retained = 0;               // bytes counted in ctx->resident after a served job ends
   bool served = false;
 };
+
+// A plain, batched or frame-range run takes a job back from a finished,
+// cancelled or failed serving state to idle, so the results of that run are
+// not reported as cancelled or failed.  Queued and running jobs are left alone
+// (the callers refuse them first).
+inline void leave_serving_state(tacaw_job* j) {
+  int s = j->serve_state.load();
+  while (s >= 3 && !j->serve_state.compare_exchange_weak(s, 0)) {
+  }
+}

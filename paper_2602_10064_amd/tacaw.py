@@ -243,6 +243,7 @@ class TacawJob:
         self.n_frames = self._d.desc.n_frames
         self.n_bins = self.n_frames if job.two_sided else self.n_frames // 2
         self.nx, self.ny = job.nx, job.ny
+        self.aberrations = None
         ab = getattr(job, "aberrations", None)
         if ab is not None:
             self.set_aberrations(ab[0], ab[1])
@@ -373,12 +374,14 @@ class TacawJob:
         for (n, m) = 10, 12, 21, 23, 30, 32, 34, 41, 43, 45, 50, 52, 54, 56."""
         if c_angstrom is None:
             _check(lib().tacaw_job_set_aberrations(self.handle, None, None))
+            self.aberrations = None
             return
         c = np.ascontiguousarray(c_angstrom, dtype=np.float64).reshape(-1)
         a = np.zeros(14) if phi_rad is None else np.ascontiguousarray(phi_rad, dtype=np.float64).reshape(-1)
         if c.size != 14 or a.size != 14:
             raise ValueError("need 14 aberration coefficients and 14 angles")
         _check(lib().tacaw_job_set_aberrations(self.handle, _ptr(c, ctypes.c_double), _ptr(a, ctypes.c_double)))
+        self.aberrations = (c.copy(), a.copy())
 
     def mean_diffraction(self) -> np.ndarray:
         """Frame-averaged diffraction pattern of every probe: [P, ny, nx] float64."""

@@ -8,9 +8,16 @@ import pytest
 from paper_2602_10064_amd.checkpoint import run_with_checkpoints
 
 
+from paper_2602_10064_amd import workloads as w
+
+
 class FakeJob:
-    def __init__(self, n_probes=2, n_frames=10, ny=3, nx=4):
+    def __init__(self, n_probes=2, n_frames=10, ny=3, nx=4, seed=7, aberrations=None):
         self.n_probes, self.n_frames, self.ny, self.nx = n_probes, n_frames, ny, nx
+        # the description the digest reads (the stand-in's waves do not depend on it)
+        self.job = w.random_small_job(seed, nx=nx, ny=ny, n_frames=n_frames, aperture_mrad=20.0,
+                                      n_probes=n_probes)
+        self.aberrations = aberrations
         self.store = np.zeros((n_probes, n_frames, ny, nx), np.complex64)
         self.present = np.zeros(n_frames, bool)
         self.computed = []
@@ -58,3 +65,23 @@ def test_other_job_or_chunking_is_refused(tmp_path):
         run_with_checkpoints(FakeJob(), str(tmp_path), 5)
     with pytest.raises(ValueError):
         run_with_checkpoints(FakeJob(), str(tmp_path / "x"), 0)
+
+
+def test_changed_job_in_same_directory_is_refused(tmp_path):
+    # same exit-store shape and chunking, different inputs: restoring the first
+    # job's waves would give a wrong spectrum silently
+    run_with_checkpoints(FakeJob(), str(tmp_path), 4)
+    assert run_with_checkpoints(FakeJob(), str(tmp_path), 4) == 0       # the same job restores
+    with pytest.raises(ValueError):
+        run_with_checkpoints(FakeJob(seed=8), str(tmp_path), 4)         # another trajectory
+    other = FakeJob()
+    other.job = other.job.replace(voltage_V=200e3)
+    with pytest.raises(ValueError):
+        run_with_checkpoints(other, str(tmp_path), 4)
+    ab = (np.r_[50.0, np.zeros(13)], np.zeros(14))
+    with pytest.raises(ValueError):
+        run_with_checkpoints(FakeJob(aberrations=ab), str(tmp_path), 4)
+    moved = FakeJob()
+    moved.job = moved.job.replace(probe_xy=moved.job.probe_xy + 0.1)
+    with pytest.raises(ValueError):
+        run_with_checkpoints(moved, str(tmp_path), 4)

@@ -113,3 +113,28 @@ def test_streamed_arrivals_overlap(tacaw):
         assert np.all(lat > 0)
         for h in hs:
             h.destroy()
+
+
+def test_cancelled_job_then_plain_run(tacaw):
+    # a job cancelled in the serving loop and then run in the plain form
+    # reports that run's spectrum, not the cancellation
+    jobs = mix()
+    victim_job = w.c1_tiny(n_frames=64)
+    with tacaw.Context(0) as ctx:
+        ref = alone(tacaw, ctx, victim_job)
+    with tacaw.Context(0) as ctx:
+        hs = [tacaw.TacawJob(ctx, j, defer_alloc=True) for j in jobs[:2]]
+        victim = tacaw.TacawJob(ctx, victim_job, defer_alloc=True)
+        for h in hs:
+            h.submit()
+        victim.submit()
+        victim.cancel()
+        with pytest.raises(tacaw.TacawError) as e:
+            victim.wait()
+        assert e.value.status == 6
+        victim.run()
+        assert np.array_equal(victim.spectrum().view(np.uint32), ref.view(np.uint32))
+        for h in hs:
+            h.wait()
+        for h in hs + [victim]:
+            h.destroy()
