@@ -13,7 +13,10 @@ What it computes (paper: PySlice, arXiv 2602.10064):
     assembled from per-species form factors over the atoms inside the slice's
     z-bounds.  The paper's tabulated Kirkland coefficients are not available;
     a 5-term Gaussian form factor f(q) = C sum_i a_i exp(-b_i q^2) stands in
-    (reading R1 below), evaluated in real space.
+    (reading R1 below), evaluated in real space.  The paper's own route, its
+    3 Lorentzian + 3 Gaussian form summed as a structure factor in reciprocal
+    space and inverse-transformed, is kspace_potential (reading R-kspace),
+    used when a job carries per-species coefficients of that form.
   * Methods 2.1 "Workflow Architecture": psi~(k, w) = F_t[psi(k,t) - <psi(k,t)>_t]
     and I(k, w) = |psi~(k, w)|^2.
   * Supplement "Sampling Considerations": dk = 1/L, df = 1/(N dt), f_max = 1/(2 dt).
@@ -26,6 +29,13 @@ Readings taken where the paper is silent, garbled or inconsistent:
             is the 2D Fourier transform of C sum_i a_i exp(-b_i q^2), in V*A.
   R-images  Every periodic image whose FP64 contribution is non-zero is summed
             (no cutoff).
+  R-kspace  The paper's own route (optional, with per-species coefficients of
+            its 3 Lorentzian + 3 Gaussian form): V(k) = sum_j f(k) exp(-2 pi i
+            k.r_j) at the potential grid's own fftfreq frequencies (one period,
+            so the potential is band-limited), inverse FFT, times C/A; the real
+            part is kept.  Only the unpaired Nyquist frequencies of even grids
+            make the sum complex, so keeping the real part is the same as taking
+            each Nyquist term as the mean of its +k and -k images.
   R-bin     An atom belongs to slice floor((zbar mod Lz)/dz) (clamped), zbar being
             its FP64 mean z over all frames; slices are half-open [k dz, (k+1) dz).
             Optionally (slice_by_instant_z) each frame bins by its own z, the
@@ -171,16 +181,56 @@ def projected_potential(xy: np.ndarray, species: np.ndarray, gauss_a: np.ndarray
     return (prof_y * weight[:, None]).T @ prof_x
 
 
+def kirkland_form_factor(q2: np.ndarray, p) -> np.ndarray:
+    """The paper's parameterised form factor (Methods 2.2, Atomic Scattering
+    Potentials): f(q) = sum_{i=1..3} [a_i / (q^2 + b_i) + c_i exp(-d_i q^2)],
+    q in cycles/A.  p = (a1, a2, a3, b1, b2, b3, c1, c2, c3, d1, d2, d3) with
+    a in 1/A, b in 1/A^2, c in A, d in A^2, so f is in A."""
+    p = np.asarray(p, dtype=np.float64)
+    out = np.zeros_like(q2, dtype=np.float64)
+    for i in range(3):
+        out += p[i] / (q2 + p[3 + i]) + p[6 + i] * np.exp(-p[9 + i] * q2)
+    return out
+
+
+def kspace_potential(xy: np.ndarray, species: np.ndarray, kirkland: np.ndarray,
+                     lx: float, ly: float, nx: int, ny: int) -> np.ndarray:
+    """The paper's reciprocal-space route (Methods 2.2, Atomic Scattering
+    Potentials; reading R-kspace): the structure-factor sum
+        V(k) = sum_j f_{Z_j}(|k|) exp(-2 pi i k.r_j)
+    over the slice's atoms at the grid's own frequencies k (numpy fftfreq of
+    the potential grid, one period: band-limited), then an inverse FFT:
+        V(r_p) = Re (C/A) sum_k V(k) exp(+2 pi i k.r_p),
+    C = 2 pi a0 e (reading R1), A = Lx Ly.  Returns V[ny, nx] in V*A.
+    kirkland: [S, 12] coefficients per species (kirkland_form_factor order)."""
+    kx = k_axis(nx, lx / nx)
+    ky = k_axis(ny, ly / ny)
+    q2 = ky[:, None] ** 2 + kx[None, :] ** 2
+    vk = np.zeros((ny, nx), dtype=np.complex128)
+    for s in np.unique(species):
+        f = kirkland_form_factor(q2, kirkland[int(s)])
+        for j in np.nonzero(species == s)[0]:
+            vk += f * np.exp(-2j * math.pi * (kx[None, :] * xy[j, 0] + ky[:, None] * xy[j, 1]))
+    # numpy's ifft2 carries 1/(nx ny): (C/A) sum_k = C/(dx dy) ifft2
+    return (potential_prefactor() * nx * ny / (lx * ly) * np.fft.ifft2(vk)).real
+
+
 def frame_potentials(positions_f: np.ndarray, atom_species: np.ndarray, slice_of: np.ndarray,
                      gauss_a: np.ndarray, gauss_b: np.ndarray, lx: float, ly: float,
-                     nx: int, ny: int, n_slices: int) -> np.ndarray:
-    """Projected potential of every slice for one frame: [n_slices, ny, nx]."""
+                     nx: int, ny: int, n_slices: int, kirkland=None) -> np.ndarray:
+    """Projected potential of every slice for one frame: [n_slices, ny, nx].
+    With kirkland ([S, 12]) the paper's reciprocal-space route is used instead
+    of the real-space Gaussian sum."""
     out = np.zeros((n_slices, ny, nx))
     for s in range(n_slices):
         sel = np.nonzero(slice_of == s)[0]
         if len(sel):
-            out[s] = projected_potential(positions_f[sel, :2], atom_species[sel], gauss_a,
-                                         gauss_b, lx, ly, nx, ny)
+            if kirkland is not None:
+                out[s] = kspace_potential(positions_f[sel, :2], atom_species[sel], kirkland,
+                                          lx, ly, nx, ny)
+            else:
+                out[s] = projected_potential(positions_f[sel, :2], atom_species[sel], gauss_a,
+                                             gauss_b, lx, ly, nx, ny)
     return out
 
 
@@ -294,7 +344,8 @@ def exit_waves(job, frames=None, probes=None) -> np.ndarray:
     for fi, f in enumerate(frames):
         slices_f = slice_of[f] if instant else slice_of
         pots = frame_potentials(job.positions[f], job.atom_species, slices_f, job.gauss_a,
-                                job.gauss_b, lx, ly, pot_nx, pot_ny, job.n_slices)
+                                job.gauss_b, lx, ly, pot_nx, pot_ny, job.n_slices,
+                                getattr(job, "kirkland", None))
         for pi, p in enumerate(probes):
             if plane:
                 psi0 = plane_wave(job.nx, job.ny)

@@ -57,6 +57,10 @@ class Job:
     aberrations: Optional[np.ndarray] = None
     # bin atoms into slices by each frame's own z instead of the frame-mean z
     slice_by_instant_z: bool = False
+    # the paper's reciprocal-space potential route: None, or (S, 12) per-species
+    # coefficients (a1..a3 [1/A], b1..b3 [1/A^2], c1..c3 [A], d1..d3 [A^2]) of
+    # f(q) = sum_i a_i / (q^2 + b_i) + c_i exp(-d_i q^2)
+    kirkland: Optional[np.ndarray] = None
     name: str = ""
 
     @property
@@ -201,6 +205,32 @@ def gaussian_coefficients(seed: int, species_Z: Sequence[int]):
         a[s] = rng.uniform(0.1, 2.0, size=5)
         b[s] = rng.uniform(0.1, 10.0, size=5)
     return a, b
+
+
+def kirkland_coefficients(seed: int, species_Z: Sequence[int]) -> np.ndarray:
+    """Per-species coefficients of the 3 Lorentzian + 3 Gaussian form factor
+    f(q) = sum_i a_i / (q^2 + b_i) + c_i exp(-d_i q^2) (the tabulated values are
+    not available; these stand in with magnitudes of the same order).
+
+    For each Z: rng = default_rng([seed, Z, 3]); a = U[0.05, 1] x3 (1/A), then
+    b = U[0.5, 50] x3 (1/A^2), then c = U[0.005, 0.2] x3 (A), then
+    d = U[0.1, 4] x3 (A^2).  Returns (S, 12) in that order.
+    """
+    out = np.zeros((len(species_Z), 12))
+    for s, z in enumerate(species_Z):
+        rng = np.random.default_rng([int(seed), int(z), 3])
+        out[s, 0:3] = rng.uniform(0.05, 1.0, size=3)
+        out[s, 3:6] = rng.uniform(0.5, 50.0, size=3)
+        out[s, 6:9] = rng.uniform(0.005, 0.2, size=3)
+        out[s, 9:12] = rng.uniform(0.1, 4.0, size=3)
+    return out
+
+
+def with_kirkland(job: "Job", seed: int = 0) -> "Job":
+    """The same job with the paper's reciprocal-space potential route (seeded
+    coefficients per species of the job)."""
+    return dataclasses.replace(job, kirkland=kirkland_coefficients(seed, job.species_Z),
+                               name=f"{job.name}_kspace")
 
 
 def probe_scan(x0: float, x1: float, nxp: int, y0: float, y1: float, nyp: int) -> np.ndarray:
