@@ -299,6 +299,20 @@ tacaw_status tacaw_spectral_diffraction(tacaw_job* job, double f_THz, double* ds
 tacaw_status tacaw_spectrum_image(tacaw_job* job, double f_THz, double k_inner, double k_outer, double* dst,
                                   size_t n, int dst_on_device);
 
+/* Allocation-free variant of tacaw_spectrum_image, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): same arguments, same result, same kernel.
+ * The per-probe sums and the k-axis tables sit in one fixed device array of
+ * the library (544 KiB per GPU, held until the process ends) instead of
+ * buffers allocated per call; the call allocates and frees nothing.
+ * Limits: n_probes <= 65536 and nx + ny <= 4096, else EINVAL (use
+ * tacaw_spectrum_image).  Every call on one GPU shares that GPU's array:
+ * calls that overlap in time on one GPU (from several threads, or while an
+ * earlier call's copy is still in flight) race and must be serialised by the
+ * caller.  Each call writes every value it reads, so no clearing is needed. */
+tacaw_status tacaw_spectrum_image_noalloc(tacaw_job* job, double f_THz, double k_inner, double k_outer,
+                                          double* dst, size_t n, int dst_on_device);
+
 /* D[i][m] = sum over probes of I[p][m] at the grid node nearest to the path
  * point (kx[i], ky[i]) (cycles/A; node index round(k L) mod N with L = N d
  * the wave grid's extent, fftfreq order), for every kept bin m; kx, ky are host arrays of n_points;

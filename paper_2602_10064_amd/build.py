@@ -13,7 +13,7 @@ CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libtacaw.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["kernels.hip", "api.cpp", "planner.cpp", "serve.cpp", "batch.cpp", "analysis.cpp"]
+SOURCES = ["kernels.hip", "noalloc.hip", "api.cpp", "planner.cpp", "serve.cpp", "batch.cpp", "analysis.cpp"]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950",

@@ -29,6 +29,10 @@ namespace {
     }                                                                       \
   } while (0)
 
+}  // namespace
+
+namespace tacaw {
+
 // the job must hold a spectrum
 tacaw_status check_ready(const tacaw_job* job) {
   if (!job) {
@@ -83,6 +87,10 @@ tacaw_status nearest_bin(const tacaw_job* job, double f, int* m_out) {
   return TACAW_OK;
 }
 
+}  // namespace tacaw
+
+namespace {
+
 // device scratch of the analysis calls, freed on return
 struct DevBuf {
   void* p = nullptr;
@@ -103,6 +111,10 @@ tacaw_status finish_copy(tacaw_job* job, hipStream_t s, double* dst, const doubl
   return TACAW_OK;
 }
 
+}  // namespace
+
+namespace tacaw {
+
 // unshifted axes kx then ky, k = fftfreq(N, d): i * (1 / (N d)), i wrapped to
 // negative values from (N + 1) / 2 on
 std::vector<double> k_axes(const HostPlan& hp) {
@@ -112,6 +124,10 @@ std::vector<double> k_axes(const HostPlan& hp) {
   for (int i = 0; i < hp.ny; ++i) ax[hp.nx + i] = (i < (hp.ny + 1) / 2 ? i : i - hp.ny) * fy;
   return ax;
 }
+
+}  // namespace tacaw
+
+namespace {
 
 // the job must hold its exit waves
 tacaw_status check_exit(const tacaw_job* job) {

@@ -476,6 +476,9 @@ tacaw_status tacaw_ctx_create(int device, size_t hbm_budget_bytes, tacaw_ctx** o
   HIP_TRY(hipSetDevice(device));
   size_t fr = 0, tot = 0;
   HIP_TRY(hipMemGetInfo(&fr, &tot));
+  // device address of the allocation-free entry points' fixed scratch array
+  tacaw_status st = noalloc_init(device);
+  if (st != TACAW_OK) return st;
   tacaw_ctx* c = new tacaw_ctx();
   c->device = device;
   c->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)fr);

@@ -83,6 +83,17 @@ tacaw_status run_time_stage(tacaw_job* job, hipStream_t s);
 
 struct tacaw_ctx_impl;
 
+// Spectrum analysis helpers (analysis.cpp): the job must hold a spectrum; the
+// kept frequency bin nearest to f; the unshifted kx then ky axes of the wave
+// grid (fftfreq order).
+tacaw_status check_ready(const tacaw_job* job);
+tacaw_status nearest_bin(const tacaw_job* job, double f, int* m_out);
+std::vector<double> k_axes(const HostPlan& hp);
+
+// Device address of the allocation-free entry points' fixed scratch array on
+// `device` (noalloc.hip); looked up once per device with that device current.
+tacaw_status noalloc_init(int device);
+
 }  // namespace tacaw
 
 struct tacaw_ctx {

@@ -63,7 +63,7 @@ EXPORTED = [
     "tacaw_get_exit_waves", "tacaw_axes", "tacaw_job_slices", "tacaw_job_destroy", "tacaw_last_error",
     "tacaw_timing_enable", "tacaw_timing_select", "tacaw_timing_get", "tacaw_version", "tacaw_job_latency",
     "tacaw_run_batch", "tacaw_autotune", "tacaw_job_plan",
-    "tacaw_spectral_diffraction", "tacaw_spectrum_image", "tacaw_dispersion",
+    "tacaw_spectral_diffraction", "tacaw_spectrum_image", "tacaw_spectrum_image_noalloc", "tacaw_dispersion",
     "tacaw_job_set_aberrations", "tacaw_mean_diffraction", "tacaw_adf",
     "tacaw_run_frames", "tacaw_finish", "tacaw_get_exit_frames", "tacaw_put_exit_frames",
     "tacaw_average_spectra",
@@ -105,6 +105,7 @@ def lib() -> ctypes.CDLL:
         "tacaw_job_plan": [vp, P(i32), P(i32)],
         "tacaw_spectral_diffraction": [vp, dp, vp, sz, ctypes.c_int],
         "tacaw_spectrum_image": [vp, dp, dp, dp, vp, sz, ctypes.c_int],
+        "tacaw_spectrum_image_noalloc": [vp, dp, dp, dp, vp, sz, ctypes.c_int],
         "tacaw_dispersion": [vp, P(dp), P(dp), i32, vp, sz, ctypes.c_int],
         "tacaw_job_set_aberrations": [vp, P(dp), P(dp)],
         "tacaw_mean_diffraction": [vp, vp, sz, ctypes.c_int],
@@ -334,6 +335,19 @@ class TacawJob:
         _check(lib().tacaw_spectrum_image(self.handle, float(f_THz), float(k_inner), float(k_outer),
                                           out.ctypes.data, out.size, 0))
         return out
+
+    def spectrum_image_noalloc(self, f_THz: float, k_inner: float = 0.0, k_outer: float = 0.0,
+                               out=None) -> np.ndarray:
+        """spectrum_image through the allocation-free entry point; `out` may be
+        a float64 torch tensor on the job's device (one value per probe)."""
+        if out is not None:
+            _check(lib().tacaw_spectrum_image_noalloc(self.handle, float(f_THz), float(k_inner),
+                                                      float(k_outer), out.data_ptr(), out.numel(), 1))
+            return out
+        res = np.empty(self.n_probes, dtype=np.float64)
+        _check(lib().tacaw_spectrum_image_noalloc(self.handle, float(f_THz), float(k_inner), float(k_outer),
+                                                  res.ctypes.data, res.size, 0))
+        return res
 
     def dispersion(self, kx, ky) -> np.ndarray:
         """Sum over probes of I at the grid nodes nearest (kx[i], ky[i]): [n_points, M] float64."""
