@@ -122,11 +122,33 @@ typedef struct {
   int32_t n_atoms;             /* >= 0                                                   */
   int32_t n_species;           /* >= 1                                                   */
   const int32_t* species_Z;    /* n_species atomic numbers (labels only)                 */
-  const double* gauss_a;       /* n_species x 5 form-factor amplitudes [A], > 0          */
-  const double* gauss_b;       /* n_species x 5 form-factor widths [A^2], > 0            */
+  const double* gauss_a;       /* n_species x 5 form-factor amplitudes [A], > 0
+                                  (ignored, may be NULL, with kspace_coef)               */
+  const double* gauss_b;       /* n_species x 5 form-factor widths [A^2], > 0 (ditto)    */
   uint32_t flags;              /* TACAW_TWO_SIDED, TACAW_KEEP_EXIT_WAVES, TACAW_DEFER_ALLOC,
                                   TACAW_USE_GRAPH                                        */
+  const double* kspace_coef;   /* NULL, or n_species x 12 coefficients of the paper's own
+                                  potential route (see below)                            */
 } tacaw_job_desc;
+
+/*
+ * Reciprocal-space potential route (Methods 2.2, "Atomic Scattering
+ * Potentials", the paper's own construction), chosen by a non-NULL
+ * kspace_coef: species s has the form factor
+ *   f_s(q) = sum_{i<3} a_i / (q^2 + b_i) + c_i exp(-d_i q^2)
+ * with kspace_coef[s] = {a1, a2, a3, b1, b2, b3, c1, c2, c3, d1, d2, d3}
+ * (q in cycles/A; a in 1/A, b in 1/A^2 with b > 0, c in A, d in A^2 with
+ * d >= 0; all finite; EINVAL otherwise).  Each slice's potential is
+ *   V(r) = (C / A) sum_k V(k) exp(2 pi i k.r),  V(k) = sum_j f_{Z_j}(|k|)
+ *   exp(-2 pi i k.r_j)
+ * over the atoms of the slice, with k the potential grid's own frequencies
+ * (one period: the potential is band-limited), C = 2 pi a0 e and A = Lx Ly.
+ * A side of even length has an unpaired Nyquist frequency; its term is taken as the
+ * mean of its +k and -k images, which is the real part of the sum.  The
+ * potential grid (pot_nx x pot_ny, or nx x ny) must be one of the compiled
+ * FFT sizes (EUNSUPPORTED otherwise).  The gauss_a / gauss_b form is not
+ * used.
+ */
 
 /* ---- context ------------------------------------------------------------ */
 
@@ -363,11 +385,13 @@ const char* tacaw_last_error(void);
 
 /* Kernel classes timed by the library when timing is on. */
 typedef enum {
-  TACAW_K_SPLAT = 0,      /* projected potentials                      */
+  TACAW_K_SPLAT = 0,      /* projected potentials (real-space sum, or the
+                             structure factors of the reciprocal-space route) */
   TACAW_K_ROW = 1,        /* row pass: iFFT_x, transmission, FFT_x     */
   TACAW_K_COL = 2,        /* column pass: FFT_y, propagator, iFFT_y    */
   TACAW_K_TIME = 3,       /* FP64 mean, time FFT, |.|^2                */
-  TACAW_K_OTHER = 4,      /* tables and incident probes                */
+  TACAW_K_OTHER = 4,      /* tables, incident probes, and the inverse FFT
+                             of the reciprocal-space potentials           */
   TACAW_K_COUNT = 5
 } tacaw_kernel_class;
 

@@ -208,9 +208,11 @@ def kspace_potential(xy: np.ndarray, species: np.ndarray, kirkland: np.ndarray,
     q2 = ky[:, None] ** 2 + kx[None, :] ** 2
     vk = np.zeros((ny, nx), dtype=np.complex128)
     for s in np.unique(species):
-        f = kirkland_form_factor(q2, kirkland[int(s)])
+        # structure factor of the species: sum_j exp(-2 pi i ky y_j) exp(-2 pi i kx x_j)
+        sf = np.zeros((ny, nx), dtype=np.complex128)
         for j in np.nonzero(species == s)[0]:
-            vk += f * np.exp(-2j * math.pi * (kx[None, :] * xy[j, 0] + ky[:, None] * xy[j, 1]))
+            sf += np.outer(np.exp(-2j * math.pi * ky * xy[j, 1]), np.exp(-2j * math.pi * kx * xy[j, 0]))
+        vk += kirkland_form_factor(q2, kirkland[int(s)]) * sf
     # numpy's ifft2 carries 1/(nx ny): (C/A) sum_k = C/(dx dy) ifft2
     return (potential_prefactor() * nx * ny / (lx * ly) * np.fft.ifft2(vk)).real
 

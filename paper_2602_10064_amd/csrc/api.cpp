@@ -51,7 +51,8 @@ void free_job_buffers(tacaw_job* j) {
   void* bufs[] = {j->d_exit,    j->d_spec,   j->d_V,      j->d_pos,     j->d_species,   j->d_tile_start,
                   j->d_tile_atoms, j->d_coef, j->d_tw_x,  j->d_tw_y,    j->d_tw_t,      j->d_px,
                   j->d_py,      j->d_px_last, j->d_py_last, j->d_probe0, j->d_origin,   j->d_rloc,
-                  j->d_count,   j->d_fslice};
+                  j->d_count,   j->d_fslice, j->d_W,    j->d_ks_start, j->d_ks_atoms, j->d_kcoef,
+                  j->d_tw_px,   j->d_tw_py};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   j->d_exit = nullptr;
@@ -69,6 +70,10 @@ void free_job_buffers(tacaw_job* j) {
   j->d_rloc = nullptr;
   j->d_count = nullptr;
   j->d_fslice = nullptr;
+  j->d_W = nullptr;
+  j->d_ks_start = j->d_ks_atoms = nullptr;
+  j->d_kcoef = nullptr;
+  j->d_tw_px = j->d_tw_py = nullptr;
 }
 
 hipEvent_t take_event(tacaw_ctx* c) {
@@ -104,7 +109,8 @@ namespace tacaw {
 // flight per wavefront) and of the column pass (0: half
 // width, 1: full width, 2: register kernel on 8-16 column tiles for 64-512
 // rows, 3: 16-column register tiles for 512 rows, 4: variant 2 with two LDS
-// buffers, 5: six-step kernel for 512 rows, the default there).  Tuned choices win;
+// buffers, 5: six-step kernel for 512 rows, the default there, 6: the six-step
+// kernel on 16-column tiles).  Tuned choices win;
 // $TACAW_ROW_VARIANT and $TACAW_COL_VARIANT override untuned defaults.
 static bool has_register_fft(int n) {
   return n == 64 || n == 128 || n == 256 || n == 384 || n == 512 || n == 768 || n == 1024;
@@ -249,8 +255,66 @@ static tacaw_status slice_passes(tacaw_job* job, hipStream_t s, int f0, int fb, 
 // step k + 2 waits for step k's row pass, the last reader of that buffer.
 // Every side-stream launch is waited on by s, so s alone orders completion
 // (and a capture of s takes in the side stream's work).
+// Potentials of slices g0 .. g0 + gn - 1 of frames [f0, f0 + fb) by the
+// paper's reciprocal-space route: structure factors of the slice pairs into
+// W, an unnormalised inverse 2D FFT of W (column pass, then row pass), whose
+// real and imaginary parts land in V as the pair's two potentials.
+static tacaw_status kspace_potentials(tacaw_job* job, hipStream_t s, int f0, int fb, int g0, int gn) {
+  const HostPlan& hp = job->hp;
+  KPotArgs k{};
+  k.pos = job->d_pos;
+  k.ks_start = job->d_ks_start;
+  k.ks_atoms = job->d_ks_atoms;
+  k.fslice = job->d_fslice;
+  k.kcoef = job->d_kcoef;
+  k.W = job->d_W;
+  k.n_atoms = hp.A;
+  k.n_species = hp.S;
+  k.f0 = f0;
+  k.fb = fb;
+  k.n_slices = hp.ns;
+  k.slice0 = g0;
+  k.npairs = (gn + 1) / 2;
+  k.pnx = hp.pnx;
+  k.pny = hp.pny;
+  k.row_tiles = (hp.pny / 2 + 1 + KP_TY - 1) / KP_TY;
+  k.col_tiles = (hp.pnx + KP_TX - 1) / KP_TX;
+  k.kx_unit = (float)(1.0 / hp.lx);
+  k.ky_unit = (float)(1.0 / hp.ly);
+  tacaw_status st = timed(job, TACAW_K_SPLAT, s, [&] { return launch_kpot(k, s); });
+  if (st != TACAW_OK) return st;
+  PassArgs a{};
+  a.exit = job->d_W;
+  a.tw_x = hp.windowed ? job->d_tw_px : job->d_tw_x;
+  a.tw_y = hp.windowed ? job->d_tw_py : job->d_tw_y;
+  a.nx = a.pnx = hp.pnx;
+  a.ny = a.pny = hp.pny;
+  a.n_probes = 1;
+  a.n_frames = a.fb = fb * k.npairs;
+  a.f0 = 0;
+  a.plane = 1;
+  st = timed(job, TACAW_K_OTHER, s, [&] { return launch_col_pass(a, COL_INVERSE_ONLY, s); });
+  if (st != TACAW_OK) return st;
+  a.vout = job->d_V;
+  return timed(job, TACAW_K_OTHER, s, [&] { return launch_row_pass(a, ROW_INVERSE_ONLY, s); });
+}
+
 tacaw_status run_batch_range(tacaw_job* job, hipStream_t s, int f_begin, int f_end) {
   const HostPlan& hp = job->hp;
+  if (hp.kspace) {
+    const int G = hp.kgroup;
+    for (int f0 = f_begin; f0 < f_end; f0 += hp.fb) {
+      const int fb = std::min(hp.fb, f_end - f0);
+      for (int g0 = 0; g0 < hp.ns; g0 += G) {
+        const int gn = std::min(G, hp.ns - g0);
+        tacaw_status st = kspace_potentials(job, s, f0, fb, g0, gn);
+        if (st != TACAW_OK) return st;
+        for (int sl = g0; sl < g0 + gn; ++sl)
+          if ((st = slice_passes(job, s, f0, fb, sl, job->d_V, 2 * ((gn + 1) / 2), g0)) != TACAW_OK) return st;
+      }
+    }
+    return TACAW_OK;
+  }
   if (!hp.overlap) {
     // serial form: potentials of hp.splat_group slices (all slices when not
     // per slice), then their row and column passes
@@ -357,7 +421,18 @@ tacaw_status materialize(tacaw_job* j, hipStream_t s0) {
   if ((e = dalloc(&(ptr), (count))) != hipSuccess) return fail("hipMalloc " #ptr, e);
   if (!j->d_exit) ALLOC(j->d_exit, (size_t)hp.P * hp.F * nk);
   if (!j->d_spec) ALLOC(j->d_spec, (size_t)hp.P * hp.M * nk);
-  ALLOC(j->d_V, (size_t)hp.fb * (hp.overlap ? 2 : hp.splat_group) * hp.pnx * hp.pny);
+  const int kpairs = (hp.kgroup + 1) / 2;
+  ALLOC(j->d_V, (size_t)hp.fb * (hp.kspace ? 2 * kpairs : hp.overlap ? 2 : hp.splat_group) * hp.pnx * hp.pny);
+  if (hp.kspace) {
+    ALLOC(j->d_W, (size_t)hp.fb * kpairs * hp.pnx * hp.pny);
+    ALLOC(j->d_ks_start, hp.ks_start.size());
+    ALLOC(j->d_ks_atoms, hp.ks_atoms.size());
+    ALLOC(j->d_kcoef, hp.kcoef.size());
+    if (hp.windowed) {
+      ALLOC(j->d_tw_px, (size_t)hp.pnx);
+      ALLOC(j->d_tw_py, (size_t)hp.pny);
+    }
+  }
   ALLOC(j->d_pos, (size_t)hp.F * hp.A);
   ALLOC(j->d_species, (size_t)hp.A);
   if (hp.instant_z) ALLOC(j->d_fslice, hp.fslice.size());
@@ -405,6 +480,22 @@ tacaw_status materialize(tacaw_job* j, hipStream_t s0) {
   if ((e = hipMemcpyAsync(j->d_coef, hp.coef.data(), hp.coef.size() * sizeof(float), hipMemcpyHostToDevice, s0)) !=
       hipSuccess)
     return fail("upload coefficients", e);
+  if (hp.kspace) {
+    if ((e = hipMemcpyAsync(j->d_ks_start, hp.ks_start.data(), hp.ks_start.size() * sizeof(int32_t),
+                            hipMemcpyHostToDevice, s0)) != hipSuccess)
+      return fail("upload structure-factor lists", e);
+    if (!hp.ks_atoms.empty() &&
+        (e = hipMemcpyAsync(j->d_ks_atoms, hp.ks_atoms.data(), hp.ks_atoms.size() * sizeof(int32_t),
+                            hipMemcpyHostToDevice, s0)) != hipSuccess)
+      return fail("upload structure-factor lists", e);
+    if ((e = hipMemcpyAsync(j->d_kcoef, hp.kcoef.data(), hp.kcoef.size() * sizeof(float), hipMemcpyHostToDevice,
+                            s0)) != hipSuccess)
+      return fail("upload form-factor coefficients", e);
+    if (hp.windowed) {
+      if ((e = launch_twiddles(j->d_tw_px, hp.pnx, s0)) != hipSuccess) return fail("twiddles", e);
+      if ((e = launch_twiddles(j->d_tw_py, hp.pny, s0)) != hipSuccess) return fail("twiddles", e);
+    }
+  }
   if ((e = hipMemcpyAsync(j->d_origin, hp.origin.data(), hp.origin.size() * sizeof(int32_t), hipMemcpyHostToDevice, s0)) !=
       hipSuccess)
     return fail("upload origins", e);
@@ -535,12 +626,16 @@ tacaw_status tacaw_job_create(tacaw_ctx* ctx, const tacaw_job_desc* d, const int
   const bool plane = d->aperture_mrad == 0.0;
   if (!plane) j->probe_xy.assign(d->probe_xy, d->probe_xy + 2 * (size_t)d->n_probes);
   j->species_Z.assign(d->species_Z, d->species_Z + d->n_species);
-  j->gauss_a.assign(d->gauss_a, d->gauss_a + (size_t)d->n_species * TACAW_N_GAUSS);
-  j->gauss_b.assign(d->gauss_b, d->gauss_b + (size_t)d->n_species * TACAW_N_GAUSS);
+  if (d->gauss_a && d->gauss_b) {
+    j->gauss_a.assign(d->gauss_a, d->gauss_a + (size_t)d->n_species * TACAW_N_GAUSS);
+    j->gauss_b.assign(d->gauss_b, d->gauss_b + (size_t)d->n_species * TACAW_N_GAUSS);
+  }
+  if (d->kspace_coef) j->kspace_coef.assign(d->kspace_coef, d->kspace_coef + (size_t)d->n_species * 12);
   j->desc.probe_xy = plane ? nullptr : j->probe_xy.data();
   j->desc.species_Z = j->species_Z.data();
-  j->desc.gauss_a = j->gauss_a.data();
-  j->desc.gauss_b = j->gauss_b.data();
+  j->desc.gauss_a = j->gauss_a.empty() ? nullptr : j->gauss_a.data();
+  j->desc.gauss_b = j->gauss_b.empty() ? nullptr : j->gauss_b.data();
+  j->desc.kspace_coef = j->kspace_coef.empty() ? nullptr : j->kspace_coef.data();
   if (plane) j->desc.n_probes = 1;
 
   static const double no_pos[1] = {0.0};
@@ -550,7 +645,7 @@ tacaw_status tacaw_job_create(tacaw_ctx* ctx, const tacaw_job_desc* d, const int
     delete j;
     return st;
   }
-  j->fp = footprint_of(&j->desc, j->hp.fb, j->hp.tile_atoms.size());
+  j->fp = footprint_of(&j->desc, j->hp.fb, j->hp.kspace ? j->hp.ks_atoms.size() : j->hp.tile_atoms.size());
   // deferred jobs are checked against the budget when submitted
   if (!(d->flags & TACAW_DEFER_ALLOC) && j->fp.total() > ctx->budget) {
     set_error("job needs %.3f GiB of device memory, above the context budget of %.3f GiB",

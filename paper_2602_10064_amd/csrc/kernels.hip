@@ -376,6 +376,232 @@ __global__ void __launch_bounds__(256) k_splat(SplatTable tab) {
 }
 
 // ---------------------------------------------------------------------------
+// The paper's reciprocal-space potential route: structure factors of a pair
+// of slices on the MFMA units
+// ---------------------------------------------------------------------------
+// exp(-2 pi i m x / n) at x = ip + fp pixels (0 <= ip < n, 0 <= fp < 1):
+// the integer part of m x is reduced exactly, the rest in FP32 revolutions.
+// nyq: m is the Nyquist index -n/2 of an even side, which takes the cosine
+// alone (the mean of the +n/2 and -n/2 terms).
+__device__ __forceinline__ float2 sf_term(int m, int ip, float fp, int n, float inv_n, bool nyq) {
+  const int t = (m * ip) % n;   // |m ip| < 2^21
+  float rev = ((float)t + (float)m * fp) * inv_n;
+  rev -= rintf(rev);
+  const float c = __builtin_amdgcn_cosf(rev);
+  return make_float2(c, nyq ? 0.f : -__builtin_amdgcn_sinf(rev));
+}
+
+// signed frequency index of grid index i (numpy fftfreq order)
+__device__ __forceinline__ int freq_index(int i, int n) { return i < (n + 1) / 2 ? i : i - n; }
+
+// sum_i a_i / (q2 + b_i) + c_i 2^(-d_i q2) for one species' coefficients
+__device__ __forceinline__ float kform(const float* cf, float q2) {
+  float ff = 0.f;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    ff += cf[i] * __builtin_amdgcn_rcpf(q2 + cf[3 + i]) + cf[6 + i] * __builtin_amdgcn_exp2f(-cf[9 + i] * q2);
+  return ff;
+}
+
+// At the corner frequency where both sides are even and both indices are
+// Nyquist, the real part of f exp(-2 pi i (mx x / Lx + my y / Ly)) is
+// f (cos a cos b - sin a sin b), while the per-axis cosines give the first
+// product only.  Returns sum over the slice's atoms of f_z sin a sin b, to be
+// subtracted there.
+__device__ float corner_sin_sum(const KPotArgs& a, int f, int s, float q2c) {
+  const int mx = -(a.pnx / 2), my = -(a.pny / 2);
+  const float inv_nx = 1.f / (float)a.pnx, inv_ny = 1.f / (float)a.pny;
+  float acc = 0.f;
+  for (int z = 0; z < a.n_species; ++z) {
+    const int js = a.ks_start[s * a.n_species + z], je = a.ks_start[s * a.n_species + z + 1];
+    float sz = 0.f;
+    for (int c = js; c < je; ++c) {
+      const size_t o = (size_t)f * a.n_atoms + a.ks_atoms[c];
+      if (a.fslice != nullptr && a.fslice[o] != s) continue;
+      const AtomPos p = a.pos[o];
+      float rx = ((float)((mx * p.ix) % a.pnx) + (float)mx * p.fx) * inv_nx;
+      float ry = ((float)((my * p.iy) % a.pny) + (float)my * p.fy) * inv_ny;
+      rx -= rintf(rx);
+      ry -= rintf(ry);
+      sz += __builtin_amdgcn_sinf(rx) * __builtin_amdgcn_sinf(ry);
+    }
+    if (je > js) acc += kform(a.kcoef + z * KP_NCOEF, q2c) * sz;
+  }
+  return acc;
+}
+
+// One workgroup computes a KP_TY x KP_TX tile (rows ky index r0 .., columns
+// kx index c0 ..) of W for one frame and one slice pair.  For each slice and
+// species, the tile's structure factor S(k) = sum_j Ey_j(ky) Ex_j(kx) is a
+// complex product of a [rows x atoms] and an [atoms x columns] matrix, taken
+// KP_K atoms at a time: the workgroup writes the stage's exponentials to LDS
+// (real and imaginary planes, [row or column][atom]), then each wavefront
+// runs v_mfma_f32_16x16x4f32 on its 32 x 32 part (four 16 x 16 blocks, real
+// part = Re Re - Im Im, imaginary part = Re Im + Im Re).  The species' form
+// factor multiplies the finished sum element by element.  Atoms are taken in
+// list order and the instruction sequence is fixed, so results are
+// deterministic.
+__global__ void __launch_bounds__(256) k_kpot(KPotArgs a) {
+  constexpr int PS = KP_K + 1;   // LDS row stride (floats)
+  __shared__ float eyr[KP_TY][PS], eyi[KP_TY][PS];
+  __shared__ float exr[KP_TX][PS], exi[KP_TX][PS];
+  typedef float v4f __attribute__((ext_vector_type(4)));
+  static_assert(KP_TY == 32 && KP_TX == 128 && KP_K == 16, "tile shape of the MFMA layout below");
+
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+  int b = blockIdx.x;
+  const int ct = b % a.col_tiles;
+  b /= a.col_tiles;
+  const int rt = b % a.row_tiles;
+  b /= a.row_tiles;
+  const int q = b % a.npairs;
+  const int fl = b / a.npairs;
+  const int f = a.f0 + fl;
+  const int r0 = rt * KP_TY, c0 = ct * KP_TX;
+  const int half_rows = a.pny / 2 + 1;   // rows 0 .. pny/2 computed here
+  const float inv_nx = 1.f / (float)a.pnx, inv_ny = 1.f / (float)a.pny;
+  const bool even_x = (a.pnx & 1) == 0, even_y = (a.pny & 1) == 0;
+
+  // exponential slots of this thread: atom gj of the stage; rows gr + 16 i
+  // (i < 2) and columns gr + 16 i (i < 8) of the tile
+  const int gj = tid % KP_K, gr = tid / KP_K;
+  int my[2], mx[8];
+  bool ok_y[2], ok_x[8], nyq_y[2], nyq_x[8];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int row = r0 + gr + 16 * i;
+    ok_y[i] = row < half_rows;
+    my[i] = freq_index(row, a.pny);
+    nyq_y[i] = even_y && 2 * row == a.pny;
+  }
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int col = c0 + gr + 16 * i;
+    ok_x[i] = col < a.pnx;
+    mx[i] = freq_index(col, a.pnx);
+    nyq_x[i] = even_x && 2 * col == a.pnx;
+  }
+
+  // |k|^2 of the 16 output elements of this lane: block u (rows 16 (u >> 1),
+  // columns 32 wave + 16 (u & 1)), element e at row 4 (lane / 16) + e of the
+  // block, column lane % 16
+  float q2[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int col = c0 + 32 * wave + 16 * (u & 1) + lane % 16;
+    const float kx = (float)freq_index(col, a.pnx) * a.kx_unit;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int row = r0 + 16 * (u >> 1) + 4 * (lane / 16) + e;
+      const float ky = (float)freq_index(row, a.pny) * a.ky_unit;
+      q2[u][e] = kx * kx + ky * ky;
+    }
+  }
+
+  v4f vs[2][4][2];   // [slice of the pair][block][re, im]
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) vs[h][u][0] = vs[h][u][1] = v4f{0.f, 0.f, 0.f, 0.f};
+
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int s = a.slice0 + 2 * q + h;
+    if (s >= a.n_slices) break;   // the last pair of an odd count has one slice
+    for (int z = 0; z < a.n_species; ++z) {
+      const int js = a.ks_start[s * a.n_species + z], je = a.ks_start[s * a.n_species + z + 1];
+      if (js == je) continue;
+      v4f acc[4][2];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u][0] = acc[u][1] = v4f{0.f, 0.f, 0.f, 0.f};
+      for (int c = js; c < je; c += KP_K) {
+        bool on = gj < je - c;
+        AtomPos p{};
+        if (on) {
+          const int at = a.ks_atoms[c + gj];
+          const size_t o = (size_t)f * a.n_atoms + at;
+          p = a.pos[o];
+          if (a.fslice != nullptr && a.fslice[o] != s) on = false;   // elsewhere in this frame
+        }
+        __syncthreads();   // the previous stage's operand reads are done
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          float2 e = make_float2(0.f, 0.f);
+          if (on && ok_y[i]) e = sf_term(my[i], p.iy, p.fy, a.pny, inv_ny, nyq_y[i]);
+          eyr[gr + 16 * i][gj] = e.x;
+          eyi[gr + 16 * i][gj] = e.y;
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          float2 e = make_float2(0.f, 0.f);
+          if (on && ok_x[i]) e = sf_term(mx[i], p.ix, p.fx, a.pnx, inv_nx, nyq_x[i]);
+          exr[gr + 16 * i][gj] = e.x;
+          exi[gr + 16 * i][gj] = e.y;
+        }
+        __syncthreads();
+        // A is 16 x 4 (row lane % 16, atom lane / 16), B is 4 x 16 (atom lane / 16,
+        // column lane % 16); unused atom slots hold zeros
+        const int kn = min(KP_K, ((je - c) + 3) & ~3);
+        for (int k0 = 0; k0 < kn; k0 += 4) {
+          const int kk = k0 + lane / 16;
+          float ar[2], ai[2], br[2], bi[2];
+#pragma unroll
+          for (int v = 0; v < 2; ++v) {
+            ar[v] = eyr[16 * v + lane % 16][kk];
+            ai[v] = eyi[16 * v + lane % 16][kk];
+            br[v] = exr[32 * wave + 16 * v + lane % 16][kk];
+            bi[v] = exi[32 * wave + 16 * v + lane % 16][kk];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int ry = u >> 1, cx = u & 1;
+            acc[u][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[ry], br[cx], acc[u][0], 0, 0, 0);
+            acc[u][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai[ry], bi[cx], acc[u][0], 0, 0, 0);
+            acc[u][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[ry], bi[cx], acc[u][1], 0, 0, 0);
+            acc[u][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[ry], br[cx], acc[u][1], 0, 0, 0);
+          }
+        }
+      }
+      // V(k) += f_z(|k|) S_z(k): f = sum_i a_i / (q^2 + b_i) + c_i 2^(-d_i q^2)
+      // (a, c carry C / A and d carries log2 e)
+      const float* cf = a.kcoef + z * KP_NCOEF;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const float ff = kform(cf, q2[u][e]);
+          vs[h][u][0][e] = fmaf(ff, acc[u][0][e], vs[h][u][0][e]);
+          vs[h][u][1][e] = fmaf(ff, acc[u][1][e], vs[h][u][1][e]);
+        }
+    }
+  }
+
+  // W(k) = A + i B and W(-k) = conj A + i conj B (A, B: the pair's slices)
+  float2* out = a.W + ((size_t)fl * a.npairs + q) * (size_t)a.pnx * a.pny;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int col = c0 + 32 * wave + 16 * (u & 1) + lane % 16;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int row = r0 + 16 * (u >> 1) + 4 * (lane / 16) + e;
+      if (row >= half_rows || col >= a.pnx) continue;
+      float are = vs[0][u][0][e], bre = vs[1][u][0][e];
+      const float aim = vs[0][u][1][e], bim = vs[1][u][1][e];
+      if (even_x && even_y && 2 * row == a.pny && 2 * col == a.pnx) {   // the corner (both Nyquist)
+        const int s = a.slice0 + 2 * q;
+        are -= corner_sin_sum(a, f, s, q2[u][e]);
+        if (s + 1 < a.n_slices) bre -= corner_sin_sum(a, f, s + 1, q2[u][e]);
+      }
+      out[(size_t)row * a.pnx + col] = make_float2(are - bim, aim + bre);
+      if (row > 0 && 2 * row < a.pny) {
+        const int mrow = a.pny - row, mcol = col == 0 ? 0 : a.pnx - col;
+        out[(size_t)mrow * a.pnx + mcol] = make_float2(are + bim, bre - aim);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Row pass: [iFFT_x] -> * exp(i sigma V) -> FFT_x for RPI rows per block
 // ---------------------------------------------------------------------------
 template <int N, int VAR>
@@ -439,8 +665,19 @@ __global__ void __launch_bounds__((RowCfg<N, VAR>::THREADS)) k_row(PassTable tab
   __syncthreads();
   if (mode != ROW_FIRST) StagesIP<N, G, true, 1, typename PL::R>::run(buf, tw, t);
   if (mode == ROW_INVERSE_ONLY) {
-    if (active)
+    if (active && a.vout) {
+      // two real planes (reciprocal-space potentials): real part, imaginary part
+      const size_t plane = (size_t)a.ny * N;
+      const size_t w = (size_t)p * a.n_frames + a.f0 + fl;
+      float* o0 = a.vout + 2 * w * plane + (size_t)y * N;
+      float* o1 = o0 + plane;
+      for (int x = t; x < N; x += G) {
+        o0[x] = buf[x].x;
+        o1[x] = buf[x].y;
+      }
+    } else if (active) {
       for (int x = t; x < N; x += G) row[x] = buf[x];
+    }
     return;
   }
   if (active) {
@@ -1019,6 +1256,135 @@ __global__ void __launch_bounds__(512) k_col_6s(PassTable tab, int total_tiles) 
     dft8<true>(x);
 #pragma unroll
     for (int j = 0; j < 8; ++j) cur_wp[(size_t)(r0 + 64 * j) * nx + cur_x0 + ca] = x[j];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The same six-step column transform on tiles of 16 columns, so that every
+// load and store instruction of a wavefront covers whole 128-byte row
+// segments (4 rows x 16 columns), with 512 threads and 68 KiB of LDS per
+// workgroup: two workgroups fit one CU.  A lane holds two columns' or two
+// rows' worth of the 8-column kernel's values:
+//   layout A: column c = lane % 16, ra = 4 wave + lane / 16; rows
+//             r0 = ra + 32 h (h < 2), values at rows r0 + 64 j;
+//   layout B: k1 = wave, columns cb + 8 h (cb = lane / 8), u = lane % 8,
+//             values at r0 = u + 8 q.
+// LDS slots of the exchanges across wavefronts: 1024 k1 + 512 (c / 8) +
+// 8 (r0 ^ (c / 8)) + ((c % 8) ^ (r0 % 8)), so columns 8 h .. 8 h + 7 fill one
+// half of wavefront k1's 1024 slots.  The local exchanges of column cb + 8 h
+// use 64 slots of that half, 512 h + 64 cb + 8 (u ^ (cb % 2)) + (k2 ^ u): a
+// half is only overwritten after this wavefront has read all of it.  Every
+// 16-lane group of an access hits 16 distinct 8-byte slots modulo 16
+// (checked by enumeration).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k_col_6w(PassTable tab, int total_tiles) {
+  constexpr int N = 512, CT = 16;
+  __shared__ float2 xs[8192];
+  __shared__ float2 twl[N];   // W512^m, for the layout-A twiddles
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int ca = lane & 15, ra = 4 * wave + (lane >> 4);   // layout A
+  const int k1 = wave, cb = lane >> 3, u = lane & 7;       // layout B
+  const int sa0 = 512 * (ca >> 3) + 8 * (ra ^ (ca >> 3)) + ((ca & 7) ^ (ra & 7));   // + 1024 k1 + 256 h
+  float2* lw0 = xs + 1024 * k1 + 64 * cb;                  // local regions of columns cb, cb + 8
+  float2* lw1 = lw0 + 512;
+  const int lodd = cb & 1;
+  // slot of (k1, r0 = u + 8 q, column cb + 8 h): 1024 k1 + 512 h + 8 (u ^ h) + 64 q + (cb ^ u)
+  const int sb0 = 1024 * k1 + 8 * u + (cb ^ u);
+  const int sb1 = 1024 * k1 + 512 + 8 * (u ^ 1) + (cb ^ u);
+  float2 tb[8];   // layout-B twiddles, entries 1..7; layout A reads W512^(r0 k) from twl
+  {
+    const float2* tw = tab.l[0].a.tw_y;
+#pragma unroll
+    for (int k = 1; k < 8; ++k) tb[k] = tw[(8 * u * k) & (N - 1)];
+    for (int i = threadIdx.x; i < N; i += blockDim.x) twl[i] = tw[i];
+  }
+  auto locate = [&](int it, int& L, int& x0, float2*& wp) {
+    const int tile_g = xcd_remap(it, total_tiles);
+    L = find_lane(tab, tile_g);
+    const PassArgs& a = tab.l[L].a;
+    const int tile = tile_g - tab.l[L].block_start;
+    const int tiles_per_wave = a.nx / CT;
+    const int w = tile / tiles_per_wave;
+    x0 = (tile % tiles_per_wave) * CT;
+    const int p = w / a.fb;
+    const int fl = w % a.fb;
+    wp = a.exit + ((size_t)p * a.n_frames + a.f0 + fl) * (size_t)N * a.nx;
+  };
+  // the two rows (layout A) or columns (layout B) of a lane go one after the
+  // other, so that only 8 values per lane are live at a time
+  for (int it = blockIdx.x; it < total_tiles; it += gridDim.x) {
+    int L = 0, x0 = 0;
+    float2* wp = nullptr;
+    locate(it, L, x0, wp);
+    const PassArgs& a = tab.l[L].a;
+    const int mode = tab.l[L].mode;
+    const int nx = a.nx;
+    float2 x[8];
+    __syncthreads();   // the previous tile's reads of the exchange buffer are done
+    // layout A: 8-point transform over j, twiddle, to LDS
+#pragma unroll 1
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) x[j] = wp[(size_t)(ra + 32 * h + 64 * j) * nx + x0 + ca];
+      dft8<false>(x);
+#pragma unroll
+      for (int k = 1; k < 8; ++k) x[k] = cmul(x[k], twl[((ra + 32 * h) * k) & (N - 1)]);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) xs[1024 * k + 256 * h + sa0] = x[k];
+    }
+    __syncthreads();
+    // layout B, one column at a time: 8-point transform over q, twiddle,
+    // local exchange, over u; propagator; and back
+    const bool last = mode == COL_LAST;
+#pragma unroll 1
+    for (int h = 0; h < 2; ++h) {
+      const int sb = h ? sb1 : sb0;
+      float2* lw = h ? lw1 : lw0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) x[q] = xs[sb + 64 * q];
+      dft8<false>(x);
+#pragma unroll
+      for (int k = 1; k < 8; ++k) x[k] = cmul(x[k], tb[k]);
+      wave_lds_sync();
+#pragma unroll
+      for (int k = 0; k < 8; ++k) lw[8 * (u ^ lodd) + (k ^ u)] = x[k];
+      wave_lds_sync();
+#pragma unroll
+      for (int v = 0; v < 8; ++v) x[v] = lw[8 * (v ^ lodd) + (u ^ v)];
+      dft8<false>(x);   // x[k3] = psi(k1 + 8 u + 64 k3) of column x0 + cb + 8 h
+      const float2 pxv = a.px[x0 + cb + 8 * h];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) x[k] = cmul(x[k], cmul(pxv, a.py[k1 + 8 * u + 64 * k]));
+      if (last) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) wp[(size_t)(k1 + 8 * u + 64 * k) * nx + x0 + cb + 8 * h] = x[k];
+        continue;
+      }
+      dft8<true>(x);    // over k3: x[v] at u-index v, this lane's k2 = u
+      wave_lds_sync();
+#pragma unroll
+      for (int v = 0; v < 8; ++v) lw[8 * (v ^ lodd) + (u ^ v)] = x[v];
+      wave_lds_sync();
+      x[0] = lw[8 * (u ^ lodd) + u];
+#pragma unroll
+      for (int k = 1; k < 8; ++k) x[k] = cmulc(lw[8 * (u ^ lodd) + (k ^ u)], tb[k]);
+      dft8<true>(x);    // over k2: x[q] at r0 = u + 8 q
+      wave_lds_sync();  // this wavefront's reads of the local region are done
+#pragma unroll
+      for (int q = 0; q < 8; ++q) xs[sb + 64 * q] = x[q];
+    }
+    if (last) continue;
+    __syncthreads();
+    // layout A: conjugate twiddle, 8-point transform over k1, store
+#pragma unroll 1
+    for (int h = 0; h < 2; ++h) {
+      x[0] = xs[256 * h + sa0];
+#pragma unroll
+      for (int k = 1; k < 8; ++k) x[k] = cmulc(xs[1024 * k + 256 * h + sa0], twl[((ra + 32 * h) * k) & (N - 1)]);
+      dft8<true>(x);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) wp[(size_t)(ra + 32 * h + 64 * j) * nx + x0 + ca] = x[j];
+    }
   }
 }
 
@@ -1679,11 +2045,35 @@ static hipError_t col_6s_launch(PassTable& t, hipStream_t s) {
   return hipGetLastError();
 }
 
+static hipError_t col_6w_launch(PassTable& t, hipStream_t s) {
+  int tiles = 0;
+  for (int i = 0; i < t.n; ++i) {
+    const PassArgs& a = t.l[i].a;
+    if (a.ny != 512 || a.nx % 16 != 0) return hipErrorInvalidValue;
+    t.l[i].block_start = tiles;
+    tiles += a.n_probes * a.fb * (a.nx / 16);
+  }
+  // grid stride over the tiles; TACAW_COL_GRID caps the grid (default 512:
+  // the two resident workgroups per CU)
+  const char* ge = getenv("TACAW_COL_GRID");
+  const int cap = ge && atoi(ge) > 0 ? atoi(ge) : 512;
+  const int grid = std::min(tiles, cap);
+  TACAW_LAUNCH(k_col_6w, dim3(grid), dim3(512), 0, s, t, tiles);
+  return hipGetLastError();
+}
+
 hipError_t launch_col_lanes(const PassLane* lanes, int n, int variant, hipStream_t s) {
   if (n < 1 || n > MAX_LANES || !same_grid(lanes, n)) return hipErrorInvalidValue;
   PassTable t{};
   t.n = n;
   for (int i = 0; i < n; ++i) t.l[i] = lanes[i];
+  if (variant == 6) {
+    // six-step kernel on 16-column tiles: ny = 512, regular and last-slice modes
+    bool ok = lanes[0].a.ny == 512 && lanes[0].a.nx % 16 == 0;
+    for (int i = 0; i < n; ++i) ok = ok && lanes[i].mode != COL_INVERSE_ONLY;
+    if (ok) return col_6w_launch(t, s);
+    variant = 5;
+  }
   if (variant == 5) {
     // six-step kernel: ny = 512, regular and last-slice modes
     bool ok = lanes[0].a.ny == 512 && lanes[0].a.nx % 8 == 0;
@@ -1817,6 +2207,13 @@ hipError_t launch_time_stage(const TimeArgs& a, hipStream_t s) {
   const long blocks = (long)a.n_probes * (a.n_k / a.kt);
   dim3 grid((unsigned)blocks), block(a.kt * TIME_G);
   TACAW_LAUNCH(k_time, grid, block, lds, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_kpot(const KPotArgs& a, hipStream_t s) {
+  const long blocks = (long)a.fb * a.npairs * a.row_tiles * a.col_tiles;
+  if (blocks <= 0 || blocks >= (1L << 31) || a.pnx > 4096 || a.pny > 4096) return hipErrorInvalidValue;
+  TACAW_LAUNCH(k_kpot, dim3((unsigned)blocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

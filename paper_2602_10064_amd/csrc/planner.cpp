@@ -96,16 +96,29 @@ tacaw_status validate_desc(const tacaw_job_desc* d) {
     set_error("n_atoms must be >= 0");
     return TACAW_EINVAL;
   }
-  if (d->n_species < 1 || !d->gauss_a || !d->gauss_b || !d->species_Z) {
-    set_error("need n_species >= 1 with species_Z, gauss_a and gauss_b");
+  const bool kspace = d->kspace_coef != nullptr;
+  if (d->n_species < 1 || !d->species_Z || (!kspace && (!d->gauss_a || !d->gauss_b))) {
+    set_error("need n_species >= 1 with species_Z, and gauss_a and gauss_b unless kspace_coef is given");
     return TACAW_EINVAL;
   }
-  for (int i = 0; i < d->n_species * TACAW_N_GAUSS; ++i)
-    if (!(d->gauss_a[i] > 0.0) || !(d->gauss_b[i] > 0.0) || !isfinite(d->gauss_a[i]) ||
-        !isfinite(d->gauss_b[i])) {
-      set_error("gauss_a and gauss_b must be positive and finite (entry %d)", i);
-      return TACAW_EINVAL;
-    }
+  if (kspace) {
+    for (int s = 0; s < d->n_species; ++s)
+      for (int i = 0; i < 12; ++i) {
+        const double v = d->kspace_coef[s * 12 + i];
+        const bool bad = !isfinite(v) || (i >= 3 && i < 6 && !(v > 0.0)) || (i >= 9 && !(v >= 0.0));
+        if (bad) {
+          set_error("kspace_coef[%d][%d] = %g: need finite values, b > 0 and d >= 0", s, i, v);
+          return TACAW_EINVAL;
+        }
+      }
+  } else {
+    for (int i = 0; i < d->n_species * TACAW_N_GAUSS; ++i)
+      if (!(d->gauss_a[i] > 0.0) || !(d->gauss_b[i] > 0.0) || !isfinite(d->gauss_a[i]) ||
+          !isfinite(d->gauss_b[i])) {
+        set_error("gauss_a and gauss_b must be positive and finite (entry %d)", i);
+        return TACAW_EINVAL;
+      }
+  }
   if (d->aperture_mrad < 0.0 || !isfinite(d->aperture_mrad)) {
     set_error("aperture_mrad must be >= 0");
     return TACAW_EINVAL;
@@ -153,6 +166,12 @@ tacaw_status validate_desc(const tacaw_job_desc* d) {
               d->nx, d->ny);
     return TACAW_EUNSUPPORTED;
   }
+  if (kspace && (!grid_supported(pnx) || !grid_supported(pny))) {
+    set_error("the reciprocal-space potential transforms the %dx%d potential grid: each side must be one of "
+              "16, 32, 48, 64, 96, 128, 160, 192, 256, 320, 384, 512, 640, 768, 1024",
+              pnx, pny);
+    return TACAW_EUNSUPPORTED;
+  }
   return TACAW_OK;
 }
 
@@ -193,6 +212,19 @@ int splat_group(int n_slices, int fb, int pnx, int pny) {
   return std::max(1, std::min(n_slices, (int)(cap / per_slice)));
 }
 
+// Slices per structure-factor launch of the reciprocal-space route: all
+// slices of a frame batch while their potentials (4 B per point) and slice-pair
+// structure factors (8 B per point per pair) stay within TACAW_V_MB (default
+// 4096 MiB), else the largest even group that fits (at least 2).
+int kspace_group(int n_slices, int fb, int pnx, int pny) {
+  double cap = 4096.0 * (1 << 20);
+  if (const char* e = getenv("TACAW_V_MB")) cap = atof(e) * (1 << 20);
+  const double per_slice = (double)fb * pnx * pny * 8.0;   // V (4 B) + half a pair's W (4 B)
+  int g = (int)std::min<double>(n_slices, std::max(2.0, floor(cap / per_slice)));
+  if (g < n_slices && (g & 1)) --g;
+  return std::max(1, g);
+}
+
 // Frames per batch: the waves and one slice of potentials of one batch should
 // stay within ~240 MiB, so that between the row and column passes of a slice
 // they can live in the 256 MiB last-level cache (at 512^2, 80-frame batches
@@ -223,111 +255,63 @@ Footprint footprint_of(const tacaw_job_desc* d, int fb, size_t n_tile_atoms) {
   const size_t M = (d->flags & TACAW_TWO_SIDED) ? d->n_frames : d->n_frames / 2;
   f.exit = P * d->n_frames * nk * sizeof(float2);
   f.spec = P * M * nk * sizeof(float);
-  f.V = (size_t)fb * (overlap_splat() ? 2 : splat_group(d->n_slices, fb, pnx, pny)) * pnx * pny * sizeof(float);
+  if (d->kspace_coef) {
+    const int g = kspace_group(d->n_slices, fb, pnx, pny);
+    const size_t pairs = (size_t)(g + 1) / 2;
+    f.V = (size_t)fb * 2 * pairs * pnx * pny * sizeof(float);
+    f.W = (size_t)fb * pairs * pnx * pny * sizeof(float2);
+  } else {
+    f.V = (size_t)fb * (overlap_splat() ? 2 : splat_group(d->n_slices, fb, pnx, pny)) * pnx * pny * sizeof(float);
+  }
   f.pos = (size_t)d->n_frames * d->n_atoms * sizeof(AtomPos) + (size_t)d->n_atoms * sizeof(int32_t);
   if (d->flags & TACAW_SLICE_BY_INSTANT_Z) f.pos += (size_t)d->n_frames * d->n_atoms * sizeof(int16_t);
   f.tiles = n_tile_atoms * sizeof(int32_t);
   f.probes = plane ? 0 : P * nk * sizeof(float2) + P * (2 * sizeof(int32_t) + 2 * sizeof(double));
   f.tables = (size_t)(2 * d->nx + 2 * d->ny + d->nx + d->ny + d->n_frames) * sizeof(float2) +
              (size_t)d->n_species * N_GAUSS * COEF_STRIDE * sizeof(float) + 64;
+  if (d->kspace_coef)
+    f.tables += (size_t)(pnx + pny) * sizeof(float2) + (size_t)d->n_species * KP_NCOEF * sizeof(float) +
+                ((size_t)d->n_slices * d->n_species + 1) * sizeof(int32_t);
   return f;
 }
 
 static inline double wrap_min_image(double d, double L) { return d - L * nearbyint(d / L); }
 
-tacaw_status plan_job(const tacaw_job_desc* d, const int32_t* atom_species, const double* pos,
-                      HostPlan& hp) {
-  hp.nx = d->nx;
-  hp.ny = d->ny;
-  hp.pnx = d->pot_nx > 0 ? d->pot_nx : d->nx;
-  hp.pny = d->pot_ny > 0 ? d->pot_ny : d->ny;
-  hp.ns = d->n_slices;
-  hp.F = d->n_frames;
-  hp.A = d->n_atoms;
-  hp.S = d->n_species;
-  hp.plane = d->aperture_mrad == 0.0;
-  hp.P = hp.plane ? 1 : d->n_probes;
-  hp.windowed = hp.pnx != hp.nx || hp.pny != hp.ny;
-  hp.two_sided = (d->flags & TACAW_TWO_SIDED) != 0;
-  hp.M = hp.two_sided ? hp.F : hp.F / 2;
-  hp.lx = d->cell[0];
-  hp.ly = d->cell[1];
-  hp.lz = d->cell[2];
-  hp.dx = hp.lx / hp.pnx;
-  hp.dy = hp.ly / hp.pny;
-  hp.dz = hp.lz / hp.ns;
-  hp.lam = wavelength_A(d->voltage_V);
-  hp.sigma = sigma_rad_per_VA(d->voltage_V);
-  hp.alpha = d->aperture_mrad * 1e-3;
-  hp.fb = choose_frame_batch(d);
-  hp.splat_per_slice = splat_per_slice();
-  hp.overlap = overlap_splat();
-  hp.splat_group = splat_group(d->n_slices, hp.fb, hp.pnx, hp.pny);
-
-  for (int j = 0; j < hp.A; ++j)
-    if (atom_species[j] < 0 || atom_species[j] >= hp.S) {
-      set_error("atom %d has species index %d outside [0, %d)", j, atom_species[j], hp.S);
-      return TACAW_EINVAL;
+// Reciprocal-space route: atoms of each (slice, species), in sorted order,
+// and the form-factor coefficients (a and c times C/A, d times log2 e).
+static void plan_kspace(const tacaw_job_desc* d, HostPlan& hp,
+                        const std::vector<std::vector<int32_t>>& slice_atoms) {
+  const double cpref_k = 2.0 * M_PI * kBohrA * kCoulombEVA / (hp.lx * hp.ly);
+  hp.ks_start.assign((size_t)hp.ns * hp.S + 1, 0);
+  hp.ks_atoms.clear();
+  for (int s = 0; s < hp.ns; ++s)
+    for (int z = 0; z < hp.S; ++z) {
+      hp.ks_start[(size_t)s * hp.S + z] = (int32_t)hp.ks_atoms.size();
+      for (const int j : slice_atoms[s])
+        if (hp.sorted_species[j] == z) hp.ks_atoms.push_back(j);
     }
-  for (size_t i = 0; i < (size_t)hp.F * hp.A * 3; ++i)
-    if (!isfinite(pos[i])) {
-      set_error("positions[%zu] is not finite", i);
-      return TACAW_EINVAL;
+  hp.ks_start[(size_t)hp.ns * hp.S] = (int32_t)hp.ks_atoms.size();
+  hp.kcoef.resize((size_t)hp.S * KP_NCOEF);
+  for (int z = 0; z < hp.S; ++z)
+    for (int i = 0; i < 3; ++i) {
+      const double* c = d->kspace_coef + (size_t)z * 12;
+      hp.kcoef[z * KP_NCOEF + i] = (float)(cpref_k * c[i]);
+      hp.kcoef[z * KP_NCOEF + 3 + i] = (float)c[3 + i];
+      hp.kcoef[z * KP_NCOEF + 6 + i] = (float)(cpref_k * c[6 + i]);
+      hp.kcoef[z * KP_NCOEF + 9 + i] = (float)(c[9 + i] / M_LN2);
     }
+  // no real-space tiles
+  hp.tiles_x = (hp.pnx + SPLAT_TX - 1) / SPLAT_TX;
+  hp.tiles_y = (hp.pny + SPLAT_TY - 1) / SPLAT_TY;
+  hp.tile_start.assign((size_t)hp.ns * hp.tiles_x * hp.tiles_y + 1, 0);
+  hp.tile_atoms.clear();
+  hp.coef.assign((size_t)hp.S * N_GAUSS * COEF_STRIDE, 0.f);
+}
 
-  // Slice binning by the FP64 frame-mean z; half-open slices, clamped.
-  hp.slice_of.assign(hp.A, 0);
-  std::vector<double> zbar(hp.A, 0.0);
-  for (int f = 0; f < hp.F; ++f)
-    for (int j = 0; j < hp.A; ++j) zbar[j] += pos[((size_t)f * hp.A + j) * 3 + 2];
-  for (int j = 0; j < hp.A; ++j) {
-    const double z = zbar[j] / (double)hp.F;
-    double zm = fmod(z, hp.lz);
-    if (zm != 0.0 && zm < 0.0) zm += hp.lz;
-    long s = (long)floor(zm / hp.dz);
-    if (s < 0) s = 0;
-    if (s > hp.ns - 1) s = hp.ns - 1;
-    hp.slice_of[j] = (int32_t)s;
-  }
-  hp.order.resize(hp.A);
-  std::iota(hp.order.begin(), hp.order.end(), 0);
-  std::stable_sort(hp.order.begin(), hp.order.end(),
-                   [&](int a, int b) { return hp.slice_of[a] < hp.slice_of[b]; });
-  std::vector<int32_t> slice_start(hp.ns + 1, 0);
-  for (int j = 0; j < hp.A; ++j) slice_start[hp.slice_of[j] + 1]++;
-  for (int s = 0; s < hp.ns; ++s) slice_start[s + 1] += slice_start[s];
-  hp.sorted_species.resize(hp.A);
-  for (int j = 0; j < hp.A; ++j) hp.sorted_species[j] = atom_species[hp.order[j]];
-
-  // Per-frame binning (TACAW_SLICE_BY_INSTANT_Z): each frame's own z, the same
-  // half-open clamped slices; an atom is a candidate in every slice it visits,
-  // and the potential kernel skips it in frames where it is elsewhere.
-  hp.instant_z = (d->flags & TACAW_SLICE_BY_INSTANT_Z) != 0;
-  std::vector<std::vector<int32_t>> slice_atoms(hp.ns);   // sorted atom indices per slice
-  if (hp.instant_z) {
-    hp.fslice.assign((size_t)hp.F * hp.A, 0);
-    for (int f = 0; f < hp.F; ++f)
-      for (int j = 0; j < hp.A; ++j) {
-        double zm = fmod(pos[((size_t)f * hp.A + hp.order[j]) * 3 + 2], hp.lz);
-        if (zm != 0.0 && zm < 0.0) zm += hp.lz;
-        long s = (long)floor(zm / hp.dz);
-        if (s < 0) s = 0;
-        if (s > hp.ns - 1) s = hp.ns - 1;
-        hp.fslice[(size_t)f * hp.A + j] = (int16_t)s;
-      }
-    std::vector<int16_t> visited;
-    for (int j = 0; j < hp.A; ++j) {   // atoms in sorted order, so every list stays sorted
-      visited.clear();
-      for (int f = 0; f < hp.F; ++f) visited.push_back(hp.fslice[(size_t)f * hp.A + j]);
-      std::sort(visited.begin(), visited.end());
-      visited.erase(std::unique(visited.begin(), visited.end()), visited.end());
-      for (int16_t s : visited) slice_atoms[s].push_back(j);
-    }
-  } else {
-    for (int s = 0; s < hp.ns; ++s)
-      for (int j = slice_start[s]; j < slice_start[s + 1]; ++j) slice_atoms[s].push_back(j);
-  }
-
+// Real-space route: per-term coefficients and the candidate (atom, term)
+// pairs of every (slice, 32 x 32 tile).
+static void plan_real_space(const tacaw_job_desc* d, const double* pos, HostPlan& hp,
+                            const std::vector<std::vector<int32_t>>& slice_atoms) {
   // Truncation radius: exp(-pi^2 r^2 / b) <= 1e-8 for the widest term.
   double bmax = 0.0;
   for (int i = 0; i < hp.S * TACAW_N_GAUSS; ++i) bmax = std::max(bmax, d->gauss_b[i]);
@@ -417,6 +401,107 @@ tacaw_status plan_job(const tacaw_job_desc* d, const int32_t* atom_species, cons
     }
   }
   hp.tile_start[(size_t)hp.ns * nt] = (int32_t)hp.tile_atoms.size();
+}
+
+tacaw_status plan_job(const tacaw_job_desc* d, const int32_t* atom_species, const double* pos,
+                      HostPlan& hp) {
+  hp.nx = d->nx;
+  hp.ny = d->ny;
+  hp.pnx = d->pot_nx > 0 ? d->pot_nx : d->nx;
+  hp.pny = d->pot_ny > 0 ? d->pot_ny : d->ny;
+  hp.ns = d->n_slices;
+  hp.F = d->n_frames;
+  hp.A = d->n_atoms;
+  hp.S = d->n_species;
+  hp.plane = d->aperture_mrad == 0.0;
+  hp.P = hp.plane ? 1 : d->n_probes;
+  hp.windowed = hp.pnx != hp.nx || hp.pny != hp.ny;
+  hp.two_sided = (d->flags & TACAW_TWO_SIDED) != 0;
+  hp.M = hp.two_sided ? hp.F : hp.F / 2;
+  hp.lx = d->cell[0];
+  hp.ly = d->cell[1];
+  hp.lz = d->cell[2];
+  hp.dx = hp.lx / hp.pnx;
+  hp.dy = hp.ly / hp.pny;
+  hp.dz = hp.lz / hp.ns;
+  hp.lam = wavelength_A(d->voltage_V);
+  hp.sigma = sigma_rad_per_VA(d->voltage_V);
+  hp.alpha = d->aperture_mrad * 1e-3;
+  hp.fb = choose_frame_batch(d);
+  hp.kspace = d->kspace_coef != nullptr;
+  hp.splat_per_slice = splat_per_slice();
+  hp.overlap = overlap_splat() && !hp.kspace;
+  hp.splat_group = splat_group(d->n_slices, hp.fb, hp.pnx, hp.pny);
+  hp.kgroup = hp.kspace ? kspace_group(d->n_slices, hp.fb, hp.pnx, hp.pny) : 0;
+
+  for (int j = 0; j < hp.A; ++j)
+    if (atom_species[j] < 0 || atom_species[j] >= hp.S) {
+      set_error("atom %d has species index %d outside [0, %d)", j, atom_species[j], hp.S);
+      return TACAW_EINVAL;
+    }
+  for (size_t i = 0; i < (size_t)hp.F * hp.A * 3; ++i)
+    if (!isfinite(pos[i])) {
+      set_error("positions[%zu] is not finite", i);
+      return TACAW_EINVAL;
+    }
+
+  // Slice binning by the FP64 frame-mean z; half-open slices, clamped.
+  hp.slice_of.assign(hp.A, 0);
+  std::vector<double> zbar(hp.A, 0.0);
+  for (int f = 0; f < hp.F; ++f)
+    for (int j = 0; j < hp.A; ++j) zbar[j] += pos[((size_t)f * hp.A + j) * 3 + 2];
+  for (int j = 0; j < hp.A; ++j) {
+    const double z = zbar[j] / (double)hp.F;
+    double zm = fmod(z, hp.lz);
+    if (zm != 0.0 && zm < 0.0) zm += hp.lz;
+    long s = (long)floor(zm / hp.dz);
+    if (s < 0) s = 0;
+    if (s > hp.ns - 1) s = hp.ns - 1;
+    hp.slice_of[j] = (int32_t)s;
+  }
+  hp.order.resize(hp.A);
+  std::iota(hp.order.begin(), hp.order.end(), 0);
+  std::stable_sort(hp.order.begin(), hp.order.end(),
+                   [&](int a, int b) { return hp.slice_of[a] < hp.slice_of[b]; });
+  std::vector<int32_t> slice_start(hp.ns + 1, 0);
+  for (int j = 0; j < hp.A; ++j) slice_start[hp.slice_of[j] + 1]++;
+  for (int s = 0; s < hp.ns; ++s) slice_start[s + 1] += slice_start[s];
+  hp.sorted_species.resize(hp.A);
+  for (int j = 0; j < hp.A; ++j) hp.sorted_species[j] = atom_species[hp.order[j]];
+
+  // Per-frame binning (TACAW_SLICE_BY_INSTANT_Z): each frame's own z, the same
+  // half-open clamped slices; an atom is a candidate in every slice it visits,
+  // and the potential kernel skips it in frames where it is elsewhere.
+  hp.instant_z = (d->flags & TACAW_SLICE_BY_INSTANT_Z) != 0;
+  std::vector<std::vector<int32_t>> slice_atoms(hp.ns);   // sorted atom indices per slice
+  if (hp.instant_z) {
+    hp.fslice.assign((size_t)hp.F * hp.A, 0);
+    for (int f = 0; f < hp.F; ++f)
+      for (int j = 0; j < hp.A; ++j) {
+        double zm = fmod(pos[((size_t)f * hp.A + hp.order[j]) * 3 + 2], hp.lz);
+        if (zm != 0.0 && zm < 0.0) zm += hp.lz;
+        long s = (long)floor(zm / hp.dz);
+        if (s < 0) s = 0;
+        if (s > hp.ns - 1) s = hp.ns - 1;
+        hp.fslice[(size_t)f * hp.A + j] = (int16_t)s;
+      }
+    std::vector<int16_t> visited;
+    for (int j = 0; j < hp.A; ++j) {   // atoms in sorted order, so every list stays sorted
+      visited.clear();
+      for (int f = 0; f < hp.F; ++f) visited.push_back(hp.fslice[(size_t)f * hp.A + j]);
+      std::sort(visited.begin(), visited.end());
+      visited.erase(std::unique(visited.begin(), visited.end()), visited.end());
+      for (int16_t s : visited) slice_atoms[s].push_back(j);
+    }
+  } else {
+    for (int s = 0; s < hp.ns; ++s)
+      for (int j = slice_start[s]; j < slice_start[s + 1]; ++j) slice_atoms[s].push_back(j);
+  }
+
+  if (hp.kspace)
+    plan_kspace(d, hp, slice_atoms);
+  else
+    plan_real_space(d, pos, hp, slice_atoms);
 
   // Probe windows: origin floor(r/d) - N/2 (wrapped for the crop); the probe
   // sits at r - origin * d inside the window.

@@ -45,12 +45,18 @@ struct HostPlan {
   std::vector<int32_t> sorted_species; // [A]
   std::vector<int32_t> origin;         // [P][2] wrapped window origin
   std::vector<double> rloc;            // [P][2] probe position relative to the window
+  // reciprocal-space potential route (kspace_coef given)
+  bool kspace = false;
+  int kgroup = 0;                      // slices per structure-factor launch (even unless all slices)
+  std::vector<int32_t> ks_start;       // [ns * S + 1] CSR offsets per (slice, species)
+  std::vector<int32_t> ks_atoms;       // sorted-atom indices
+  std::vector<float> kcoef;            // [S][12] (a, c times C/A; d times log2 e)
 };
 
 // Device bytes of each buffer of a job.
 struct Footprint {
-  size_t exit = 0, spec = 0, V = 0, pos = 0, tiles = 0, probes = 0, tables = 0;
-  size_t total() const { return exit + spec + V + pos + tiles + probes + tables; }
+  size_t exit = 0, spec = 0, V = 0, W = 0, pos = 0, tiles = 0, probes = 0, tables = 0;
+  size_t total() const { return exit + spec + V + W + pos + tiles + probes + tables; }
 };
 
 tacaw_status validate_desc(const tacaw_job_desc* d);
@@ -58,6 +64,7 @@ int choose_frame_batch(const tacaw_job_desc* d);
 bool splat_per_slice();
 bool overlap_splat();
 int splat_group(int n_slices, int fb, int pnx, int pny);
+int kspace_group(int n_slices, int fb, int pnx, int pny);
 Footprint footprint_of(const tacaw_job_desc* d, int fb, size_t n_tile_atoms_estimate);
 double wavelength_A(double volt);
 double sigma_rad_per_VA(double volt);
@@ -132,6 +139,7 @@ struct tacaw_job {
   std::vector<double> probe_xy;
   std::vector<int32_t> species_Z;
   std::vector<double> gauss_a, gauss_b;
+  std::vector<double> kspace_coef;   // n_species x 12, or empty
   tacaw::HostPlan hp;
   tacaw::Footprint fp;
   // device buffers
@@ -154,6 +162,13 @@ struct tacaw_job {
   tacaw::Aberrations aberr{};    // probe aberrations (off unless set)
   int32_t* d_origin = nullptr;
   int16_t* d_fslice = nullptr;   // [F][A] per-frame slices (instant-z binning only)
+  // reciprocal-space potential route
+  float2* d_W = nullptr;         // [fb][kgroup/2 rounded up][pny][pnx] structure factors of slice pairs
+  int32_t* d_ks_start = nullptr;
+  int32_t* d_ks_atoms = nullptr;
+  float* d_kcoef = nullptr;
+  float2* d_tw_px = nullptr;     // potential-grid twiddles (windowed jobs; else the wave grid's)
+  float2* d_tw_py = nullptr;
   double* d_rloc = nullptr;
   int* d_count = nullptr;
   std::vector<tacaw::AtomPos> enc;   // encoded positions, kept until the device copy exists

@@ -55,7 +55,39 @@ struct PassArgs {
   float sigma;                 // interaction parameter [rad / (V A)]
   float plane_amp;             // 1 / sqrt(nx ny)
   int plane;                   // 1: plane-wave incident wave
+  float* vout;                 // inverse-only row pass of the reciprocal-space potentials: when set,
+                               // wave w's real part goes to plane 2w of vout and its imaginary part to
+                               // plane 2w + 1 ([2 W][ny][nx] float) instead of back into exit
 };
+
+// The paper's reciprocal-space potential route for one batch of frames and a
+// group of slices taken in pairs (2q, 2q + 1): W = V(k) of slice 2q + i V(k)
+// of slice 2q + 1, V(k) = sum over the slice's atoms of f_Z(|k|) exp(-2 pi i
+// k.r_j) at the potential grid's frequencies, with f the 3 Lorentzian + 3
+// Gaussian form factor times C/A.  Both slices' potentials are real, so one
+// unnormalised inverse 2D FFT of W gives them as its real and imaginary parts.
+// The kernel computes the rows ky index 0 .. pny/2 and writes the others as
+// W(-k) = conj V_2q(k) + i conj V_2q+1(k).  W is then the Hermitian part of
+// the literal sum, so the transform gives the real part of the literal
+// potential: a Nyquist frequency of an even side takes cos(pi n x) (the mean
+// of its +k and -k terms), and the corner where both are Nyquist takes
+// cos(a + b) = cos a cos b - sin a sin b.
+struct KPotArgs {
+  const AtomPos* pos;          // [F][A], atoms in slice-sorted order
+  const int32_t* ks_start;     // [n_slices * n_species + 1]: CSR offsets per (slice, species)
+  const int32_t* ks_atoms;     // sorted-atom indices, by (slice, species)
+  const int16_t* fslice;       // [F][A] each frame's own slice (sorted order), or nullptr
+  const float* kcoef;          // [S][12]: a1..a3 (times C/A), b1..b3, c1..c3 (times C/A),
+                               // d1..d3 (times log2 e)
+  float2* W;                   // [fb][npairs][pny][pnx]
+  int n_atoms, n_species, f0, fb, n_slices, slice0, npairs, pnx, pny;
+  int row_tiles, col_tiles;    // tiles over rows 0 .. pny/2 and over the columns
+  float kx_unit, ky_unit;      // 1/Lx, 1/Ly [1/A]
+};
+constexpr int KP_TY = 32;      // reciprocal-space potential tile: rows
+constexpr int KP_TX = 128;     // columns (four wavefronts of 32)
+constexpr int KP_K = 16;       // atoms per LDS stage
+constexpr int KP_NCOEF = 12;
 
 struct TimeArgs {
   const float2* exit;          // [P][F][n_k]
@@ -102,6 +134,7 @@ hipError_t launch_col_lanes(const PassLane* lanes, int n, int variant, hipStream
 hipError_t launch_splat_lanes(const SplatLane* lanes, int n, hipStream_t s);
 hipError_t launch_col_pass(const PassArgs& a, int mode, hipStream_t s);
 hipError_t launch_time_stage(const TimeArgs& a, hipStream_t s);
+hipError_t launch_kpot(const KPotArgs& a, hipStream_t s);
 int time_stage_kt(int n_frames, int n_k);
 
 // Setup kernels: twiddle table exp(-2 pi i m / n) (FP64 -> FP32); separable

@@ -52,6 +52,7 @@ class JobDesc(ctypes.Structure):
         ("gauss_a", ctypes.POINTER(ctypes.c_double)),
         ("gauss_b", ctypes.POINTER(ctypes.c_double)),
         ("flags", ctypes.c_uint32),
+        ("kspace_coef", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -142,8 +143,8 @@ class _DescHolder:
 
     def __init__(self, job, keep_exit_waves: Optional[bool] = None):
         self.species_Z = np.ascontiguousarray(job.species_Z, dtype=np.int32)
-        self.gauss_a = np.ascontiguousarray(job.gauss_a, dtype=np.float64)
-        self.gauss_b = np.ascontiguousarray(job.gauss_b, dtype=np.float64)
+        self.gauss_a = None if job.gauss_a is None else np.ascontiguousarray(job.gauss_a, dtype=np.float64)
+        self.gauss_b = None if job.gauss_b is None else np.ascontiguousarray(job.gauss_b, dtype=np.float64)
         self.probe_xy = np.ascontiguousarray(job.probe_xy, dtype=np.float64).reshape(-1, 2)
         if self.probe_xy.size == 0:
             self.probe_xy = np.zeros((1, 2))
@@ -160,12 +161,17 @@ class _DescHolder:
         d.n_atoms = int(job.positions.shape[1])
         d.n_species = int(len(self.species_Z))
         d.species_Z = _ptr(self.species_Z, ctypes.c_int32)
-        d.gauss_a = _ptr(self.gauss_a, ctypes.c_double)
-        d.gauss_b = _ptr(self.gauss_b, ctypes.c_double)
+        if self.gauss_a is not None and self.gauss_b is not None:
+            d.gauss_a = _ptr(self.gauss_a, ctypes.c_double)
+            d.gauss_b = _ptr(self.gauss_b, ctypes.c_double)
         keep = job.keep_exit_waves if keep_exit_waves is None else keep_exit_waves
         d.flags = (TWO_SIDED if job.two_sided else 0) | (KEEP_EXIT_WAVES if keep else 0)
         if getattr(job, "slice_by_instant_z", False):
             d.flags |= SLICE_BY_INSTANT_Z
+        kirk = getattr(job, "kirkland", None)
+        if kirk is not None:        # the paper's reciprocal-space potential route
+            self.kspace_coef = np.ascontiguousarray(kirk, dtype=np.float64).reshape(len(self.species_Z), 12)
+            d.kspace_coef = _ptr(self.kspace_coef, ctypes.c_double)
         self.desc = d
 
 

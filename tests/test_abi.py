@@ -98,3 +98,37 @@ def test_per_frame_binning_footprint_and_limit():
     with pytest.raises(t.TacawError) as e:
         t.footprint(inst.replace(n_slices=40000))            # 16-bit slice indices
     assert e.value.status == 1
+
+
+def test_kspace_route_validation_and_footprint():
+    # the paper's reciprocal-space potential route: coefficient checks, the
+    # potential grid must have FFT plans, and the slice-pair structure factors
+    # add to the footprint
+    t = _tacaw()
+    base = w.with_kirkland(w.random_small_job(5, nx=32, ny=32, n_frames=8, n_slices=4), seed=1)
+    real = base.replace(kirkland=None)
+    assert t.footprint(base) > t.footprint(real)
+    assert t.footprint(base.replace(gauss_a=None, gauss_b=None)) == t.footprint(base)
+    for col in (3, 4, 5):                                    # b must be > 0
+        k = base.kirkland.copy()
+        k[0, col] = 0.0
+        with pytest.raises(t.TacawError) as e:
+            t.footprint(base.replace(kirkland=k))
+        assert e.value.status == 1
+    k = base.kirkland.copy()
+    k[1, 10] = -0.5                                          # d must be >= 0
+    with pytest.raises(t.TacawError) as e:
+        t.footprint(base.replace(kirkland=k))
+    assert e.value.status == 1
+    k = base.kirkland.copy()
+    k[0, 0] = np.nan
+    with pytest.raises(t.TacawError) as e:
+        t.footprint(base.replace(kirkland=k))
+    assert e.value.status == 1
+    # a window on a potential grid without FFT plans (1000 x 866) is refused
+    win = base.replace(aperture_mrad=30.0, probe_xy=np.array([[3.0, 3.0]]), pot_nx=1000, pot_ny=866,
+                       cell=np.array([100.0, 86.6, 4.0]))
+    with pytest.raises(t.TacawError) as e:
+        t.footprint(win)
+    assert e.value.status == 7
+    assert t.footprint(win.replace(kirkland=None)) > 0

@@ -238,17 +238,18 @@ def test_overlapped_potentials_graph_replay(tacaw, ctx, monkeypatch):
             (x * 2).sum().item()
 
 
-@pytest.mark.parametrize("variant", ["2", "3", "4", "5"])
+@pytest.mark.parametrize("variant", ["2", "3", "4", "5", "6"])
 def test_c2_shape_register_column_kernels(tacaw, ctx, oracle, monkeypatch, variant):
     # register column pass on 8-column tiles (2), 16-column tiles (3),
-    # 8-column tiles with two LDS buffers (4) and the six-step kernel (5)
+    # 8-column tiles with two LDS buffers (4), the six-step kernel on
+    # 8-column tiles (5) and on 16-column tiles (6)
     monkeypatch.setenv("TACAW_COL_VARIANT", variant)
     monkeypatch.setenv("TACAW_FB", "3")
     job = w.c2_plain(n_frames=5)
     check_job(tacaw, ctx, oracle, job)
 
 
-@pytest.mark.parametrize("variant", ["2", "5"])
+@pytest.mark.parametrize("variant", ["2", "5", "6"])
 def test_512_rows_narrow_grid(tacaw, ctx, oracle, monkeypatch, variant):
     # 512 rows and 64 columns: the six-step column kernel (default at 512 rows)
     # and the register kernel, probes included, ragged frame batches
