@@ -56,11 +56,21 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def cpu_baseline(job, sample_frames: int, what: str = ""):
-    """FP64 oracle on `sample_frames` frames of the workload, one frame per worker."""
+# worker processes of the oracle baseline: the host CPUs this process may run
+# on, capped at the 16 that a one-GPU share of the host provides
+ORACLE_MAX_WORKERS = 16
+
+
+def cpu_baseline(job, sample_frames: int, full_slice_steps: int, what: str = ""):
+    """FP64 oracle on `sample_frames` frames of the workload, one frame per
+    worker process, every worker busy (sample_frames is a multiple of the
+    worker count).  The rate is the sample's; `extrapolated_s` scales the
+    sample time linearly to the whole workload (work is linear in frames and
+    probes)."""
     from tests.oracle_pool import exit_waves_parallel
     from oracle import tacaw_oracle
-    workers = max(1, min(sample_frames, 16, len(os.sched_getaffinity(0))))
+    host_cpus = len(os.sched_getaffinity(0))
+    workers = max(1, min(sample_frames, ORACLE_MAX_WORKERS, host_cpus))
     frames = list(range(sample_frames))
     t0 = time.perf_counter()
     ex = exit_waves_parallel(job, frames=frames, workers=workers)
@@ -68,8 +78,11 @@ def cpu_baseline(job, sample_frames: int, what: str = ""):
     dt = time.perf_counter() - t0
     steps = job.nx * job.ny * job.n_slices * sample_frames * job.n_probes
     return {"value": steps / dt, "unit": "slice-steps/s", "cores": workers, "kind": "oracle",
+            "host_cpus": host_cpus, "sample_s": round(dt, 2), "sample_slice_steps": steps,
+            "extrapolated_s": round(dt * full_slice_steps / steps, 1),
             "sample": (what or f"{sample_frames} of the 1024 frames (full 512^2 grid, all 32 slices, "
-                               f"spectrum of the sample)") + f", FP64 numpy, one frame per process, {dt:.1f} s"}
+                               f"spectrum of the sample)") +
+                      f", FP64 numpy, one frame per process on {workers} processes, {dt:.1f} s"}
 
 
 def bench_c4(args):
@@ -388,11 +401,12 @@ def main():
         if args.workload == "c3":
             # 4 probe positions x the sample frames, full windows and slices
             sub = job.replace(probe_xy=job.probe_xy[:4], positions=job.positions[:args.cpu_sample])
-            cpu = cpu_baseline(sub, args.cpu_sample, what="4 of the 1024 probe positions x %d of the "
+            cpu = cpu_baseline(sub, args.cpu_sample, slice_steps,
+                               what="4 of the 1024 probe positions x %d of the "
                                "256 frames (256^2 windows, all 20 slices, potentials on the 1000x866 "
                                "grid, spectrum of the sample)" % args.cpu_sample)
         else:
-            cpu = cpu_baseline(job, args.cpu_sample)
+            cpu = cpu_baseline(job, args.cpu_sample, slice_steps)
 
     out = {
         "metric": "slice-steps/sec (grid-pts*slices*frames/s) + %HBM peak",
