@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <numeric>
+#include <thread>
 
 #include "runtime.h"
 
@@ -277,6 +278,27 @@ Footprint footprint_of(const tacaw_job_desc* d, int fb, size_t n_tile_atoms) {
 
 static inline double wrap_min_image(double d, double L) { return d - L * nearbyint(d / L); }
 
+// fn(begin, end) over [0, n) in contiguous chunks on up to 16 threads (the
+// host share of one GPU) when there are at least 2^22 work units (n times
+// `units` per item); one thread otherwise.  Callers keep every per-item result
+// independent of the split.
+template <typename Fn>
+static void parallel_for(size_t n, size_t units, Fn&& fn) {
+  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+  const unsigned nt = (unsigned)std::min<size_t>(std::min(16u, hw), n);
+  if (nt <= 1 || n * units < ((size_t)1 << 22)) {
+    fn((size_t)0, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  const size_t chunk = (n + nt - 1) / nt;
+  for (unsigned t = 0; t < nt; ++t) {
+    const size_t b = t * chunk, e = std::min(n, b + chunk);
+    if (b < e) th.emplace_back([&fn, b, e] { fn(b, e); });
+  }
+  for (auto& x : th) x.join();
+}
+
 // Reciprocal-space route: atoms of each (slice, species), in sorted order,
 // and the form-factor coefficients (a and c times C/A, d times log2 e).
 static void plan_kspace(const tacaw_job_desc* d, HostPlan& hp,
@@ -349,22 +371,25 @@ static void plan_real_space(const tacaw_job_desc* d, const double* pos, HostPlan
   // displacement from its mean position (and half a pixel for the rounding
   // of positions), can reach the tile along both axes (periodic).  Entries
   // are sorted-atom * 8 + term, in atom order then term order.
-  std::vector<double> xbar(hp.A), ybar(hp.A), dmx(hp.A, 0.0), dmy(hp.A, 0.0);
-  for (int j = 0; j < hp.A; ++j) {
-    const double x0 = pos[(size_t)j * 3], y0 = pos[(size_t)j * 3 + 1];
-    double sx = 0.0, sy = 0.0;
-    for (int f = 0; f < hp.F; ++f) {
-      sx += wrap_min_image(pos[((size_t)f * hp.A + j) * 3] - x0, hp.lx);
-      sy += wrap_min_image(pos[((size_t)f * hp.A + j) * 3 + 1] - y0, hp.ly);
+  // per atom: mean position (minimum-image displacements from frame 0, summed
+  // over frames in order) and largest displacement from it
+  std::vector<double> xbar(hp.A, 0.0), ybar(hp.A, 0.0), dmx(hp.A, 0.0), dmy(hp.A, 0.0);
+  parallel_for((size_t)hp.A, (size_t)hp.F, [&](size_t j0, size_t j1) {
+    for (int f = 0; f < hp.F; ++f)
+      for (size_t j = j0; j < j1; ++j) {
+        xbar[j] += wrap_min_image(pos[((size_t)f * hp.A + j) * 3] - pos[j * 3], hp.lx);
+        ybar[j] += wrap_min_image(pos[((size_t)f * hp.A + j) * 3 + 1] - pos[j * 3 + 1], hp.ly);
+      }
+    for (size_t j = j0; j < j1; ++j) {
+      xbar[j] = pos[j * 3] + xbar[j] / hp.F;
+      ybar[j] = pos[j * 3 + 1] + ybar[j] / hp.F;
     }
-    xbar[j] = x0 + sx / hp.F;
-    ybar[j] = y0 + sy / hp.F;
-  }
-  for (int f = 0; f < hp.F; ++f)
-    for (int j = 0; j < hp.A; ++j) {
-      dmx[j] = std::max(dmx[j], fabs(wrap_min_image(pos[((size_t)f * hp.A + j) * 3] - xbar[j], hp.lx)));
-      dmy[j] = std::max(dmy[j], fabs(wrap_min_image(pos[((size_t)f * hp.A + j) * 3 + 1] - ybar[j], hp.ly)));
-    }
+    for (int f = 0; f < hp.F; ++f)
+      for (size_t j = j0; j < j1; ++j) {
+        dmx[j] = std::max(dmx[j], fabs(wrap_min_image(pos[((size_t)f * hp.A + j) * 3] - xbar[j], hp.lx)));
+        dmy[j] = std::max(dmy[j], fabs(wrap_min_image(pos[((size_t)f * hp.A + j) * 3 + 1] - ybar[j], hp.ly)));
+      }
+  });
   hp.tiles_x = (hp.pnx + SPLAT_TX - 1) / SPLAT_TX;
   hp.tiles_y = (hp.pny + SPLAT_TY - 1) / SPLAT_TY;
   const int nt = hp.tiles_x * hp.tiles_y;
@@ -439,17 +464,32 @@ tacaw_status plan_job(const tacaw_job_desc* d, const int32_t* atom_species, cons
       set_error("atom %d has species index %d outside [0, %d)", j, atom_species[j], hp.S);
       return TACAW_EINVAL;
     }
-  for (size_t i = 0; i < (size_t)hp.F * hp.A * 3; ++i)
-    if (!isfinite(pos[i])) {
-      set_error("positions[%zu] is not finite", i);
-      return TACAW_EINVAL;
-    }
+  {
+    // first non-finite coordinate, if any (per-frame chunks, lowest index wins)
+    const size_t per_frame = (size_t)hp.A * 3;
+    std::vector<size_t> bad(hp.F, SIZE_MAX);
+    parallel_for((size_t)hp.F, per_frame, [&](size_t f0, size_t f1) {
+      for (size_t f = f0; f < f1; ++f)
+        for (size_t i = f * per_frame; i < (f + 1) * per_frame; ++i)
+          if (!isfinite(pos[i])) {
+            bad[f] = i;
+            break;
+          }
+    });
+    for (size_t f = 0; f < (size_t)hp.F; ++f)
+      if (bad[f] != SIZE_MAX) {
+        set_error("positions[%zu] is not finite", bad[f]);
+        return TACAW_EINVAL;
+      }
+  }
 
   // Slice binning by the FP64 frame-mean z; half-open slices, clamped.
   hp.slice_of.assign(hp.A, 0);
   std::vector<double> zbar(hp.A, 0.0);
-  for (int f = 0; f < hp.F; ++f)
-    for (int j = 0; j < hp.A; ++j) zbar[j] += pos[((size_t)f * hp.A + j) * 3 + 2];
+  parallel_for((size_t)hp.A, (size_t)hp.F, [&](size_t j0, size_t j1) {
+    for (int f = 0; f < hp.F; ++f)
+      for (size_t j = j0; j < j1; ++j) zbar[j] += pos[((size_t)f * hp.A + j) * 3 + 2];
+  });
   for (int j = 0; j < hp.A; ++j) {
     const double z = zbar[j] / (double)hp.F;
     double zm = fmod(z, hp.lz);
@@ -476,15 +516,17 @@ tacaw_status plan_job(const tacaw_job_desc* d, const int32_t* atom_species, cons
   std::vector<std::vector<int32_t>> slice_atoms(hp.ns);   // sorted atom indices per slice
   if (hp.instant_z) {
     hp.fslice.assign((size_t)hp.F * hp.A, 0);
-    for (int f = 0; f < hp.F; ++f)
-      for (int j = 0; j < hp.A; ++j) {
-        double zm = fmod(pos[((size_t)f * hp.A + hp.order[j]) * 3 + 2], hp.lz);
-        if (zm != 0.0 && zm < 0.0) zm += hp.lz;
-        long s = (long)floor(zm / hp.dz);
-        if (s < 0) s = 0;
-        if (s > hp.ns - 1) s = hp.ns - 1;
-        hp.fslice[(size_t)f * hp.A + j] = (int16_t)s;
-      }
+    parallel_for((size_t)hp.F, (size_t)hp.A, [&](size_t f0, size_t f1) {
+      for (int f = (int)f0; f < (int)f1; ++f)
+        for (int j = 0; j < hp.A; ++j) {
+          double zm = fmod(pos[((size_t)f * hp.A + hp.order[j]) * 3 + 2], hp.lz);
+          if (zm != 0.0 && zm < 0.0) zm += hp.lz;
+          long s = (long)floor(zm / hp.dz);
+          if (s < 0) s = 0;
+          if (s > hp.ns - 1) s = hp.ns - 1;
+          hp.fslice[(size_t)f * hp.A + j] = (int16_t)s;
+        }
+    });
     std::vector<int16_t> visited;
     for (int j = 0; j < hp.A; ++j) {   // atoms in sorted order, so every list stays sorted
       visited.clear();
@@ -529,21 +571,23 @@ tacaw_status plan_job(const tacaw_job_desc* d, const int32_t* atom_species, cons
 // Encode positions of frames [f0, f1) in sorted atom order: integer pixel and
 // sub-pixel offset on the potential grid.
 void encode_positions(const HostPlan& hp, const double* pos, int f0, int f1, AtomPos* out) {
-  for (int f = f0; f < f1; ++f)
-    for (int j = 0; j < hp.A; ++j) {
-      const double* p = pos + ((size_t)f * hp.A + hp.order[j]) * 3;
-      const double ux = p[0] / hp.dx, uy = p[1] / hp.dy;
-      const double fxl = floor(ux), fyl = floor(uy);
-      long ix = (long)fxl, iy = (long)fyl;
-      AtomPos a;
-      a.fx = (float)(ux - fxl);
-      a.fy = (float)(uy - fyl);
-      if (a.fx >= 1.0f) { a.fx = 0.0f; ix += 1; }  // rounding up to 1.0f
-      if (a.fy >= 1.0f) { a.fy = 0.0f; iy += 1; }
-      a.ix = (int32_t)(((ix % hp.pnx) + hp.pnx) % hp.pnx);
-      a.iy = (int32_t)(((iy % hp.pny) + hp.pny) % hp.pny);
-      out[(size_t)(f - f0) * hp.A + j] = a;
-    }
+  parallel_for((size_t)(f1 - f0), (size_t)hp.A, [&](size_t c0, size_t c1) {
+    for (int f = f0 + (int)c0; f < f0 + (int)c1; ++f)
+      for (int j = 0; j < hp.A; ++j) {
+        const double* p = pos + ((size_t)f * hp.A + hp.order[j]) * 3;
+        const double ux = p[0] / hp.dx, uy = p[1] / hp.dy;
+        const double fxl = floor(ux), fyl = floor(uy);
+        long ix = (long)fxl, iy = (long)fyl;
+        AtomPos a;
+        a.fx = (float)(ux - fxl);
+        a.fy = (float)(uy - fyl);
+        if (a.fx >= 1.0f) { a.fx = 0.0f; ix += 1; }  // rounding up to 1.0f
+        if (a.fy >= 1.0f) { a.fy = 0.0f; iy += 1; }
+        a.ix = (int32_t)(((ix % hp.pnx) + hp.pnx) % hp.pnx);
+        a.iy = (int32_t)(((iy % hp.pny) + hp.pny) % hp.pny);
+        out[(size_t)(f - f0) * hp.A + j] = a;
+      }
+  });
 }
 
 }  // namespace tacaw

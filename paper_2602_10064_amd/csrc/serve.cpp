@@ -1,17 +1,24 @@
 // Serving loop: admission by device-memory footprint and continuous batching.
 //
-// Submitted jobs wait in a FIFO queue.  The loop admits the head of the queue
-// as soon as its footprint fits the context budget next to the jobs already
-// resident and a stream slot is free, materialises it (allocation, upload,
-// tables), and from then on interleaves frame batches of every running job:
-// each running job owns a non-blocking stream and keeps one frame batch
+// Submitted jobs wait in a queue.  When a stream slot is free, the loop
+// admits the first queued job, in submission order, whose footprint fits the
+// context budget next to the jobs already resident, so a small job can pass a
+// large one that does not fit yet.  A job that has waited longer than
+// TACAW_SERVE_AGE_MS (default 1000 ms) at the head of the queue stops that:
+// then only the head is admitted, as soon as it fits.  An admitted job is
+// materialised (allocation, upload, tables) by a housekeeping thread on its
+// slot's stream, so allocation never stalls the issue of other jobs' work;
+// from then on the loop interleaves frame batches of every running job: each
+// running job owns a non-blocking stream and keeps one frame batch
 // (potentials + all slice passes of fb frames) in flight, so batches of
 // different requests overlap on the device.  When a job's last batch is done
-// its time stage runs; then its working buffers are freed and only the
-// spectrum (and, if kept, the exit waves) stays resident until the job is
-// destroyed.  A job's result is computed by the same kernels on the same
-// frame batches as in the plain form, so it is bitwise the same alone or in
-// any mix.
+// its time stage runs; then the housekeeping thread frees its working buffers
+// and only the spectrum (and, if kept, the exit waves) stays resident until
+// the job is destroyed.  A job's result is computed by the same kernels on the
+// same frame batches as in the plain form, so it is bitwise the same alone or
+// in any mix.
+#include <stdlib.h>
+
 #include <chrono>
 
 #include "runtime.h"
@@ -44,11 +51,58 @@ struct Slot {
   hipEvent_t ev = nullptr;
   bool inflight = false;
   bool time_issued = false;
+  std::atomic<int> setup{0};   // 0 none, 1 materialising, 2 ready, 3 failed
 };
 
-void finish(tacaw_ctx* c, Slot& s, int state) {
-  tacaw_job* j = s.job;
-  (void)hipStreamSynchronize(s.stream);
+// One background thread for the slow host-side steps: materialising admitted
+// jobs and releasing finished ones.
+struct Housekeeper {
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<std::function<void()>> tasks;
+  bool stop = false;
+  std::thread th;
+  void start(int device) {
+    th = std::thread([this, device] {
+      (void)hipSetDevice(device);
+      for (;;) {
+        std::function<void()> t;
+        {
+          std::unique_lock<std::mutex> lk(mu);
+          cv.wait(lk, [&] { return stop || !tasks.empty(); });
+          if (tasks.empty()) return;   // stop requested and nothing left
+          t = std::move(tasks.front());
+          tasks.pop_front();
+        }
+        t();
+      }
+    });
+  }
+  void post(std::function<void()> t) {
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      tasks.push_back(std::move(t));
+    }
+    cv.notify_one();
+  }
+  void join() {
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      stop = true;
+    }
+    cv.notify_one();
+    if (th.joinable()) th.join();
+  }
+};
+
+double age_limit_ms() {
+  const char* e = getenv("TACAW_SERVE_AGE_MS");
+  return e ? atof(e) : 1000.0;
+}
+
+// Release a finished, cancelled or failed job's device memory and publish its
+// final state (runs on the housekeeping thread; the job's stream is idle).
+void release(tacaw_ctx* c, tacaw_job* j, int state) {
   size_t keep = 0;
   if (state == ST_DONE) {
     mark_all_present(j);
@@ -64,7 +118,6 @@ void finish(tacaw_ctx* c, Slot& s, int state) {
     j->d_spec = nullptr;
     j->has_result = false;
   }
-  j->t_done = now_ms();
   {
     std::lock_guard<std::mutex> lk(c->mu);
     c->resident -= j->fp.total();
@@ -73,9 +126,19 @@ void finish(tacaw_ctx* c, Slot& s, int state) {
     j->serve_state.store(state);
   }
   c->cv.notify_all();
+}
+
+// The slot's job is over: wait for its stream, stamp the end, hand the
+// release to the housekeeper and free the slot.
+void finish(tacaw_ctx* c, Housekeeper& hk, Slot& s, int state) {
+  tacaw_job* j = s.job;
+  (void)hipStreamSynchronize(s.stream);
+  j->t_done = now_ms();
+  hk.post([c, j, state] { release(c, j, state); });
   s.job = nullptr;
   s.inflight = false;
   s.time_issued = false;
+  s.setup.store(0);
 }
 
 void server_main(tacaw_ctx* c) {
@@ -85,6 +148,9 @@ void server_main(tacaw_ctx* c) {
     (void)hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking);
     (void)hipEventCreateWithFlags(&s.ev, hipEventDisableTiming);
   }
+  Housekeeper hk;
+  hk.start(c->device);
+  const double age_ms = age_limit_ms();
   for (;;) {
     bool progressed = false;
     {
@@ -109,40 +175,53 @@ void server_main(tacaw_ctx* c) {
       }
     }
     if (progressed) c->cv.notify_all();
-    // admission (FIFO): the head waits until its footprint fits and a slot frees
+    // admission: the first queued job that fits, unless the head has aged
+    // past the limit, in which case only the head
     for (auto& s : slots) {
       if (s.job) continue;
       tacaw_job* j = nullptr;
       {
         std::lock_guard<std::mutex> lk(c->mu);
         if (c->queue.empty()) break;
-        tacaw_job* h = c->queue.front();
-        if (c->resident + h->fp.total() > c->budget) break;
-        c->queue.pop_front();
-        c->resident += h->fp.total();
-        j = h;
+        const bool head_only = now_ms() - c->queue.front()->t_submit > age_ms;
+        for (auto it = c->queue.begin(); it != c->queue.end(); ++it) {
+          if (c->resident + (*it)->fp.total() <= c->budget) {
+            j = *it;
+            c->queue.erase(it);
+            break;
+          }
+          if (head_only) break;
+        }
+        if (!j) break;
+        c->resident += j->fp.total();
       }
       j->t_admit = now_ms();
       j->next_frame = 0;
       s.job = j;
-      if (materialize(j, s.stream) != TACAW_OK) {
-        finish(c, s, ST_FAILED);
-        continue;
-      }
-      j->serve_state.store(ST_RUNNING);
+      s.setup.store(1);
+      Slot* sp = &s;
+      hk.post([j, sp] { sp->setup.store(materialize(j, sp->stream) == TACAW_OK ? 2 : 3); });
       progressed = true;
     }
     // issue / retire work
     for (auto& s : slots) {
       tacaw_job* j = s.job;
       if (!j) continue;
+      const int setup = s.setup.load();
+      if (setup == 1) continue;   // still being materialised
+      if (setup == 3) {
+        finish(c, hk, s, ST_FAILED);
+        progressed = true;
+        continue;
+      }
+      if (j->serve_state.load() == ST_QUEUED) j->serve_state.store(ST_RUNNING);
       if (s.inflight) {
         if (hipEventQuery(s.ev) != hipSuccess) continue;
         s.inflight = false;
         progressed = true;
       }
       if (j->cancel_req.load() || c->stop) {
-        finish(c, s, ST_CANCELLED);
+        finish(c, hk, s, ST_CANCELLED);
         progressed = true;
         continue;
       }
@@ -155,12 +234,12 @@ void server_main(tacaw_ctx* c) {
         st = run_time_stage(j, s.stream);
         s.time_issued = true;
       } else {
-        finish(c, s, ST_DONE);
+        finish(c, hk, s, ST_DONE);
         progressed = true;
         continue;
       }
       if (st != TACAW_OK) {
-        finish(c, s, ST_FAILED);
+        finish(c, hk, s, ST_FAILED);
         continue;
       }
       (void)hipEventRecord(s.ev, s.stream);
@@ -170,7 +249,13 @@ void server_main(tacaw_ctx* c) {
     if (!progressed) std::this_thread::sleep_for(std::chrono::microseconds(50));
   }
   for (auto& s : slots) {
-    if (s.job) finish(c, s, ST_CANCELLED);
+    if (s.job) {
+      while (s.setup.load() == 1) std::this_thread::sleep_for(std::chrono::microseconds(50));
+      finish(c, hk, s, ST_CANCELLED);
+    }
+  }
+  hk.join();   // every posted setup and release has run
+  for (auto& s : slots) {
     (void)hipEventDestroy(s.ev);
     (void)hipStreamDestroy(s.stream);
   }

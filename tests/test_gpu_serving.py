@@ -138,3 +138,36 @@ def test_cancelled_job_then_plain_run(tacaw):
             h.wait()
         for h in hs + [victim]:
             h.destroy()
+
+
+def test_c5_requests_alone_vs_mix(tacaw):
+    """The first 16 requests of the serving workload (Poisson arrivals at
+    4 req/s; 13 uneven jobs of the c4 generator and three 1024^2 x 2048-frame
+    jobs), each run alone, then all submitted to the serving loop at once:
+    every spectrum is the same bit for bit."""
+    times, big = w.c5_arrivals(16)
+    big_job = w.c4_job(0, seed_base=5500, big=True)
+    jobs, ri = [], 0
+    for k in range(16):
+        if big[k]:
+            jobs.append(big_job)
+        else:
+            jobs.append(w.c4_job(ri, seed_base=5000))
+            ri += 1
+    print(f"[gpu] c5 mix: {int(big.sum())} big jobs of {big_job.slice_steps():.3e} slice-steps, "
+          f"{16 - int(big.sum())} uneven jobs", flush=True)
+    with tacaw.Context(0) as ctx:
+        handles = [tacaw.TacawJob(ctx, j, keep_exit_waves=False, defer_alloc=True) for j in jobs]
+        ref = []
+        for h in handles:
+            h.run()
+            ref.append(h.spectrum())
+        print("[gpu] c5 mix: alone runs done", flush=True)
+        for h in handles:
+            h.submit()
+        for h, r in zip(handles, ref):
+            h.wait()
+            got = h.spectrum()
+            assert np.array_equal(got.view(np.uint32), r.view(np.uint32)), h.job.name
+        for h in handles:
+            h.destroy()
