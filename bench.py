@@ -86,14 +86,18 @@ def cpu_baseline(job, sample_frames: int, full_slice_steps: int, what: str = "")
 
 
 def bench_c4(args):
-    """64 seeded uneven jobs: plain per-job launches vs the batched executor."""
+    """64 seeded uneven jobs: plain per-job launches vs the batched executor.
+    --workload c4small draws the same mix on small grids (64-128) with 16-96
+    frames, where a job's launches are too small to fill the device alone."""
     import torch
     from paper_2602_10064_amd import tacaw, workloads
+    small = args.workload == "c4small"
     ctx = tacaw.Context(0)
     handles, steps_total = [], 0
     t0 = time.perf_counter()
     for j in range(args.jobs):
-        job = workloads.c4_job(j)
+        job = (workloads.c4_job(j, seed_base=4500, grids=(64, 96, 128), frames_range=(16, 96)) if small
+               else workloads.c4_job(j))
         steps_total += job.slice_steps()
         handles.append(tacaw.TacawJob(ctx, job, keep_exit_waves=False))
         del job
@@ -149,8 +153,10 @@ def bench_c4(args):
         "ms_batched": t_batch * 1e3, "ms_plain": t_plain * 1e3, "ms_batched_one_stream": t_batch1 * 1e3,
         "higher_is_better": True,
         "dtype": "fp32", "data": "synthetic",
-        "config": {"workload": f"{args.jobs} seeded uneven jobs (grids 128-512, 8-48 slices, "
-                               f"128-1024 frames, plane wave or probe)", "slice_steps": steps_total},
+        "config": {"workload": (f"{args.jobs} seeded uneven small jobs (grids 64-128, 8-48 slices, 16-96 "
+                                f"frames, plane wave or probe)") if small else
+                               (f"{args.jobs} seeded uneven jobs (grids 128-512, 8-48 slices, "
+                                f"128-1024 frames, plane wave or probe)"), "slice_steps": steps_total},
     }
 
 
@@ -242,9 +248,9 @@ def bench_c5(args):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"],
-                    help="c2: the 512^2 x 32 x 1024 plane-wave workload (default); c4: uneven-job "
-                         "batch; c5: serving")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c4small", "c5"],
+                    help="c2: the 512^2 x 32 x 1024 plane-wave workload (default); c3: the spectrum "
+                         "image; c4: uneven-job batch (c4small: the same on small grids); c5: serving")
     ap.add_argument("--jobs", type=int, default=64)
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--requests", type=int, default=120)
@@ -274,7 +280,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    if args.workload == "c4":
+    if args.workload in ("c4", "c4small"):
         print(json.dumps(bench_c4(args)), flush=True)
         return
     if args.workload == "c5":

@@ -869,11 +869,16 @@ k_row_r8(PassTable tab) {
       if (yy >= a.pny) yy -= a.pny;
       const float* vrow =
           a.V + (((size_t)fl * a.v_slices + (a.slice - a.v_slice0)) * a.pny + yy) * (size_t)a.pnx;
+      if (ox == 0 && a.pnx == N) {   // plane wave, or a window at the origin: no wrap
 #pragma unroll
-      for (int r = 0; r < 8; ++r) {
-        int xx = ox + t + r * G;
-        if (xx >= a.pnx) xx -= a.pnx;
-        vv[r] = vrow[xx];
+        for (int r = 0; r < 8; ++r) vv[r] = vrow[t + r * G];
+      } else {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          int xx = ox + t + r * G;
+          if (xx >= a.pnx) xx -= a.pnx;
+          vv[r] = vrow[xx];
+        }
       }
     }
   };
