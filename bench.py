@@ -133,6 +133,15 @@ def bench_c4(args):
     t_batch1 = time.perf_counter() - t0
     del os.environ["TACAW_BATCH_STREAMS"]
     print(f"[bench] batched on one stream: {t_batch1:.3f} s", file=sys.stderr, flush=True)
+    # the batched launch sequence captured once as a HIP graph, then replayed
+    with tacaw.Batch(handles) as graph:
+        graph.launch(stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        graph.launch(stream)
+        torch.cuda.synchronize()
+        t_graph = time.perf_counter() - t0
+    print(f"[bench] batched, graph replay: {t_graph:.3f} s", file=sys.stderr, flush=True)
     for mb in os.environ.get("BENCH_LANE_MB_SWEEP", "").split():
         os.environ["TACAW_BATCH_LANE_MB"] = mb
         for ns in ("1", "4"):
@@ -151,6 +160,7 @@ def bench_c4(args):
         "value": steps_total / t_batch, "unit": "slice-steps/s", "n_gpus": 1,
         "plain_value": steps_total / t_plain, "speedup_vs_plain": t_plain / t_batch,
         "ms_batched": t_batch * 1e3, "ms_plain": t_plain * 1e3, "ms_batched_one_stream": t_batch1 * 1e3,
+        "ms_batched_graph_replay": t_graph * 1e3, "speedup_graph_vs_plain": t_plain / t_graph,
         "higher_is_better": True,
         "dtype": "fp32", "data": "synthetic",
         "config": {"workload": (f"{args.jobs} seeded uneven small jobs (grids 64-128, 8-48 slices, 16-96 "

@@ -217,6 +217,21 @@ tacaw_status tacaw_run(tacaw_job* job, void* hip_stream);
  * tacaw_run result bit for bit. */
 tacaw_status tacaw_run_batch(tacaw_job* const* jobs, int n_jobs, void* hip_stream);
 
+/* Captured batch (the benchmark spec's graph-captured frame loops for uneven
+ * jobs): the whole batched launch sequence of a fixed set of jobs, exactly as
+ * tacaw_run_batch enqueues it, recorded once as one HIP graph and replayed on
+ * any stream, so a repeated batch costs one graph launch instead of thousands
+ * of kernel launches.  Capture materialises every job first (allocation and
+ * uploads stay outside the graph) and records nothing while context timing is
+ * on.  The graph holds the jobs' device addresses: the jobs must outlive the
+ * batch, and a launch after a job's buffers were reallocated (a serving-loop
+ * submission, for one) is refused with EINVAL.  Results after a launch are
+ * bitwise those of tacaw_run.  Errors as tacaw_run_batch. */
+typedef struct tacaw_batch tacaw_batch;
+tacaw_status tacaw_batch_capture(tacaw_job* const* jobs, int32_t n_jobs, tacaw_batch** out);
+tacaw_status tacaw_batch_launch(tacaw_batch* batch, void* hip_stream);
+tacaw_status tacaw_batch_destroy(tacaw_batch* batch);
+
 /* Autotuner: time the row-pass variants (rows per workgroup, and for grids
  * of 64 to 1024 register-resident kernels with one or two rows in flight) and
  * the column-pass variants (tile widths, and for 64 to 1024 rows

@@ -209,15 +209,15 @@ void load_tune_cache(tacaw_ctx* c) {
 
 }  // namespace
 
-extern "C" {
+namespace {
 
-tacaw_status tacaw_run_batch(tacaw_job* const* jobs, int n_jobs, void* hip_stream) {
-  clear_error();
+// Checks of a batch: jobs of one context, none twice, none in the serving loop.
+tacaw_status check_batch(tacaw_job* const* jobs, int n_jobs) {
   if (!jobs || n_jobs < 1) {
     set_error("need at least one job");
     return TACAW_EINVAL;
   }
-  tacaw_ctx* c = jobs[0]->ctx;
+  tacaw_ctx* c = jobs[0] ? jobs[0]->ctx : nullptr;
   for (int i = 0; i < n_jobs; ++i) {
     if (!jobs[i] || jobs[i]->ctx != c) {
       set_error("job %d is NULL or belongs to another context", i);
@@ -234,15 +234,16 @@ tacaw_status tacaw_run_batch(tacaw_job* const* jobs, int n_jobs, void* hip_strea
         return TACAW_EINVAL;
       }
   }
-  for (int i = 0; i < n_jobs; ++i) leave_serving_state(jobs[i]);
-  if (hipSetDevice(c->device) != hipSuccess) {
-    set_error("hipSetDevice failed");
-    return TACAW_EDEVICE;
-  }
+  return TACAW_OK;
+}
+
+// Enqueue the batched form of every job on `user` (and the context's batch
+// streams, forked from and joined back to it).  Host-side bookkeeping only;
+// nothing here waits for the device, so a capture of `user` takes it all in.
+tacaw_status enqueue_batch(tacaw_ctx* c, tacaw_job* const* jobs, int n_jobs, hipStream_t user) {
   load_tune_cache(c);
   tacaw_status st = ensure_streams(c);
   if (st != TACAW_OK) return st;
-  hipStream_t user = (hipStream_t)hip_stream;
   // Jobs whose frame batches hold at least TACAW_BATCH_LARGE_MB (default 64)
   // MiB of waves fill the device on their own: they run one after another on
   // the first stream, exactly as the plain form runs them (sharing launches
@@ -333,6 +334,146 @@ tacaw_status tacaw_run_batch(tacaw_job* const* jobs, int n_jobs, void* hip_strea
   (void)hipEventDestroy(start);
   if (st != TACAW_OK) return st;
   for (int i = 0; i < n_jobs; ++i) jobs[i]->last_stream = user;
+  return TACAW_OK;
+}
+
+}  // namespace
+
+// A captured batch: the whole batched launch sequence of a fixed set of jobs
+// as one HIP graph, replayed on any stream.  The graph holds the jobs' device
+// addresses at capture time.
+struct tacaw_batch {
+  tacaw_ctx* ctx = nullptr;
+  std::vector<tacaw_job*> jobs;
+  std::vector<std::vector<const void*>> buffers;   // per job: every device buffer at capture
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+// every device buffer a job's kernels may touch
+std::vector<const void*> job_buffers(const tacaw_job* j) {
+  return {j->d_exit,    j->d_spec,   j->d_V,       j->d_pos,      j->d_species,  j->d_tile_start, j->d_tile_atoms,
+          j->d_coef,    j->d_tw_x,   j->d_tw_y,    j->d_tw_t,     j->d_px,       j->d_py,         j->d_px_last,
+          j->d_py_last, j->d_probe0, j->d_origin,  j->d_rloc,     j->d_count,    j->d_fslice,     j->d_W,
+          j->d_ks_start, j->d_ks_atoms, j->d_kcoef, j->d_tw_px,  j->d_tw_py};
+}
+}  // namespace
+
+extern "C" {
+
+tacaw_status tacaw_run_batch(tacaw_job* const* jobs, int n_jobs, void* hip_stream) {
+  clear_error();
+  tacaw_status st = check_batch(jobs, n_jobs);
+  if (st != TACAW_OK) return st;
+  tacaw_ctx* c = jobs[0]->ctx;
+  for (int i = 0; i < n_jobs; ++i) leave_serving_state(jobs[i]);
+  if (hipSetDevice(c->device) != hipSuccess) {
+    set_error("hipSetDevice failed");
+    return TACAW_EDEVICE;
+  }
+  return enqueue_batch(c, jobs, n_jobs, (hipStream_t)hip_stream);
+}
+
+tacaw_status tacaw_batch_capture(tacaw_job* const* jobs, int32_t n_jobs, tacaw_batch** out) {
+  clear_error();
+  if (!out) {
+    set_error("out is NULL");
+    return TACAW_EINVAL;
+  }
+  *out = nullptr;
+  tacaw_status st = check_batch(jobs, n_jobs);
+  if (st != TACAW_OK) return st;
+  tacaw_ctx* c = jobs[0]->ctx;
+  if (hipSetDevice(c->device) != hipSuccess) {
+    set_error("hipSetDevice failed");
+    return TACAW_EDEVICE;
+  }
+  // allocation and uploads stay outside the graph
+  for (int i = 0; i < n_jobs; ++i)
+    if ((st = materialize(jobs[i], nullptr)) != TACAW_OK) return st;
+  hipStream_t cap = nullptr;
+  if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) {
+    set_error("hipStreamCreate failed");
+    return TACAW_EDEVICE;
+  }
+  bool timing = false;
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    timing = c->timing;
+    c->timing = false;   // no timing events inside the graph
+  }
+  tacaw_batch* b = new tacaw_batch();
+  b->ctx = c;
+  hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    st = enqueue_batch(c, jobs, n_jobs, cap);
+    e = hipStreamEndCapture(cap, &b->graph);
+  }
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    c->timing = timing;
+  }
+  if (st == TACAW_OK && e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+  (void)hipStreamDestroy(cap);
+  if (st != TACAW_OK || e != hipSuccess) {
+    if (st == TACAW_OK) {
+      set_error("batch capture failed: %s", hipGetErrorString(e));
+      st = TACAW_EDEVICE;
+    }
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    delete b;
+    return st;
+  }
+  for (int i = 0; i < n_jobs; ++i) {
+    b->jobs.push_back(jobs[i]);
+    b->buffers.push_back(job_buffers(jobs[i]));
+  }
+  *out = b;
+  return TACAW_OK;
+}
+
+tacaw_status tacaw_batch_launch(tacaw_batch* b, void* hip_stream) {
+  clear_error();
+  if (!b) {
+    set_error("batch is NULL");
+    return TACAW_EINVAL;
+  }
+  tacaw_status st = check_batch(b->jobs.data(), (int)b->jobs.size());
+  if (st != TACAW_OK) return st;
+  for (size_t i = 0; i < b->jobs.size(); ++i) {
+    const tacaw_job* j = b->jobs[i];
+    if (!j->materialized || job_buffers(j) != b->buffers[i]) {
+      set_error("job %zu's device buffers changed since the capture: capture the batch again", i);
+      return TACAW_EINVAL;
+    }
+  }
+  if (hipSetDevice(b->ctx->device) != hipSuccess) {
+    set_error("hipSetDevice failed");
+    return TACAW_EDEVICE;
+  }
+  hipStream_t s = (hipStream_t)hip_stream;
+  const hipError_t e = hipGraphLaunch(b->exec, s);
+  if (e != hipSuccess) {
+    set_error("hipGraphLaunch: %s", hipGetErrorString(e));
+    return TACAW_EDEVICE;
+  }
+  for (tacaw_job* j : b->jobs) {
+    leave_serving_state(j);
+    mark_all_present(j);
+    j->has_result = true;
+    j->last_stream = s;
+  }
+  return TACAW_OK;
+}
+
+tacaw_status tacaw_batch_destroy(tacaw_batch* b) {
+  clear_error();
+  if (!b) return TACAW_OK;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  delete b;
   return TACAW_OK;
 }
 

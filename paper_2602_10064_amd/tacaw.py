@@ -67,7 +67,7 @@ EXPORTED = [
     "tacaw_spectral_diffraction", "tacaw_spectrum_image", "tacaw_spectrum_image_noalloc", "tacaw_dispersion",
     "tacaw_job_set_aberrations", "tacaw_mean_diffraction", "tacaw_adf",
     "tacaw_run_frames", "tacaw_finish", "tacaw_get_exit_frames", "tacaw_put_exit_frames",
-    "tacaw_average_spectra",
+    "tacaw_average_spectra", "tacaw_batch_capture", "tacaw_batch_launch", "tacaw_batch_destroy",
 ]
 
 
@@ -116,6 +116,9 @@ def lib() -> ctypes.CDLL:
         "tacaw_get_exit_frames": [vp, i32, i32, vp, sz, ctypes.c_int],
         "tacaw_put_exit_frames": [vp, i32, i32, vp, sz, ctypes.c_int],
         "tacaw_average_spectra": [P(vp), i32, vp, sz, ctypes.c_int],
+        "tacaw_batch_capture": [P(vp), i32, P(vp)],
+        "tacaw_batch_launch": [vp, vp],
+        "tacaw_batch_destroy": [vp],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -437,6 +440,32 @@ def run_batch(jobs, stream=None):
     """tacaw_run_batch over a list of TacawJob of one context."""
     arr = (ctypes.c_void_p * len(jobs))(*[j.handle.value for j in jobs])
     _check(lib().tacaw_run_batch(arr, len(jobs), _stream_handle(stream)))
+
+
+class Batch:
+    """tacaw_batch: the batched launch sequence of a list of TacawJob,
+    captured once as a HIP graph and replayed with launch()."""
+
+    def __init__(self, jobs):
+        self.jobs = list(jobs)
+        arr = (ctypes.c_void_p * len(self.jobs))(*[j.handle.value for j in self.jobs])
+        h = ctypes.c_void_p()
+        _check(lib().tacaw_batch_capture(arr, len(self.jobs), ctypes.byref(h)))
+        self.handle = h
+
+    def launch(self, stream=None):
+        _check(lib().tacaw_batch_launch(self.handle, _stream_handle(stream)))
+
+    def destroy(self):
+        if self.handle:
+            _check(lib().tacaw_batch_destroy(self.handle))
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.destroy()
 
 
 def footprint(job) -> int:

@@ -73,6 +73,57 @@ def test_run_batch_equals_plain_bitwise(tacaw, monkeypatch, large_mb):
             h.destroy()
 
 
+def test_run_batch_against_oracle(tacaw, oracle):
+    """The batched executor's results against the FP64 oracle (not only
+    against the plain form), for the small jobs of the uneven set: three
+    64^2 jobs of different frame and slice counts, two 96 x 64 jobs, probes,
+    and windows cut from a larger potential grid."""
+    from tests.parity import check_parity
+    jobs = uneven_jobs()[:7]
+    with tacaw.Context(0) as ctx:
+        hs = [tacaw.TacawJob(ctx, j) for j in jobs]
+        tacaw.run_batch(hs)
+        for h, job in zip(hs, jobs):
+            ref_ex = oracle.exit_waves(job)
+            ref_spec = oracle.tacaw_spectrum(ref_ex, two_sided=job.two_sided)
+            check_parity(h.exit_waves(), h.spectrum(), ref_ex, ref_spec, job.two_sided, f"batched {job.name}")
+        for h in hs:
+            h.destroy()
+
+
+def test_captured_batch_replays_bitwise(tacaw, monkeypatch):
+    """The batched launch sequence captured once as a HIP graph and replayed
+    three times on a torch stream, with eager work and synchronisation in
+    between: every replay equals the plain per-job results bit for bit.  A
+    launch after a job's buffers were reallocated is refused."""
+    import torch
+    jobs = uneven_jobs()
+    monkeypatch.setenv("TACAW_FB", "5")
+    with tacaw.Context(0) as ctx:
+        ref = plain_results(tacaw, ctx, jobs)
+        hs = [tacaw.TacawJob(ctx, j) for j in jobs]
+        s = torch.cuda.Stream()
+        with tacaw.Batch(hs) as b:
+            for rep in range(3):
+                b.launch(stream=s)
+                s.synchronize()
+                for h, (ex, sp) in zip(hs, ref):
+                    assert np.array_equal(h.spectrum().view(np.uint32), sp.view(np.uint32)), (rep, h.job.name)
+                    assert np.array_equal(h.exit_waves().view(np.uint32), ex.view(np.uint32)), (rep, h.job.name)
+                hs[0].run()                               # eager work between replays
+                x = torch.randn(1 << 20, device="cuda")
+                torch.cuda.synchronize()
+                assert float(x.abs().sum()) > 0
+            # serving-loop submission reallocates a job's buffers: the graph is stale
+            hs[1].submit()
+            hs[1].wait()
+            with pytest.raises(tacaw.TacawError) as e:
+                b.launch(stream=s)
+            assert e.value.status == 1
+        for h in hs:
+            h.destroy()
+
+
 def test_graph_replay_matches_eager(tacaw):
     import torch
     job = w.c1_tiny(n_frames=32)
