@@ -23,6 +23,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
+FP32_MFMA_PEAK_TFLOPS = 157.3
 WORKLOAD = ("12x12x8 diamond-cubic C/Si supercell (9216 atoms, 50/50 Z=6/14), 512x512 grid, "
             "32 slices of 1.3575 A, 100 kV plane wave, 1024 frames at 2 fs, seeded harmonic "
             "phonons (32 modes, 0.08 A rms), 512 one-sided energy bins")
@@ -275,6 +276,9 @@ def main():
     ap.add_argument("--timing-every", type=int, default=7,
                     help="time one launch in this many of each timed class (7: coprime with the "
                          "slice count, so the sampled launches rotate over the slices)")
+    ap.add_argument("--kspace", action="store_true",
+                    help="c2 on the paper's reciprocal-space potential route (seeded 3 Lorentzian + 3 Gaussian "
+                         "coefficients); the structure-factor kernel's MFMA roofline is reported")
     ap.add_argument("--no-host", action="store_true",
                     help="skip the host-transfer figures (profiling runs: they add copy kernels and a run)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -301,6 +305,8 @@ def main():
         job = workloads.c3_probe(n_frames=min(args.frames, 256))
     else:
         job = workloads.c2_plain(n_frames=args.frames)
+    if args.kspace:      # the paper's reciprocal-space potential route, seeded coefficients
+        job = workloads.with_kirkland(job, seed=2)
     t_gen = time.perf_counter() - t_gen
     print(f"[bench] inputs generated in {t_gen:.1f} s", file=sys.stderr, flush=True)
 
@@ -318,6 +324,8 @@ def main():
     # timed region: one launch in --timing-every of the two HBM passes (the
     # roofline candidates) records start/end events; the rest run without
     timed_classes = {"all": None, "passes": ("row", "col"), "none": ()}[args.timing]
+    if args.kspace and timed_classes is not None and timed_classes:
+        timed_classes = timed_classes + ("splat",)    # the structure-factor kernel is the candidate
     ctx.timing_select(timed_classes, args.timing_every)
     ctx.timing_enable(args.timing != "none")
     torch.cuda.synchronize()
@@ -335,7 +343,8 @@ def main():
     ctx.timing_enable(True)
     j.run(stream=stream)
     torch.cuda.synchronize()
-    breakdown = {k: round(ctx.timing_get(k)[0], 3) for k in ("splat", "row", "col", "time")}
+    breakdown_full = {k: ctx.timing_get(k) for k in ("splat", "row", "col", "time")}
+    breakdown = {k: round(v[0], 3) for k, v in breakdown_full.items()}
     ctx.timing_enable(False)
 
     # host transfers, outside the timed region (c2 only: the c3 spectrum is
@@ -380,6 +389,24 @@ def main():
     # roofline of the dominant kernel class: the timed class with the largest
     # total time in the timed region
     timed = {k: v for k, v in timing.items() if v[1] > 0 and k in ("row", "col", "splat")}
+    roofline_kpot = None
+    if args.kspace and "splat" in timed:
+        # structure factors on MFMA: 8 real flops (one complex multiply-add)
+        # per atom and computed k point (rows 0 .. ny/2 of the potential grid)
+        # per frame, every atom lying in one slice; one launch covers a frame
+        # batch and a group of slices (the breakdown step, with every launch
+        # timed, counts the launches of a step)
+        ms, n = timed.pop("splat")
+        avg_ms = ms / n
+        pnx, pny = job.pot_nx or job.nx, job.pot_ny or job.ny
+        flops_step = 8.0 * (pny // 2 + 1) * pnx * job.n_atoms * job.n_frames
+        flops_launch = flops_step / breakdown_full["splat"][1]
+        tflops = flops_launch / (avg_ms * 1e-3) / 1e12
+        roofline_kpot = {"bound": "mfma", "kernel": "structure factors (k_kpot)", "achieved": round(tflops, 2),
+                         "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(tflops / FP32_MFMA_PEAK_TFLOPS, 4), "traffic": None,
+                         "avg_launch_ms": round(avg_ms, 4), "launches": n,
+                         "algorithmic_flops_per_launch": flops_launch}
     roofline = None
     if timed:
         dom = max(timed, key=lambda k: timed[k][0])
@@ -440,7 +467,8 @@ def main():
         "vs_baseline": None,
         "dtype": "fp32",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD_C3 if args.workload == "c3" else WORKLOAD,
+        "config": {"workload": (WORKLOAD_C3 if args.workload == "c3" else WORKLOAD) +
+                               (", reciprocal-space potentials (paper's route)" if args.kspace else ""),
                    "grid": [job.nx, job.ny], "slices": job.n_slices,
                    "frames": job.n_frames, "probes": job.n_probes, "atoms": job.n_atoms,
                    "precision": "complex64 (FP32) multislice and time FFT, FP64 frame mean"},
@@ -450,6 +478,7 @@ def main():
         "timed_region_kernel_ms_per_step": kernel_ms,
         "host_transfers": host,
         "roofline": roofline,
+        **({"roofline_kpot": roofline_kpot} if roofline_kpot else {}),
         "cpu_baseline": cpu,
     }
     j.destroy()
