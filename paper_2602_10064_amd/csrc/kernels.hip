@@ -203,20 +203,78 @@ __device__ __forceinline__ float profile(int node, int ipos, float fpos, int n, 
 // sequence are fixed, so the result is deterministic.
 // IZ: per-frame slice binning (lanes carry a frame-slice table); a separate
 // instantiation keeps the check out of the default kernel.
+// Profile fill of one round: NPL nodes per lane.  Lanes form 64 / NPL parts
+// of NPL lanes (one pair each); the first half of the parts fill column
+// profiles (unit amplitude), the second half row profiles (the term's
+// amplitude), node-major in LDS.  Pairs mp .. mp4 - 1 get zeros (the MFMA
+// steps take four pairs at a time).
+template <int NPL, int PS, bool IZ>
+__device__ __forceinline__ void splat_fill(float (*gx)[PS], float (*gy)[PS], int lane, int mp, int mp4,
+                                           const AtomPos& p, const float* c, int at, const SplatArgs& a, int s,
+                                           size_t frame_off, int tx0, int ty0, bool simple_x, bool simple_y) {
+  const int pr = lane % NPL;                      // pair of this lane
+  const int part = lane / NPL;
+  const bool along_y = part >= 32 / NPL;          // lanes 0-31: column profiles, 32-63: row profiles
+  const int nbase = (part % (32 / NPL)) * NPL;    // first profile node of this lane
+  float* dst = along_y ? &gy[nbase][pr] : &gx[nbase][pr];   // node nbase + j at dst[j * PS]
+  if (pr < mp) {
+    // per-frame binning: an atom outside this slice in this frame adds nothing
+    const bool gone = IZ && a.fslice != nullptr && at >= 0 && a.fslice[frame_off + at] != s;
+    // lanes 0-31 and 32-63 run the same instructions on their own axis
+    const int n_ax = along_y ? a.pny : a.pnx;
+    const int node0 = along_y ? ty0 : tx0;
+    const int ip = along_y ? p.iy : p.ix;
+    const float fp = along_y ? p.fy : p.fx;
+    const float amp = along_y ? c[0] : 1.f;
+    const float e2 = along_y ? c[2] : c[1];
+    const float rc = along_y ? c[4] : c[3];
+    if (along_y ? simple_y : simple_x) {
+      int o = node0 - ip;
+      if (o >= n_ax - n_ax / 2) o -= n_ax;
+      if (o < -(n_ax / 2)) o += n_ax;
+      // node j sits at d = j - u pixels from the atom, u = f - o.  Every
+      // node of a tile the term's box reaches gets the exact value (beyond
+      // the radius it is below 1e-8 of the peak, or underflows to 0; only
+      // this image reaches the tile), which saves the cutoff test.  The
+      // value amp 2^(-e2 d^2) is 2^(A x^2 + B x + C) with x = j - NPL/2
+      // (centred, so the terms stay small), A = -e2, B = 2 e2 u',
+      // C = log2(amp) - e2 u'^2, u' = u - NPL/2: two FMAs and one exp2
+      // per node.
+      const float up = fp - (float)(o + nbase) - (float)(NPL / 2);
+      const float la = along_y ? c[5] : 0.f;
+      const float qa = -e2, qb = 2.f * e2 * up;
+      const float qc = IZ && gone ? -INFINITY : fmaf(-e2 * up, up, la);
+#pragma unroll
+      for (int x = 0; x < NPL; ++x) {
+        const float xc = (float)(x - NPL / 2);
+        dst[x * PS] = __builtin_amdgcn_exp2f(fmaf(qa, xc * xc, fmaf(qb, xc, qc)));
+      }
+    } else {
+      const int img = along_y ? a.img_y : a.img_x;
+      const float amp_f = IZ && gone ? 0.f : amp;
+      for (int x = 0; x < NPL; ++x)
+        dst[x * PS] = amp_f * profile(node0 + nbase + x, ip, fp, n_ax, e2, rc, img);
+    }
+  } else if (pr < mp4) {
+#pragma unroll
+    for (int x = 0; x < NPL; ++x) dst[x * PS] = 0.f;
+  }
+}
+
 template <int MP, bool IZ>
-__global__ void __launch_bounds__(256) k_splat(SplatTable tab) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_splat(SplatTable tab) {
   // MP pairs per round (32 or 16).  Lanes split into 64 / MP parts of MP
   // lanes; each part fills NPL = MP nodes of the column (x) or row (y)
-  // profiles of the round's pairs.
+  // profiles of the round's pairs (fewer nodes per lane in a short last
+  // round).
   static_assert(MP == 32 || MP == 16, "round sizes 32 and 16");
-  constexpr int NPL = MP;                 // profile nodes per lane
-  constexpr int PARTS_PER_AXIS = 32 / MP;
-  // profiles in LDS as [node][pair], rows of PS floats: a fill instruction
-  // (32 lanes: consecutive pairs of one or two nodes) and an MFMA operand
-  // read (16 nodes x 2 pairs) both hit 32 distinct banks
+  constexpr int NPL = MP;                 // profile nodes per lane in a full round
+  // profiles in LDS as [node][pair], rows of PS floats: a full round's fill
+  // instruction (32 lanes: consecutive pairs of one or two nodes) and an
+  // MFMA operand read (16 nodes x 2 pairs) both hit 32 distinct banks
   constexpr int PS = MP == 32 ? MP + 2 : MP + 1;
   static_assert(SPLAT_TX == 32 && SPLAT_TY == 32, "MFMA tiling assumes 32 x 32 tiles");
-  __shared__ float gxs[4][SPLAT_TX][PS];
+  __shared__ __align__(16) float gxs[4][SPLAT_TX][PS];
   __shared__ float gys[4][SPLAT_TY][PS];
   __shared__ float coef_s[SPLAT_MAX_SPECIES * N_GAUSS * COEF_STRIDE];
 
@@ -250,16 +308,12 @@ __global__ void __launch_bounds__(256) k_splat(SplatTable tab) {
   const bool simple_y = a.img_y == 0 && 2 * (a.rcy + SPLAT_TY + 2) < a.pny;
   float (*gx)[PS] = gxs[wave];
   float (*gy)[PS] = gys[wave];
-  const int pr = lane % MP;                       // pair of this lane
-  const int part = lane / MP;
-  const bool along_y = part >= PARTS_PER_AXIS;    // lanes 0-31: column profiles, 32-63: row profiles
-  const int nbase = (part % PARTS_PER_AXIS) * NPL;  // first profile node of this lane
-  float* dst = along_y ? &gy[nbase][pr] : &gx[nbase][pr];   // node nbase + j at dst[j * PS]
+  const int pr = lane % MP;   // pair of this lane in a full round (positions are loaded for it)
   typedef float v4f __attribute__((ext_vector_type(4)));
 
   // per round: this lane's atom and coefficients are the same for every
   // frame; positions of the first PRE rounds are prefetched one frame ahead
-  constexpr int PRE = 4;
+  constexpr int PRE = 2;
   int atom_r[PRE];
   int coef_r[PRE];
   AtomPos pn[PRE];
@@ -287,14 +341,14 @@ __global__ void __launch_bounds__(256) k_splat(SplatTable tab) {
       const int mp = min(MP, ce - c0);
       const int mp4 = (mp + 3) & ~3;
       AtomPos p{};
-      const float* c = coef;
+      int coff = 0;  // this lane's coefficient offset
       int at = -1;   // this lane's atom (sorted index)
       if (r < PRE) {
 #pragma unroll
         for (int q = 0; q < PRE; ++q)
           if (q == r) {
             p = pn[q];
-            c = coef + coef_r[q];
+            coff = coef_r[q];
             at = atom_r[q];
             if (atom_r[q] >= 0 && k + 1 < nf) pn[q] = a.pos[frame_off + a.n_atoms + atom_r[q]];
           }
@@ -302,51 +356,29 @@ __global__ void __launch_bounds__(256) k_splat(SplatTable tab) {
         const int entry = a.tile_atoms[c0 + pr];
         at = entry >> 3;
         p = a.pos[frame_off + at];
-        c = coef + (a.species[at] * N_GAUSS + (entry & 7)) * COEF_STRIDE;
+        coff = (a.species[at] * N_GAUSS + (entry & 7)) * COEF_STRIDE;
       }
-      // per-frame binning: an atom outside this slice in this frame adds nothing
-      const bool gone = IZ && a.fslice != nullptr && at >= 0 && a.fslice[frame_off + at] != s;
       wave_lds_sync();  // the previous round's MFMA reads are done
-      if (pr < mp) {
-        // lanes 0-31 and 32-63 run the same instructions on their own axis
-        // (column profile: unit amplitude; row profile: the term's amplitude)
-        const int n_ax = along_y ? a.pny : a.pnx;
-        const int node0 = along_y ? ty0 : tx0;
-        const int ip = along_y ? p.iy : p.ix;
-        const float fp = along_y ? p.fy : p.fx;
-        const float amp = along_y ? c[0] : 1.f;
-        const float e2 = along_y ? c[2] : c[1];
-        const float rc = along_y ? c[4] : c[3];
-        if (along_y ? simple_y : simple_x) {
-          int o = node0 - ip;
-          if (o >= n_ax - n_ax / 2) o -= n_ax;
-          if (o < -(n_ax / 2)) o += n_ax;
-          // node j sits at d = j - u pixels from the atom, u = f - o.  Every
-          // node of a tile the term's box reaches gets the exact value (beyond
-          // the radius it is below 1e-8 of the peak, or underflows to 0; only
-          // this image reaches the tile), which saves the cutoff test.  The
-          // value amp 2^(-e2 d^2) is 2^(A x^2 + B x + C) with x = j - NPL/2
-          // (centred, so the terms stay small), A = -e2, B = 2 e2 u',
-          // C = log2(amp) - e2 u'^2, u' = u - NPL/2: two FMAs and one exp2
-          // per node.
-          const float up = fp - (float)(o + nbase) - (float)(NPL / 2);
-          const float la = along_y ? c[5] : 0.f;
-          const float qa = -e2, qb = 2.f * e2 * up;
-          const float qc = IZ && gone ? -INFINITY : fmaf(-e2 * up, up, la);
-#pragma unroll
-          for (int x = 0; x < NPL; ++x) {
-            const float xc = (float)(x - NPL / 2);
-            dst[x * PS] = __builtin_amdgcn_exp2f(fmaf(qa, xc * xc, fmaf(qb, xc, qc)));
-          }
-        } else {
-          const int img = along_y ? a.img_y : a.img_x;
-          const float amp_f = IZ && gone ? 0.f : amp;
-          for (int x = 0; x < NPL; ++x)
-            dst[x * PS] = amp_f * profile(node0 + nbase + x, ip, fp, n_ax, e2, rc, img);
-        }
-      } else if (pr < mp4) {
-#pragma unroll
-        for (int x = 0; x < NPL; ++x) dst[x * PS] = 0.f;
+      // A round of at most MP/2 (MP/4) pairs fills with MP/2 (MP/4) nodes per
+      // lane: lane l takes pair l mod MP/2 from lane l mod MP/2, which holds
+      // it (the same instruction stream, a quarter or half of the exp2 work)
+      if (mp > MP / 2) {
+        splat_fill<NPL, PS, IZ>(gx, gy, lane, mp, mp4, p, coef + coff, at, a, s, frame_off, tx0, ty0, simple_x,
+                                simple_y);
+      } else {
+        const int src = lane % (mp > MP / 4 || MP / 4 < 8 ? MP / 2 : MP / 4);
+        p.ix = __shfl(p.ix, src);
+        p.iy = __shfl(p.iy, src);
+        p.fx = __shfl(p.fx, src);
+        p.fy = __shfl(p.fy, src);
+        coff = __shfl(coff, src);
+        at = __shfl(at, src);
+        if (mp > MP / 4 || MP / 4 < 8)
+          splat_fill<NPL / 2, PS, IZ>(gx, gy, lane, mp, mp4, p, coef + coff, at, a, s, frame_off, tx0, ty0,
+                                      simple_x, simple_y);
+        else
+          splat_fill<(MP / 4 < 8 ? 8 : NPL / 4), PS, IZ>(gx, gy, lane, mp, mp4, p, coef + coff, at, a, s,
+                                                         frame_off, tx0, ty0, simple_x, simple_y);
       }
       wave_lds_sync();
       // V[r][c] += sum_k gy[k][r] gx[k][c] over four 16 x 16 quarters; A is 16 x 4
@@ -363,13 +395,40 @@ __global__ void __launch_bounds__(256) k_splat(SplatTable tab) {
     }
     // D layout: lane holds rows 4 (lane / 16) + j, j < 4, of column lane % 16
     float* out = a.V + ((size_t)fl * nsl + sl) * a.pny * a.pnx;
+    if (MP == 32 && a.pnx % 4 == 0) {
+      // through this wavefront's profile buffer (32 x 32 floats, rows of 32,
+      // bit 4 of the column flipped in odd quads of rows so that both 16-lane
+      // groups of a write hit distinct banks), then whole 128-byte rows with
+      // 16-byte stores: eight lanes per row, eight rows per instruction
+      float* T = &gx[0][0];
+      wave_lds_sync();  // the last round's MFMA reads are done
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int x = tx0 + 16 * (q & 1) + lane % 16;
+      for (int q = 0; q < 4; ++q)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int y = ty0 + 16 * (q >> 1) + 4 * (lane / 16) + j;
-        if (y < a.pny && x < a.pnx) out[(size_t)y * a.pnx + x] = acc[q][j];
+        for (int j = 0; j < 4; ++j) {
+          const int row = 16 * (q >> 1) + 4 * (lane / 16) + j;
+          const int col = 16 * (q & 1) + lane % 16;
+          T[row * 32 + (col ^ (((row >> 2) & 1) << 4))] = acc[q][j];
+        }
+      wave_lds_sync();
+      const int col = 4 * (lane % 8);
+      const int x = tx0 + col;
+#pragma unroll
+      for (int k8 = 0; k8 < 4; ++k8) {
+        const int row = lane / 8 + 8 * k8;
+        const float4 v = *reinterpret_cast<const float4*>(&T[row * 32 + (col ^ (((row >> 2) & 1) << 4))]);
+        const int y = ty0 + row;
+        if (y < a.pny && x < a.pnx) *reinterpret_cast<float4*>(&out[(size_t)y * a.pnx + x]) = v;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int x = tx0 + 16 * (q & 1) + lane % 16;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int y = ty0 + 16 * (q >> 1) + 4 * (lane / 16) + j;
+          if (y < a.pny && x < a.pnx) out[(size_t)y * a.pnx + x] = acc[q][j];
+        }
       }
     }
   }
@@ -2093,7 +2152,10 @@ hipError_t launch_col_lanes(const PassLane* lanes, int n, int variant, hipStream
     variant = 2;
   }
   if (variant == 3) {
-    if (lanes[0].a.ny == 512 && lanes[0].a.nx % C8<512, 1>::CT == 0) return col_r8_launch<512, 1>(t, s);
+    // 16-column tiles: whole 128-byte row segments per tile row
+    const int ny = lanes[0].a.ny, nx = lanes[0].a.nx;
+    if (ny == 512 && nx % C8<512, 1>::CT == 0) return col_r8_launch<512, 1>(t, s);
+    if (ny == 256 && nx % C8<256, 1>::CT == 0) return col_r8_launch<256, 1>(t, s);
     variant = 2;
   }
   if (variant == 2) {

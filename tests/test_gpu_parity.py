@@ -260,6 +260,18 @@ def test_512_rows_narrow_grid(tacaw, ctx, oracle, monkeypatch, variant):
     check_job(tacaw, ctx, oracle, job)
 
 
+@pytest.mark.parametrize("variant", ["2", "3", "4"])
+def test_256_rows_column_kernels(tacaw, ctx, oracle, monkeypatch, variant):
+    # 256 rows: the register column kernel on 8-column tiles (2), 16-column
+    # tiles (3) and 8-column tiles with two LDS buffers (4); probes in windows
+    # of a larger potential grid, ragged frame batches
+    monkeypatch.setenv("TACAW_COL_VARIANT", variant)
+    monkeypatch.setenv("TACAW_FB", "3")
+    job = w.random_small_job(48, nx=48, ny=256, n_slices=3, n_frames=10, cell=(6.0, 32.0, 4.0), n_atoms=24,
+                             aperture_mrad=25.0, n_probes=3, pot_grid=(64, 320))
+    check_job(tacaw, ctx, oracle, job)
+
+
 def test_splat_rounds_of_16(tacaw, ctx, oracle, monkeypatch):
     # potentials built in rounds of 16 (atom, term) pairs: same values as
     # rounds of 32 up to the order of the FP32 sums, parity with the oracle
