@@ -239,6 +239,7 @@ def bench_c5(args):
     elapsed = max(finished_at) - start
     lat = np.array(lat)
     lib_lat = np.array(lib_lat)
+    shared, grouped = ctx.serve_stats()
     ctx.close()
     return {
         "metric": "slice-steps/sec (grid-pts*slices*frames/s) + p50/p99 request latency",
@@ -249,7 +250,8 @@ def bench_c5(args):
         "p50_job_create_ms": float(np.percentile(create_ms, 50)),
         "p99_job_create_ms": float(np.percentile(create_ms, 99)),
         "requests": int(args.requests), "rate_per_s": args.rate, "elapsed_s": elapsed,
-        "big_requests": int(big.sum()), "higher_is_better": True, "dtype": "fp32", "data": "synthetic",
+        "big_requests": int(big.sum()), "shared_pass_launches": int(shared), "requests_in_shared_launches": int(grouped),
+        "higher_is_better": True, "dtype": "fp32", "data": "synthetic",
         "latency": "scheduled arrival -> spectrum in host memory, job creation (planning, uploads) included",
         "config": {"workload": "Poisson arrivals of seeded uneven jobs (90%) and 1024^2 x 2048-frame "
                                "jobs (10%), admission by device-memory footprint with backfill, continuous "

@@ -246,7 +246,12 @@ tacaw_status tacaw_autotune(tacaw_job* job, void* hip_stream, int* row_variant, 
 
 /* Serving form: hand the job to the context's continuous-batching loop.
  * The loop admits it once its footprint fits the budget next to the jobs
- * already resident and interleaves its slice steps with theirs. */
+ * already resident and interleaves its slice steps with theirs.  Jobs whose
+ * frame batches are small (under TACAW_BATCH_LARGE_MB MiB of waves) share
+ * launches with the other running jobs of their grid size: one launch
+ * advances one frame batch of each by one slice.  Larger jobs run on their
+ * own stream, one frame batch in flight, overlapping the others.  The result
+ * is bitwise the one the job gets alone. */
 tacaw_status tacaw_submit(tacaw_ctx* ctx, tacaw_job* job);
 
 /* *done = 1 once a submitted job has its spectrum (or was cancelled). */
@@ -263,6 +268,12 @@ tacaw_status tacaw_cancel(tacaw_job* job);
  * admission (queued_ms) and from submit to the spectrum being ready on the
  * device (total_ms), in milliseconds.  ENOTREADY before it finishes. */
 tacaw_status tacaw_job_latency(const tacaw_job* job, double* queued_ms, double* total_ms);
+
+/* Counters of the context's serving loop since the context was created:
+ * row and column pass launches that served more than one job
+ * (*shared_launches), and served jobs that ran in shared launches
+ * (*grouped_jobs).  Either pointer may be NULL. */
+tacaw_status tacaw_serve_stats(tacaw_ctx* ctx, int64_t* shared_launches, int64_t* grouped_jobs);
 
 /* Copy the spectrum I[p][m][ky][kx] (float32, n = n_probes * M * ny * nx,
  * M = F/2 or F) into dst, a host pointer or (dst_on_device != 0) a device

@@ -37,11 +37,6 @@ using namespace tacaw;
 
 namespace {
 
-struct BLane {
-  tacaw_job* job;
-  int f0, fb, slice;
-};
-
 tacaw_status ensure_streams(tacaw_ctx* c) {
   for (auto& st : c->batch_streams)
     if (!st && hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
@@ -78,115 +73,158 @@ SplatArgs splat_args(tacaw_job* j, int f0, int fb, int slice) {
   return sa;
 }
 
+}  // namespace
+
+namespace tacaw {
+
+// Jobs whose frame batches hold at least TACAW_BATCH_LARGE_MB (default 64)
+// MiB of waves fill the device on their own and run as the plain form runs
+// them (sharing launches would only make the working set outgrow the
+// last-level cache); jobs on the reciprocal-space potential route build their
+// potentials with their own launch sequence.  The others share launches.
+bool shares_launches(const tacaw_job* j) {
+  double large_mb = 64.0;
+  if (const char* e = getenv("TACAW_BATCH_LARGE_MB")) large_mb = atof(e);
+  const HostPlan& hp = j->hp;
+  const double wave_mb = (double)hp.fb * hp.P * hp.nx * hp.ny * 8.0 / (1 << 20);
+  return wave_mb < large_mb && !hp.kspace;
+}
+
 // One group of same-grid jobs on one stream, advanced one iteration at a
 // time: each iteration launches the potentials of the lanes that start a
 // slice group, then one row pass and one column pass over all active lanes.
-struct GroupRun {
-  tacaw_ctx* c = nullptr;
-  hipStream_t s = nullptr;
-  std::deque<BLane> pending;
-  std::vector<BLane> active;
-  std::map<tacaw_job*, int> left;  // frame batches not finished per job
-  int rv = 0, cv = 0;
+LaneGroup::LaneGroup(tacaw_ctx* ctx, hipStream_t stream, int nx, int ny, bool serving_)
+    : c(ctx), s(stream), serving(serving_) {
+  rv = row_variant_for(c, nx);
+  cv = col_variant_for(c, ny);
+}
 
-  GroupRun(tacaw_ctx* ctx, const std::vector<tacaw_job*>& jobs, hipStream_t stream) : c(ctx), s(stream) {
-    for (tacaw_job* j : jobs) {
-      for (int f0 = 0; f0 < j->hp.F; f0 += j->hp.fb) pending.push_back({j, f0, std::min(j->hp.fb, j->hp.F - f0), 0});
-      left[j] = (j->hp.F + j->hp.fb - 1) / j->hp.fb;
+void LaneGroup::add(tacaw_job* j) {
+  for (int f0 = 0; f0 < j->hp.F; f0 += j->hp.fb) pending.push_back({j, f0, std::min(j->hp.fb, j->hp.F - f0), 0});
+  left[j] = (j->hp.F + j->hp.fb - 1) / j->hp.fb;
+}
+
+bool LaneGroup::has(const tacaw_job* j) const { return left.count(const_cast<tacaw_job*>(j)) > 0; }
+
+bool LaneGroup::drop(tacaw_job* j) {
+  if (!has(j)) return true;
+  for (auto it = pending.begin(); it != pending.end();) it = it->job == j ? pending.erase(it) : it + 1;
+  for (auto& l : active)
+    if (l.job == j) {
+      dropped.insert(j);   // its lane ends with the frame batch in flight; no time stage
+      return false;
     }
-    rv = row_variant_for(c, jobs[0]->hp.nx);
-    cv = col_variant_for(c, jobs[0]->hp.ny);
+  left.erase(j);
+  return true;
+}
+
+// waves and one potential slice of a lane's frame batch
+static double lane_bytes(const LaneGroup::Lane& l) {
+  const HostPlan& hp = l.job->hp;
+  return (double)l.fb * ((double)hp.P * hp.nx * hp.ny * 8.0 + (double)hp.pnx * hp.pny * 4.0);
+}
+
+tacaw_status LaneGroup::step(std::vector<tacaw_job*>* finished) {
+  // fill free lanes: at most one lane per job (a job has one potential
+  // buffer), and while the lanes' waves fit the working-set target
+  // (TACAW_BATCH_LANE_MB, default 256: the last-level cache), at least one
+  const char* e = getenv("TACAW_BATCH_LANE_MB");
+  const double cap = (e ? atof(e) : 256.0) * (1 << 20);
+  double in_use = 0.0;
+  for (auto& l : active) in_use += lane_bytes(l);
+  for (auto it = pending.begin(); it != pending.end() && (int)active.size() < MAX_LANES;) {
+    bool busy = false;
+    for (auto& l : active) busy |= l.job == it->job;
+    if (busy) {
+      ++it;
+      continue;
+    }
+    if (!active.empty() && in_use + lane_bytes(*it) > cap) break;
+    in_use += lane_bytes(*it);
+    active.push_back(*it);
+    it = pending.erase(it);
   }
-  bool done() const { return pending.empty() && active.empty(); }
-
-  // waves and one potential slice of a lane's frame batch
-  static double lane_bytes(const BLane& l) {
-    const HostPlan& hp = l.job->hp;
-    return (double)l.fb * ((double)hp.P * hp.nx * hp.ny * 8.0 + (double)hp.pnx * hp.pny * 4.0);
+  const int n = (int)active.size();
+  if (n == 0) return TACAW_OK;
+  // potentials: a lane at the start of a slice group builds that group's
+  // slices (the job's splat_group) in this iteration's potential launch
+  SplatLane sl[MAX_LANES];
+  PassLane rl[MAX_LANES], cl[MAX_LANES];
+  int n_splat = 0;
+  for (int i = 0; i < n; ++i) {
+    Lane& L = active[i];
+    tacaw_job* j = L.job;
+    const int G = j->hp.splat_group;
+    const int g0 = L.slice - L.slice % G;
+    const int gn = std::min(G, j->hp.ns - g0);
+    if (L.slice == g0) {
+      sl[n_splat] = SplatLane{};
+      sl[n_splat].a = splat_args(j, L.f0, L.fb, g0);
+      sl[n_splat].n_slices_launch = gn;
+      ++n_splat;
+    }
+    PassArgs a = pass_args(j);
+    a.f0 = L.f0;
+    a.fb = L.fb;
+    a.slice = L.slice;
+    a.v_slices = gn;
+    a.v_slice0 = g0;
+    rl[i] = PassLane{};
+    rl[i].a = a;
+    rl[i].mode = L.slice == 0 ? ROW_FIRST : ROW_REGULAR;
+    const bool last = L.slice == j->hp.ns - 1;
+    cl[i] = PassLane{};
+    cl[i].a = a;
+    if (last) {
+      cl[i].a.px = j->d_px_last;
+      cl[i].a.py = j->d_py_last;
+    }
+    cl[i].mode = last ? COL_LAST : COL_REGULAR;
   }
-
-  tacaw_status step() {
-    // fill free lanes: at most one lane per job (a job has one potential
-    // buffer), and while the lanes' waves fit the working-set target
-    // (TACAW_BATCH_LANE_MB, default 256: the last-level cache), at least one
-    const char* e = getenv("TACAW_BATCH_LANE_MB");
-    const double cap = (e ? atof(e) : 256.0) * (1 << 20);
-    double in_use = 0.0;
-    for (auto& l : active) in_use += lane_bytes(l);
-    for (auto it = pending.begin(); it != pending.end() && (int)active.size() < MAX_LANES;) {
-      bool busy = false;
-      for (auto& l : active) busy |= l.job == it->job;
-      if (busy) {
-        ++it;
-        continue;
-      }
-      if (!active.empty() && in_use + lane_bytes(*it) > cap) break;
-      in_use += lane_bytes(*it);
-      active.push_back(*it);
-      it = pending.erase(it);
+  tacaw_status st = TACAW_OK;
+  if (n_splat > 0) {
+    st = timed_launch(c, TACAW_K_SPLAT, s, [&] { return launch_splat_lanes(sl, n_splat, s); });
+    if (st != TACAW_OK) return st;
+  }
+  st = timed_launch(c, TACAW_K_ROW, s, [&] { return launch_row_lanes(rl, n, rv, s); });
+  if (st != TACAW_OK) return st;
+  st = timed_launch(c, TACAW_K_COL, s, [&] { return launch_col_lanes(cl, n, cv, s); });
+  if (st != TACAW_OK) return st;
+  if (n > 1) shared_launches += 2;   // the row and the column launch served several jobs
+  std::vector<Lane> still;
+  for (auto& L : active) {
+    L.slice += 1;
+    if (L.slice < L.job->hp.ns) {
+      still.push_back(L);
+      continue;
     }
-    const int n = (int)active.size();
-    // potentials: a lane at the start of a slice group builds that group's
-    // slices (the job's splat_group) in this iteration's potential launch
-    SplatLane sl[MAX_LANES];
-    PassLane rl[MAX_LANES], cl[MAX_LANES];
-    int n_splat = 0;
-    for (int i = 0; i < n; ++i) {
-      BLane& L = active[i];
-      tacaw_job* j = L.job;
-      const int G = j->hp.splat_group;
-      const int g0 = L.slice - L.slice % G;
-      const int gn = std::min(G, j->hp.ns - g0);
-      if (L.slice == g0) {
-        sl[n_splat] = SplatLane{};
-        sl[n_splat].a = splat_args(j, L.f0, L.fb, g0);
-        sl[n_splat].n_slices_launch = gn;
-        ++n_splat;
-      }
-      PassArgs a = pass_args(j);
-      a.f0 = L.f0;
-      a.fb = L.fb;
-      a.slice = L.slice;
-      a.v_slices = gn;
-      a.v_slice0 = g0;
-      rl[i] = PassLane{};
-      rl[i].a = a;
-      rl[i].mode = L.slice == 0 ? ROW_FIRST : ROW_REGULAR;
-      const bool last = L.slice == j->hp.ns - 1;
-      cl[i] = PassLane{};
-      cl[i].a = a;
-      if (last) {
-        cl[i].a.px = j->d_px_last;
-        cl[i].a.py = j->d_py_last;
-      }
-      cl[i].mode = last ? COL_LAST : COL_REGULAR;
+    tacaw_job* j = L.job;
+    if (dropped.count(j)) {
+      // a dropped job ends with its lane: no time stage
+      dropped.erase(j);
+      left.erase(j);
+      if (finished) finished->push_back(j);
+      continue;
     }
-    tacaw_status st = TACAW_OK;
-    if (n_splat > 0) {
-      st = timed_launch(c, TACAW_K_SPLAT, s, [&] { return launch_splat_lanes(sl, n_splat, s); });
+    if (--left[j] == 0) {
+      left.erase(j);
+      st = run_time_stage(j, s);
       if (st != TACAW_OK) return st;
-    }
-    st = timed_launch(c, TACAW_K_ROW, s, [&] { return launch_row_lanes(rl, n, rv, s); });
-    if (st != TACAW_OK) return st;
-    st = timed_launch(c, TACAW_K_COL, s, [&] { return launch_col_lanes(cl, n, cv, s); });
-    if (st != TACAW_OK) return st;
-    std::vector<BLane> still;
-    for (auto& L : active) {
-      L.slice += 1;
-      if (L.slice < L.job->hp.ns) {
-        still.push_back(L);
-      } else if (--left[L.job] == 0) {
-        st = run_time_stage(L.job, s);
-        if (st != TACAW_OK) return st;
-        mark_all_present(L.job);
-        L.job->has_result = true;
-        L.job->last_stream = s;
+      if (!serving) {
+        mark_all_present(j);
+        j->has_result = true;
+        j->last_stream = s;
       }
+      if (finished) finished->push_back(j);
     }
-    active.swap(still);
-    return TACAW_OK;
   }
-};
+  active.swap(still);
+  return TACAW_OK;
+}
+
+}  // namespace tacaw
+
+namespace {
 
 void load_tune_cache(tacaw_ctx* c) {
   if (c->tune_loaded) return;
@@ -244,26 +282,19 @@ tacaw_status enqueue_batch(tacaw_ctx* c, tacaw_job* const* jobs, int n_jobs, hip
   load_tune_cache(c);
   tacaw_status st = ensure_streams(c);
   if (st != TACAW_OK) return st;
-  // Jobs whose frame batches hold at least TACAW_BATCH_LARGE_MB (default 64)
-  // MiB of waves fill the device on their own: they run one after another on
-  // the first stream, exactly as the plain form runs them (sharing launches
-  // would only make the working set outgrow the last-level cache).  The
-  // smaller jobs share launches, grouped by grid, on the other streams.
-  double large_mb = 64.0;
-  if (const char* e = getenv("TACAW_BATCH_LARGE_MB")) large_mb = atof(e);
+  // Large jobs run one after another on the first stream, exactly as the
+  // plain form runs them; the others share launches, grouped by grid, on the
+  // other streams.
   std::map<std::pair<int, int>, std::vector<tacaw_job*>> groups;
   std::vector<tacaw_job*> large;
   for (int i = 0; i < n_jobs; ++i) {
     st = materialize(jobs[i], nullptr);
     if (st != TACAW_OK) return st;
     const HostPlan& hp = jobs[i]->hp;
-    const double wave_mb = (double)hp.fb * hp.P * hp.nx * hp.ny * 8.0 / (1 << 20);
-    // jobs on the reciprocal-space potential route build their potentials
-    // with their own launch sequence: they run as large jobs do
-    if (wave_mb >= large_mb || hp.kspace)
-      large.push_back(jobs[i]);
-    else
+    if (shares_launches(jobs[i]))
       groups[{hp.nx, hp.ny}].push_back(jobs[i]);
+    else
+      large.push_back(jobs[i]);
   }
   hipEvent_t start;
   if (hipEventCreateWithFlags(&start, hipEventDisableTiming) != hipSuccess) {
@@ -271,7 +302,7 @@ tacaw_status enqueue_batch(tacaw_ctx* c, tacaw_job* const* jobs, int n_jobs, hip
     return TACAW_EDEVICE;
   }
   (void)hipEventRecord(start, user);
-  std::vector<GroupRun> runs;
+  std::vector<LaneGroup> runs;
   bool used[4] = {false, false, false, false};
   int n_streams = 4;   // TACAW_BATCH_STREAMS: streams the work spreads over (1-4)
   if (const char* e = getenv("TACAW_BATCH_STREAMS")) n_streams = std::max(1, std::min(4, atoi(e)));
@@ -281,7 +312,8 @@ tacaw_status enqueue_batch(tacaw_ctx* c, tacaw_job* const* jobs, int n_jobs, hip
     const int k = first_group_stream + (int)runs.size() % span;
     if (!used[k]) (void)hipStreamWaitEvent(c->batch_streams[k], start, 0);
     used[k] = true;
-    runs.emplace_back(c, g.second, c->batch_streams[k]);
+    runs.emplace_back(c, c->batch_streams[k], g.first.first, g.first.second, false);
+    for (tacaw_job* j : g.second) runs.back().add(j);
   }
   // the large jobs advance one frame batch per round of the loop below
   size_t li = 0;
@@ -318,7 +350,7 @@ tacaw_status enqueue_batch(tacaw_ctx* c, tacaw_job* const* jobs, int n_jobs, hip
     }
     for (auto& r : runs) {
       if (r.done()) continue;
-      st = r.step();
+      st = r.step(nullptr);
       if (st != TACAW_OK) break;
       more = true;
     }

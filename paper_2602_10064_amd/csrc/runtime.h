@@ -7,7 +7,9 @@
 #include <condition_variable>
 #include <deque>
 #include <functional>
+#include <map>
 #include <mutex>
+#include <set>
 #include <string>
 #include <thread>
 #include <vector>
@@ -88,6 +90,44 @@ tacaw_status materialize(tacaw_job* j, hipStream_t s);
 tacaw_status run_batch_range(tacaw_job* job, hipStream_t s, int f_begin, int f_end);
 tacaw_status run_time_stage(tacaw_job* job, hipStream_t s);
 
+// Continuous lane batching of same-grid jobs on one stream (batch.cpp): a
+// lane is one frame batch of one job at its own slice; each step launches the
+// potentials of lanes that start a slice group, then one row and one column
+// pass over every active lane, and the time stage of each job whose last frame
+// batch it finished.  Used by the batched executor and by the serving loop,
+// which adds jobs as they are admitted.
+struct LaneGroup {
+  struct Lane {
+    tacaw_job* job;
+    int f0, fb, slice;
+  };
+  tacaw_ctx* c = nullptr;
+  hipStream_t s = nullptr;
+  bool serving = false;   // results are published by the serving loop, not here
+  std::deque<Lane> pending;
+  std::vector<Lane> active;
+  std::map<tacaw_job*, int> left;   // frame batches not finished per job
+  std::set<tacaw_job*> dropped;     // cancelled jobs whose lane is still in flight
+  int rv = 0, cv = 0;
+  int64_t shared_launches = 0;      // pass launches that served more than one job
+
+  LaneGroup(tacaw_ctx* ctx, hipStream_t stream, int nx, int ny, bool serving);
+  void add(tacaw_job* j);           // queue every frame batch of j
+  bool has(const tacaw_job* j) const;
+  // Remove j's queued frame batches.  True when nothing of j is in flight;
+  // otherwise its lane ends with the batch in flight (no time stage) and
+  // step() reports it among the finished jobs.
+  bool drop(tacaw_job* j);
+  bool done() const { return pending.empty() && active.empty(); }
+  // One iteration; jobs whose work ended in it (time stage enqueued, or
+  // dropped) are appended to *finished.
+  tacaw_status step(std::vector<tacaw_job*>* finished);
+};
+
+// Whether a job shares pass launches with other jobs of its grid in the
+// batched executor and the serving loop (else it runs as in the plain form).
+bool shares_launches(const tacaw_job* j);
+
 struct tacaw_ctx_impl;
 
 // Spectrum analysis helpers (analysis.cpp): the job must hold a spectrum; the
@@ -125,6 +165,8 @@ struct tacaw_ctx {
   bool stop = false;
   bool server_started = false;
   hipStream_t serve_stream = nullptr;
+  int64_t serve_shared_launches = 0;   // pass launches of the serving loop that served several jobs
+  int64_t serve_grouped_jobs = 0;      // served jobs that ran in shared launches
   // batched executor and autotuner
   hipStream_t batch_streams[4] = {nullptr, nullptr, nullptr, nullptr};
   int row_variant[2048] = {0};   // by grid size: 0 untuned (use 1), else variant + 1

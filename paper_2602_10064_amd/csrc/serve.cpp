@@ -1,25 +1,39 @@
 // Serving loop: admission by device-memory footprint and continuous batching.
 //
-// Submitted jobs wait in a queue.  When a stream slot is free, the loop
-// admits the first queued job, in submission order, whose footprint fits the
-// context budget next to the jobs already resident, so a small job can pass a
+// Submitted jobs wait in a queue.  The loop admits the first queued job, in
+// submission order, whose footprint fits the context budget next to the jobs
+// already resident and for which there is room, so a small job can pass a
 // large one that does not fit yet.  A job that has waited longer than
 // TACAW_SERVE_AGE_MS (default 1000 ms) at the head of the queue stops that:
 // then only the head is admitted, as soon as it fits.  An admitted job is
-// materialised (allocation, upload, tables) by a housekeeping thread on its
-// slot's stream, so allocation never stalls the issue of other jobs' work;
-// from then on the loop interleaves frame batches of every running job: each
-// running job owns a non-blocking stream and keeps one frame batch
+// materialised (allocation, upload, tables) by a housekeeping thread, so
+// allocation never stalls the issue of other jobs' work.
+//
+// Jobs whose frame batches are small (the batched executor's rule) join the
+// lane group of their grid size: one stream per group, where each launch
+// advances one frame batch of every member job by one slice (potentials,
+// then the row and column passes of all lanes together), a finished frame
+// batch makes room for the next one of any member, and jobs join as they are
+// admitted and leave when their time stage is queued.  So slice steps of
+// different requests share launches.  Up to four groups (grid sizes) run at
+// once, with two iterations in flight each.
+//
+// Large jobs take one of four stream slots: each keeps one frame batch
 // (potentials + all slice passes of fb frames) in flight, so batches of
 // different requests overlap on the device.  When a job's last batch is done
-// its time stage runs; then the housekeeping thread frees its working buffers
-// and only the spectrum (and, if kept, the exit waves) stays resident until
-// the job is destroyed.  A job's result is computed by the same kernels on the
-// same frame batches as in the plain form, so it is bitwise the same alone or
-// in any mix.
+// its time stage runs.
+//
+// When a job is over, the housekeeping thread frees its working buffers and
+// only the spectrum (and, if kept, the exit waves) stays resident until the
+// job is destroyed.  A job's result is computed by the same per-row and
+// per-column arithmetic on the same frame batches as in the plain form, so it
+// is bitwise the same alone or in any mix.
 #include <stdlib.h>
 
 #include <chrono>
+#include <map>
+#include <memory>
+#include <set>
 
 #include "runtime.h"
 
@@ -141,6 +155,30 @@ void finish(tacaw_ctx* c, Housekeeper& hk, Slot& s, int state) {
   s.setup.store(0);
 }
 
+// A lane group of the serving loop: its stream, the iterations in flight
+// (each with the jobs whose work ended in it) and the admitted jobs still
+// being materialised.
+struct ServeGroup {
+  struct Joining {
+    tacaw_job* job;
+    std::shared_ptr<std::atomic<int>> setup;   // 1 materialising, 2 ready, 3 failed
+  };
+  struct Iter {
+    hipEvent_t ev;
+    std::vector<tacaw_job*> ended;
+  };
+  LaneGroup lg;
+  std::deque<Iter> inflight;
+  std::vector<Joining> joining;
+  std::set<tacaw_job*> cancelled;   // dropped members
+  int64_t shared_seen = 0;
+  ServeGroup(tacaw_ctx* c, hipStream_t s, int nx, int ny) : lg(c, s, nx, ny, true) {}
+  bool idle() const { return lg.left.empty() && inflight.empty() && joining.empty(); }
+};
+
+constexpr int kGroups = 4;   // grid sizes served in shared launches at once
+constexpr int kGroupDepth = 2;   // iterations in flight per group
+
 void server_main(tacaw_ctx* c) {
   (void)hipSetDevice(c->device);
   Slot slots[kSlots];
@@ -148,15 +186,28 @@ void server_main(tacaw_ctx* c) {
     (void)hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking);
     (void)hipEventCreateWithFlags(&s.ev, hipEventDisableTiming);
   }
+  std::vector<hipStream_t> free_group_streams;
+  for (int i = 0; i < kGroups; ++i) {
+    hipStream_t st = nullptr;
+    (void)hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    free_group_streams.push_back(st);
+  }
+  std::map<std::pair<int, int>, std::unique_ptr<ServeGroup>> groups;
   Housekeeper hk;
   hk.start(c->device);
   const double age_ms = age_limit_ms();
+  // a grouped job's work is over (its stream has passed it): publish it
+  auto end_grouped = [&](tacaw_job* j, int state) {
+    j->t_done = now_ms();
+    hk.post([c, j, state] { release(c, j, state); });
+  };
   for (;;) {
     bool progressed = false;
     {
       std::unique_lock<std::mutex> lk(c->mu);
       int busy = 0;
       for (auto& s : slots) busy += s.job != nullptr;
+      busy += (int)groups.size();
       if (busy == 0 && c->queue.empty()) {
         if (c->stop) break;
         c->cv.wait(lk, [&] { return c->stop || !c->queue.empty(); });
@@ -175,18 +226,30 @@ void server_main(tacaw_ctx* c) {
       }
     }
     if (progressed) c->cv.notify_all();
-    // admission: the first queued job that fits, unless the head has aged
+    // admission: the first queued job that fits and has room (its grid's
+    // group, a free group stream, or a free slot), unless the head has aged
     // past the limit, in which case only the head
-    for (auto& s : slots) {
-      if (s.job) continue;
+    for (;;) {
       tacaw_job* j = nullptr;
+      bool grouped = false;
+      Slot* slot = nullptr;
+      for (auto& s : slots)
+        if (!s.job) {
+          slot = &s;
+          break;
+        }
       {
         std::lock_guard<std::mutex> lk(c->mu);
         if (c->queue.empty()) break;
         const bool head_only = now_ms() - c->queue.front()->t_submit > age_ms;
         for (auto it = c->queue.begin(); it != c->queue.end(); ++it) {
-          if (c->resident + (*it)->fp.total() <= c->budget) {
-            j = *it;
+          tacaw_job* cand = *it;
+          const bool small = shares_launches(cand);
+          const bool room = small ? (groups.count({cand->hp.nx, cand->hp.ny}) > 0 || !free_group_streams.empty())
+                                  : slot != nullptr;
+          if (room && c->resident + cand->fp.total() <= c->budget) {
+            j = cand;
+            grouped = small;
             c->queue.erase(it);
             break;
           }
@@ -197,13 +260,106 @@ void server_main(tacaw_ctx* c) {
       }
       j->t_admit = now_ms();
       j->next_frame = 0;
-      s.job = j;
-      s.setup.store(1);
-      Slot* sp = &s;
-      hk.post([j, sp] { sp->setup.store(materialize(j, sp->stream) == TACAW_OK ? 2 : 3); });
       progressed = true;
+      if (grouped) {
+        auto key = std::make_pair(j->hp.nx, j->hp.ny);
+        auto g = groups.find(key);
+        if (g == groups.end()) {
+          hipStream_t st = free_group_streams.back();
+          free_group_streams.pop_back();
+          g = groups.emplace(key, std::make_unique<ServeGroup>(c, st, j->hp.nx, j->hp.ny)).first;
+        }
+        auto setup = std::make_shared<std::atomic<int>>(1);
+        g->second->joining.push_back({j, setup});
+        // materialised on the housekeeper's own (null) stream, synchronously
+        hk.post([j, setup] { setup->store(materialize(j, nullptr) == TACAW_OK ? 2 : 3); });
+      } else {
+        slot->job = j;
+        slot->setup.store(1);
+        hk.post([j, slot] { slot->setup.store(materialize(j, slot->stream) == TACAW_OK ? 2 : 3); });
+      }
     }
-    // issue / retire work
+    // lane groups: join ready jobs, drop cancelled ones, retire finished
+    // iterations, issue the next
+    for (auto it = groups.begin(); it != groups.end();) {
+      ServeGroup& g = *it->second;
+      for (size_t k = 0; k < g.joining.size();) {
+        const int st = g.joining[k].setup->load();
+        tacaw_job* j = g.joining[k].job;
+        if (st == 1) {
+          ++k;
+          continue;
+        }
+        g.joining.erase(g.joining.begin() + k);
+        if (st == 3) {
+          end_grouped(j, ST_FAILED);
+        } else {
+          j->serve_state.store(ST_RUNNING);
+          g.lg.add(j);
+          std::lock_guard<std::mutex> lk(c->mu);
+          c->serve_grouped_jobs += 1;
+        }
+        progressed = true;
+      }
+      std::vector<tacaw_job*> members;
+      for (auto& kv : g.lg.left) members.push_back(kv.first);
+      for (tacaw_job* j : members) {
+        if (!(j->cancel_req.load() || c->stop) || g.cancelled.count(j)) continue;
+        g.cancelled.insert(j);
+        if (g.lg.drop(j)) {
+          // nothing of it in flight beyond what the stream already holds
+          hipEvent_t ev = nullptr;
+          (void)hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+          (void)hipEventRecord(ev, g.lg.s);
+          g.inflight.push_back({ev, {j}});
+        }
+        progressed = true;
+      }
+      while (!g.inflight.empty() && hipEventQuery(g.inflight.front().ev) == hipSuccess) {
+        for (tacaw_job* j : g.inflight.front().ended) {
+          const bool cancelled = g.cancelled.erase(j) > 0;
+          end_grouped(j, cancelled ? ST_CANCELLED : ST_DONE);
+        }
+        (void)hipEventDestroy(g.inflight.front().ev);
+        g.inflight.pop_front();
+        progressed = true;
+      }
+      if (!g.lg.done() && (int)g.inflight.size() < kGroupDepth) {
+        std::vector<tacaw_job*> ended;
+        tacaw_status st = g.lg.step(&ended);
+        if (st != TACAW_OK) {
+          // the group's stream state is unknown: wait for it, fail its jobs
+          (void)hipStreamSynchronize(g.lg.s);
+          for (auto& f : g.inflight) {
+            for (tacaw_job* j : f.ended) end_grouped(j, ST_FAILED);
+            (void)hipEventDestroy(f.ev);
+          }
+          g.inflight.clear();
+          for (auto& kv : g.lg.left) end_grouped(kv.first, ST_FAILED);
+          for (tacaw_job* j : ended) end_grouped(j, ST_FAILED);
+          g.lg.left.clear();
+          g.lg.pending.clear();
+          g.lg.active.clear();
+        } else {
+          hipEvent_t ev = nullptr;
+          (void)hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+          (void)hipEventRecord(ev, g.lg.s);
+          g.inflight.push_back({ev, std::move(ended)});
+          std::lock_guard<std::mutex> lk(c->mu);
+          c->serve_shared_launches += g.lg.shared_launches - g.shared_seen;
+          g.shared_seen = g.lg.shared_launches;
+        }
+        progressed = true;
+      }
+      if (g.idle()) {
+        free_group_streams.push_back(g.lg.s);
+        it = groups.erase(it);
+        progressed = true;
+      } else {
+        ++it;
+      }
+    }
+    // stream slots: issue / retire work
     for (auto& s : slots) {
       tacaw_job* j = s.job;
       if (!j) continue;
@@ -259,6 +415,7 @@ void server_main(tacaw_ctx* c) {
     (void)hipEventDestroy(s.ev);
     (void)hipStreamDestroy(s.stream);
   }
+  for (hipStream_t st : free_group_streams) (void)hipStreamDestroy(st);
 }
 
 }  // namespace
@@ -378,6 +535,18 @@ tacaw_status tacaw_cancel(tacaw_job* j) {
   }
   j->cancel_req.store(true);
   j->ctx->cv.notify_all();
+  return TACAW_OK;
+}
+
+tacaw_status tacaw_serve_stats(tacaw_ctx* c, int64_t* shared_launches, int64_t* grouped_jobs) {
+  clear_error();
+  if (!c) {
+    set_error("ctx is NULL");
+    return TACAW_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (shared_launches) *shared_launches = c->serve_shared_launches;
+  if (grouped_jobs) *grouped_jobs = c->serve_grouped_jobs;
   return TACAW_OK;
 }
 

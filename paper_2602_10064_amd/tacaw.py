@@ -68,6 +68,7 @@ EXPORTED = [
     "tacaw_job_set_aberrations", "tacaw_mean_diffraction", "tacaw_adf",
     "tacaw_run_frames", "tacaw_finish", "tacaw_get_exit_frames", "tacaw_put_exit_frames",
     "tacaw_average_spectra", "tacaw_batch_capture", "tacaw_batch_launch", "tacaw_batch_destroy",
+    "tacaw_serve_stats",
 ]
 
 
@@ -101,6 +102,7 @@ def lib() -> ctypes.CDLL:
         "tacaw_timing_select": [vp, ctypes.c_uint, ctypes.c_int],
         "tacaw_timing_get": [vp, ctypes.c_int, P(dp), P(ctypes.c_int64)],
         "tacaw_job_latency": [vp, P(dp), P(dp)],
+        "tacaw_serve_stats": [vp, P(ctypes.c_int64), P(ctypes.c_int64)],
         "tacaw_run_batch": [P(vp), ctypes.c_int, vp],
         "tacaw_autotune": [vp, vp, P(ctypes.c_int), P(ctypes.c_int)],
         "tacaw_job_plan": [vp, P(i32), P(i32)],
@@ -229,6 +231,13 @@ class Context:
 
     def submit(self, job: "TacawJob"):
         _check(lib().tacaw_submit(self.handle, job.handle))
+
+    def serve_stats(self) -> tuple:
+        """(pass launches of the serving loop that served several jobs, served
+        jobs that ran in shared launches)."""
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().tacaw_serve_stats(self.handle, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
 
 
 class TacawJob:

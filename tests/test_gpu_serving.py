@@ -171,3 +171,29 @@ def test_c5_requests_alone_vs_mix(tacaw):
             assert np.array_equal(got.view(np.uint32), r.view(np.uint32)), h.job.name
         for h in handles:
             h.destroy()
+
+
+def test_shared_launches_across_requests(tacaw):
+    """Small requests of one grid size run in shared launches (one launch
+    advances a frame batch of each by one slice), with results bitwise those
+    of each job alone; a second grid size forms a group of its own."""
+    jobs = [w.random_small_job(60 + i, nx=64, ny=64, n_slices=40 + 8 * (i % 3), n_frames=16 + 8 * (i % 2),
+                               cell=(8.0, 8.0, 30.0), n_atoms=40) for i in range(6)]
+    jobs += [w.random_small_job(70 + i, nx=96, ny=64, n_slices=40, n_frames=10, cell=(12.0, 8.0, 30.0), n_atoms=30,
+                                aperture_mrad=25.0, n_probes=2, voltage_V=60e3) for i in range(3)]
+    with tacaw.Context(0) as ctx:
+        ref = [alone(tacaw, ctx, j) for j in jobs]
+    with tacaw.Context(0) as ctx:
+        hs = [tacaw.TacawJob(ctx, j, defer_alloc=True) for j in jobs]
+        for h in hs:
+            h.submit()
+        for h in hs:
+            h.wait()
+        shared, grouped = ctx.serve_stats()
+        print(f"[gpu] shared launches {shared}, grouped jobs {grouped}", flush=True)
+        for h, r in zip(hs, ref):
+            got = h.spectrum()
+            assert np.array_equal(got.view(np.uint32), r.view(np.uint32)), h.job.name
+            h.destroy()
+    assert grouped == len(jobs)
+    assert shared > 0
