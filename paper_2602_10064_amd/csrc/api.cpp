@@ -187,6 +187,35 @@ PassArgs pass_args(tacaw_job* j) {
   return a;
 }
 
+// Whether waves of this job run resident in LDS (k_res): square 64 or 128
+// grids, real-space potentials, unless TACAW_RESIDENT is 0 (then the row and
+// column passes).  Measured faster than the passes at every wave count tried,
+// 64 waves (64^2, one workgroup per wave) included.  `waves` (the waves of
+// the launch) is for a future threshold.
+bool resident_for(const tacaw_job* j, long waves) {
+  (void)waves;
+  const HostPlan& hp = j->hp;
+  if (!resident_supported(hp.nx, hp.ny) || hp.kspace) return false;
+  const char* e = getenv("TACAW_RESIDENT");
+  return !(e && *e && atoi(e) == 0);
+}
+
+// One resident lane: frames [f0, f0 + fb) through slices sl .. sl + n - 1,
+// whose potentials V holds as slices v_slice0 .. v_slice0 + v_slices - 1.
+ResLane res_lane(tacaw_job* j, int f0, int fb, int sl, int n, int v_slices, int v_slice0) {
+  ResLane l{};
+  l.a = pass_args(j);
+  l.a.f0 = f0;
+  l.a.fb = fb;
+  l.a.slice = sl;
+  l.a.v_slices = v_slices;
+  l.a.v_slice0 = v_slice0;
+  l.px_last = j->d_px_last;
+  l.py_last = j->d_py_last;
+  l.n_slices_launch = n;
+  return l;
+}
+
 static SplatArgs splat_args_of(tacaw_job* job, int f0, int fb) {
   const HostPlan& hp = job->hp;
   SplatArgs sa{};
@@ -318,16 +347,24 @@ tacaw_status run_batch_range(tacaw_job* job, hipStream_t s, int f_begin, int f_e
   }
   if (!hp.overlap) {
     // serial form: potentials of hp.splat_group slices (all slices when not
-    // per slice), then their row and column passes
+    // per slice), then their row and column passes, or one resident launch
+    // that carries the waves through all of them
     const int G = hp.splat_group;
     for (int f0 = f_begin; f0 < f_end; f0 += hp.fb) {
       const int fb = std::min(hp.fb, f_end - f0);
+      const bool res = resident_for(job, (long)hp.P * fb);
       for (int g0 = 0; g0 < hp.ns; g0 += G) {
         const int gn = std::min(G, hp.ns - g0);
         SplatArgs sa = splat_args_of(job, f0, fb);
         sa.slice0 = g0;
         tacaw_status st = timed(job, TACAW_K_SPLAT, s, [&] { return launch_splat(sa, gn, s); });
         if (st != TACAW_OK) return st;
+        if (res) {
+          const ResLane rl = res_lane(job, f0, fb, g0, gn, gn, g0);
+          st = timed(job, TACAW_K_ROW, s, [&] { return launch_res_lanes(&rl, 1, s); });
+          if (st != TACAW_OK) return st;
+          continue;
+        }
         for (int sl = g0; sl < g0 + gn; ++sl)
           if ((st = slice_passes(job, s, f0, fb, sl, job->d_V, gn, g0)) != TACAW_OK) return st;
       }
@@ -571,6 +608,13 @@ tacaw_status tacaw_ctx_create(int device, size_t hbm_budget_bytes, tacaw_ctx** o
   // device address of the allocation-free entry points' fixed scratch array
   tacaw_status st = noalloc_init(device);
   if (st != TACAW_OK) return st;
+  // kernel attributes (large dynamic LDS) set before any launch, so that no
+  // first launch inside a graph capture has to set them
+  hipError_t ke = kernels_init();
+  if (ke != hipSuccess) {
+    set_error("kernel attributes: %s", hipGetErrorString(ke));
+    return TACAW_EDEVICE;
+  }
   tacaw_ctx* c = new tacaw_ctx();
   c->device = device;
   c->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)fr);

@@ -146,10 +146,16 @@ tacaw_status LaneGroup::step(std::vector<tacaw_job*>* finished) {
   }
   const int n = (int)active.size();
   if (n == 0) return TACAW_OK;
+  // resident step: every lane runs to the end of its slice group in one
+  // launch, the waves held in LDS (square 64 and 128 grids)
+  long waves = 0;
+  for (auto& l : active) waves += (long)l.job->hp.P * l.fb;
+  const bool res = resident_for(active[0].job, waves);
   // potentials: a lane at the start of a slice group builds that group's
   // slices (the job's splat_group) in this iteration's potential launch
   SplatLane sl[MAX_LANES];
   PassLane rl[MAX_LANES], cl[MAX_LANES];
+  ResLane xl[MAX_LANES];
   int n_splat = 0;
   for (int i = 0; i < n; ++i) {
     Lane& L = active[i];
@@ -163,6 +169,7 @@ tacaw_status LaneGroup::step(std::vector<tacaw_job*>* finished) {
       sl[n_splat].n_slices_launch = gn;
       ++n_splat;
     }
+    xl[i] = res_lane(j, L.f0, L.fb, L.slice, g0 + gn - L.slice, gn, g0);
     PassArgs a = pass_args(j);
     a.f0 = L.f0;
     a.fb = L.fb;
@@ -186,14 +193,21 @@ tacaw_status LaneGroup::step(std::vector<tacaw_job*>* finished) {
     st = timed_launch(c, TACAW_K_SPLAT, s, [&] { return launch_splat_lanes(sl, n_splat, s); });
     if (st != TACAW_OK) return st;
   }
-  st = timed_launch(c, TACAW_K_ROW, s, [&] { return launch_row_lanes(rl, n, rv, s); });
-  if (st != TACAW_OK) return st;
-  st = timed_launch(c, TACAW_K_COL, s, [&] { return launch_col_lanes(cl, n, cv, s); });
-  if (st != TACAW_OK) return st;
-  if (n > 1) shared_launches += 2;   // the row and the column launch served several jobs
+  if (res) {
+    st = timed_launch(c, TACAW_K_ROW, s, [&] { return launch_res_lanes(xl, n, s); });
+    if (st != TACAW_OK) return st;
+    if (n > 1) shared_launches += 1;
+  } else {
+    st = timed_launch(c, TACAW_K_ROW, s, [&] { return launch_row_lanes(rl, n, rv, s); });
+    if (st != TACAW_OK) return st;
+    st = timed_launch(c, TACAW_K_COL, s, [&] { return launch_col_lanes(cl, n, cv, s); });
+    if (st != TACAW_OK) return st;
+    if (n > 1) shared_launches += 2;   // the row and the column launch served several jobs
+  }
   std::vector<Lane> still;
-  for (auto& L : active) {
-    L.slice += 1;
+  for (int i = 0; i < n; ++i) {
+    Lane& L = active[i];
+    L.slice += res ? xl[i].n_slices_launch : 1;
     if (L.slice < L.job->hp.ns) {
       still.push_back(L);
       continue;

@@ -1190,6 +1190,186 @@ __global__ void __launch_bounds__((C8<N, WIDE>::THREADS)) k_col_r8(PassTable tab
 }
 
 // ---------------------------------------------------------------------------
+// Waves resident in LDS (square grids of 64 and 128): one workgroup holds one
+// (probe, frame) wave for a run of slices, so HBM carries only the potentials
+// and, at the ends of the run, the wave itself.  Per slice: every row goes
+// through iFFT_x, the transmission exp(i sigma V) and FFT_x, then every column
+// through FFT_y, the propagator and iFFT_y (or FFT_y and the last-slice
+// propagator at the job's last slice), with a workgroup barrier after each
+// phase.  Rows and columns use the register FFT of the row and column passes
+// (same stages, twiddles, butterflies and products, so the same arithmetic),
+// with their exchanges done in place in the resident wave.  Layout: element
+// (y, x) at slot (y + y/16) PITCH + x + x/16; a 16-lane access then hits at
+// most two slots per bank pair (checked by enumeration of every exchange of
+// both phases).
+// ---------------------------------------------------------------------------
+template <int N>
+struct RS {
+  static constexpr int G = N / 8;                  // lanes per line
+  static constexpr int RPW = 64 / G;               // lines per wavefront
+  static constexpr int WAVES = N == 128 ? 16 : 8;
+  static constexpr int THREADS = WAVES * 64;
+  static constexpr int PITCH = N == 128 ? 145 : 67;
+  static constexpr int ROWS = N + (N - 1) / 16;    // physical rows: rs_pad(N - 1) + 1
+  static constexpr int ITS = N / (WAVES * RPW);    // line iterations per phase
+  static constexpr size_t LDS = (size_t)ROWS * PITCH * sizeof(float2);
+  static_assert(N == 64 || N == 128, "resident grids: 64 and 128");
+  static_assert(PITCH >= N + (N - 1) / 16, "rows hold their padded slots");
+};
+__device__ __forceinline__ int rs_pad(int i) { return i + (i >> 4); }
+
+// line handled by (iteration, wavefront, line within the wavefront): 128:
+// consecutive lines per wavefront; 64: lines w + 8 sub (the two lines of a
+// 16-lane group are 8 apart, which the bank check prefers)
+template <int N>
+__device__ __forceinline__ int rs_line(int it, int wave, int sub) {
+  if constexpr (N == 128)
+    return (it * RS<N>::WAVES + wave) * RS<N>::RPW + sub;
+  else
+    return wave + RS<N>::WAVES * sub;
+}
+
+// Stage J of the register FFT (the arithmetic of reg_fft_stage) with the
+// exchanges at LDS slots addr(position).
+template <int N, bool INV, int J, typename Addr>
+__device__ __forceinline__ void res_fft_stage(float2 (&x)[8], float2* psi, const Addr& addr,
+                                              const float2 (&tw)[R8<N>::S][7], int t) {
+  constexpr int S = R8<N>::S, G = R8<N>::G;
+  constexpr int R = R8<N>::radix(J), P = R8<N>::stride(J), Q = 8 / R;
+  if constexpr (J > 0) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        const float2 w = tw[J][q * (R - 1) + r - 1];
+        x[q + Q * r] = INV ? cmulc(x[q + Q * r], w) : cmul(x[q + Q * r], w);
+      }
+  }
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    float2 y[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) y[r] = x[q + Q * r];
+    dft<R, INV>(y);
+#pragma unroll
+    for (int r = 0; r < R; ++r) x[q + Q * r] = y[r];
+  }
+  if constexpr (J < S - 1) {
+    wave_lds_sync();  // earlier reads of this line by the wavefront are done
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int b = t + G * q;
+      const int k = b % P;
+      const int base = (b - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) psi[addr(base + r * P)] = x[q + Q * r];
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int r = 0; r < 8; ++r) x[r] = psi[addr(t + G * r)];
+    res_fft_stage<N, INV, J + 1>(x, psi, addr, tw, t);
+  }
+}
+
+template <int N>
+__global__ void __launch_bounds__(RS<N>::THREADS) k_res(ResTable tab) {
+  constexpr int G = RS<N>::G, S = R8<N>::S, PITCH = RS<N>::PITCH;
+  extern __shared__ float2 psi[];
+  const int L = find_lane(tab, blockIdx.x);
+  const ResLane& ln = tab.l[L];
+  const PassArgs& a = ln.a;
+  const int w = blockIdx.x - ln.block_start;    // wave of the lane: probe p, frame f0 + fl
+  const int p = w / a.fb;
+  const int fl = w - p * a.fb;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int sub = lane / G, t = lane % G;
+  float2* store = a.exit + ((size_t)p * a.n_frames + a.f0 + fl) * (size_t)N * N;
+  float2 tw[S][7];
+  reg_twiddles<N>(tw, a.tw_x, t);   // square grid: the y transform has the same twiddles
+  const int ox = a.plane ? 0 : a.origin[2 * p];
+  const int oy = a.plane ? 0 : a.origin[2 * p + 1];
+  const int s0 = a.slice, s1 = a.slice + ln.n_slices_launch;
+
+  // the wave in flight ((kx, y) layout) unless the run starts at slice 0
+  if (s0 > 0) {
+    for (int e = threadIdx.x; e < N * N; e += RS<N>::THREADS)
+      psi[rs_pad(e / N) * PITCH + rs_pad(e % N)] = store[e];
+    __syncthreads();
+  }
+  for (int sl = s0; sl < s1; ++sl) {
+    // rows: iFFT_x (not at slice 0: the incident wave is in real space),
+    // transmission, FFT_x
+#pragma unroll 1
+    for (int it = 0; it < RS<N>::ITS; ++it) {
+      const int y = rs_line<N>(it, wave, sub);
+      float2* row = psi + rs_pad(y) * PITCH;
+      auto addr = [](int i) { return rs_pad(i); };
+      float2 x[8];
+      if (sl == 0) {
+        if (a.plane) {
+#pragma unroll
+          for (int r = 0; r < 8; ++r) x[r] = make_float2(a.plane_amp, 0.f);
+        } else {
+          const float2* src = a.probe0 + ((size_t)p * a.ny + y) * (size_t)N;
+#pragma unroll
+          for (int r = 0; r < 8; ++r) x[r] = src[t + r * G];
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) x[r] = row[addr(t + r * G)];
+      }
+      int yy = oy + y;
+      if (yy >= a.pny) yy -= a.pny;
+      const float* vrow = a.V + (((size_t)fl * a.v_slices + (sl - a.v_slice0)) * a.pny + yy) * (size_t)a.pnx;
+      float v[8];
+      if (ox == 0 && a.pnx == N) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) v[r] = vrow[t + r * G];
+      } else {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          int xx = ox + t + r * G;
+          if (xx >= a.pnx) xx -= a.pnx;
+          v[r] = vrow[xx];
+        }
+      }
+      if (sl > 0) res_fft_stage<N, true, 0>(x, row, addr, tw, t);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) x[r] = cmul(x[r], phase_factor(a.sigma * v[r]));
+      res_fft_stage<N, false, 0>(x, row, addr, tw, t);
+      wave_lds_sync();
+#pragma unroll
+      for (int r = 0; r < 8; ++r) row[addr(t + r * G)] = x[r];
+    }
+    __syncthreads();
+    // columns: FFT_y, propagator, iFFT_y (the job's last slice: FFT_y and the
+    // last-slice propagator)
+    const bool last = sl == a.n_slices - 1;
+    const float2* px = last ? ln.px_last : a.px;
+    const float2* py = last ? ln.py_last : a.py;
+#pragma unroll 1
+    for (int it = 0; it < RS<N>::ITS; ++it) {
+      const int xc = rs_line<N>(it, wave, sub);
+      const int cs = rs_pad(xc);
+      auto addr = [cs](int i) { return rs_pad(i) * PITCH + cs; };
+      float2 x[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) x[r] = psi[addr(t + r * G)];
+      res_fft_stage<N, false, 0>(x, psi, addr, tw, t);
+      const float2 pxv = px[xc];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) x[r] = cmul(x[r], cmul(pxv, py[t + r * G]));
+      if (!last) res_fft_stage<N, true, 0>(x, psi, addr, tw, t);
+      wave_lds_sync();
+#pragma unroll
+      for (int r = 0; r < 8; ++r) psi[addr(t + r * G)] = x[r];
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < N * N; e += RS<N>::THREADS) store[e] = psi[rs_pad(e / N) * PITCH + rs_pad(e % N)];
+}
+
+// ---------------------------------------------------------------------------
 // Column pass for ny = 512 as 512 = 8 x 64 (six-step), tiles of 8 columns.
 // Lanes run along x, so a tile is read and written straight from its rows in
 // 64-byte segments with no LDS transpose:
@@ -2043,6 +2223,51 @@ static hipError_t col_rv_launch(PassTable& t, hipStream_t s) {
   const int grid = std::min(tiles, 2048);
   TACAW_LAUNCH((k_col_rv<N>), dim3(grid), dim3(CV<N>::THREADS), 0, s, t, tiles);
   return hipGetLastError();
+}
+
+bool resident_supported(int nx, int ny) { return nx == ny && (nx == 64 || nx == 128); }
+
+template <int N>
+static hipError_t res_set_attributes() {
+  return hipFuncSetAttribute((const void*)k_res<N>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)RS<N>::LDS);
+}
+
+hipError_t kernels_init() {
+  hipError_t e = res_set_attributes<64>();
+  return e == hipSuccess ? res_set_attributes<128>() : e;
+}
+
+template <int N>
+static hipError_t res_launch(ResTable& t, hipStream_t s) {
+  long blocks = 0;
+  for (int i = 0; i < t.n; ++i) {
+    const PassArgs& a = t.l[i].a;
+    if (a.nx != N || a.ny != N || t.l[i].n_slices_launch < 1 || a.slice < 0 ||
+        a.slice + t.l[i].n_slices_launch > a.n_slices || a.slice < a.v_slice0 ||
+        a.slice + t.l[i].n_slices_launch > a.v_slice0 + a.v_slices)
+      return hipErrorInvalidValue;
+    t.l[i].block_start = (int)blocks;
+    blocks += (long)a.n_probes * a.fb;
+  }
+  if (blocks < 1 || blocks > (1L << 30)) return hipErrorInvalidValue;
+  // the dynamic LDS limit was raised by kernels_init (context creation)
+  TACAW_LAUNCH((k_res<N>), dim3((unsigned)blocks), dim3(RS<N>::THREADS), RS<N>::LDS, s, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_res_lanes(const ResLane* lanes, int n, hipStream_t s) {
+  if (n < 1 || n > MAX_LANES) return hipErrorInvalidValue;
+  ResTable t{};
+  t.n = n;
+  for (int i = 0; i < n; ++i) {
+    t.l[i] = lanes[i];
+    if (lanes[i].a.nx != lanes[0].a.nx || lanes[i].a.ny != lanes[0].a.ny) return hipErrorInvalidValue;
+  }
+  switch (lanes[0].a.nx) {
+    case 64: return res_launch<64>(t, s);
+    case 128: return res_launch<128>(t, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_row_lanes(const PassLane* lanes, int n, int variant, hipStream_t s) {

@@ -118,6 +118,23 @@ struct SplatTable {
   SplatLane l[MAX_LANES];
 };
 
+// A batch of waves carried through a run of slices with each wave resident
+// in one workgroup's LDS (square grids of 64 and 128): one lane is one frame
+// batch of one job and the slices a.slice .. a.slice + n_slices_launch - 1,
+// whose potentials V holds (a.v_slice0, a.v_slices).  The last slice of the
+// job ends in reciprocal space with the last-slice propagator.
+struct ResLane {
+  PassArgs a;
+  const float2* px_last;
+  const float2* py_last;
+  int n_slices_launch;
+  int block_start;   // set by the launcher
+};
+struct ResTable {
+  int n;
+  ResLane l[MAX_LANES];
+};
+
 enum RowMode { ROW_FIRST = 0, ROW_REGULAR = 1, ROW_INVERSE_ONLY = 2 };
 enum ColMode { COL_REGULAR = 0, COL_LAST = 1, COL_INVERSE_ONLY = 2 };
 
@@ -135,6 +152,9 @@ hipError_t launch_splat_lanes(const SplatLane* lanes, int n, hipStream_t s);
 hipError_t launch_col_pass(const PassArgs& a, int mode, hipStream_t s);
 hipError_t launch_time_stage(const TimeArgs& a, hipStream_t s);
 hipError_t launch_kpot(const KPotArgs& a, hipStream_t s);
+bool resident_supported(int nx, int ny);
+hipError_t kernels_init();   // per-kernel attributes on the current device
+hipError_t launch_res_lanes(const ResLane* lanes, int n, hipStream_t s);
 int time_stage_kt(int n_frames, int n_k);
 
 // Setup kernels: twiddle table exp(-2 pi i m / n) (FP64 -> FP32); separable

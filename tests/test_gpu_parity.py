@@ -175,6 +175,7 @@ def test_c3_shape_reduced_probes_frames(tacaw, ctx, oracle):
 def test_deep_row_kernel_matches(tacaw, ctx, monkeypatch, n):
     # two rows in flight per wavefront: the same per-row arithmetic, so the
     # same values to FP32 rounding (ragged grid stride over 9 frames)
+    monkeypatch.setenv("TACAW_RESIDENT", "0")   # the row and column passes, not the LDS-resident kernel
     job = w.random_small_job(41, nx=n, ny=n, n_slices=3, n_frames=9, cell=(n / 9.0, n / 9.0, 4.0))
     _, a, _ = run_gpu(tacaw, ctx, job)
     monkeypatch.setenv("TACAW_ROW_VARIANT", "3")
@@ -186,6 +187,7 @@ def test_fft_variants_agree(tacaw, ctx, monkeypatch):
     # the LDS Stockham kernels with one or two rows per workgroup run the same
     # arithmetic per row (bitwise equal); the register kernels agree with them
     # to FP32 rounding
+    monkeypatch.setenv("TACAW_RESIDENT", "0")   # the row and column passes, not the LDS-resident kernel
     job = w.c1_tiny(n_frames=16)
     _, reg, _ = run_gpu(tacaw, ctx, job)          # default: register kernels for 64
     monkeypatch.setenv("TACAW_COL_VARIANT", "0")
