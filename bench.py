@@ -196,7 +196,7 @@ def bench_c5(args):
     t0 = time.perf_counter()
     reg_inputs, big_input = c5_inputs(min(args.requests, 24), bool(big.any()))
     print(f"[bench] serving inputs ready in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
-    lat, lib_lat, create_ms, done_steps, finished_at = [], [], [], [0], []
+    lat, lib_lat, create_ms, copy_ms, done_steps, finished_at = [], [], [], [], [0], []
     lock = threading.Lock()
 
     def request(job, arrival):
@@ -205,6 +205,7 @@ def bench_c5(args):
         tcreate = time.perf_counter() - tc
         h.submit()
         h.wait()
+        tw = time.perf_counter()
         spec = h.spectrum()               # to host memory
         t_end = time.perf_counter()
         q, tot = h.latency_ms()
@@ -214,6 +215,7 @@ def bench_c5(args):
             lat.append((t_end - arrival) * 1e3)
             lib_lat.append(tot)
             create_ms.append(tcreate * 1e3)
+            copy_ms.append((t_end - tw) * 1e3)
             done_steps[0] += job.slice_steps()
             finished_at.append(t_end)
 
@@ -249,6 +251,8 @@ def bench_c5(args):
         "p99_ms_from_submit_to_device_result": float(np.percentile(lib_lat, 99)),
         "p50_job_create_ms": float(np.percentile(create_ms, 50)),
         "p99_job_create_ms": float(np.percentile(create_ms, 99)),
+        "p50_spectrum_to_host_ms": float(np.percentile(copy_ms, 50)),
+        "p99_spectrum_to_host_ms": float(np.percentile(copy_ms, 99)),
         "requests": int(args.requests), "rate_per_s": args.rate, "elapsed_s": elapsed,
         "big_requests": int(big.sum()), "shared_pass_launches": int(shared), "requests_in_shared_launches": int(grouped),
         "higher_is_better": True, "dtype": "fp32", "data": "synthetic",

@@ -45,18 +45,29 @@ void drop_graph(tacaw_job* j) {
   j->graph = nullptr;
 }
 
-void free_job_buffers(tacaw_job* j) {
+// Free the job's device buffers.  keep_results: the spectrum and, with
+// TACAW_KEEP_EXIT_WAVES, the exit store stay, and their pointer fields are
+// not written (a reader of the results may run meanwhile).
+void free_buffers(tacaw_job* j, bool keep_results) {
   drop_graph(j);
-  if (j->d_exit) j->present.clear();   // a new exit store holds no frames
-  void* bufs[] = {j->d_exit,    j->d_spec,   j->d_V,      j->d_pos,     j->d_species,   j->d_tile_start,
-                  j->d_tile_atoms, j->d_coef, j->d_tw_x,  j->d_tw_y,    j->d_tw_t,      j->d_px,
-                  j->d_py,      j->d_px_last, j->d_py_last, j->d_probe0, j->d_origin,   j->d_rloc,
-                  j->d_count,   j->d_fslice, j->d_W,    j->d_ks_start, j->d_ks_atoms, j->d_kcoef,
-                  j->d_tw_px,   j->d_tw_py};
+  const bool keep_exit = keep_results && (j->desc.flags & TACAW_KEEP_EXIT_WAVES);
+  if (!keep_exit) {
+    if (j->d_exit) {
+      j->present.clear();   // a new exit store holds no frames
+      (void)hipFree(j->d_exit);
+    }
+    j->d_exit = nullptr;
+  }
+  if (!keep_results) {
+    if (j->d_spec) (void)hipFree(j->d_spec);
+    j->d_spec = nullptr;
+  }
+  void* bufs[] = {j->d_V,       j->d_pos,     j->d_species,  j->d_tile_start, j->d_tile_atoms, j->d_coef,
+                  j->d_tw_x,    j->d_tw_y,    j->d_tw_t,     j->d_px,         j->d_py,         j->d_px_last,
+                  j->d_py_last, j->d_probe0,  j->d_origin,   j->d_rloc,       j->d_count,      j->d_fslice,
+                  j->d_W,       j->d_ks_start, j->d_ks_atoms, j->d_kcoef,     j->d_tw_px,      j->d_tw_py};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
-  j->d_exit = nullptr;
-  j->d_spec = nullptr;
   j->d_V = nullptr;
   j->d_pos = nullptr;
   j->d_species = nullptr;
@@ -75,6 +86,8 @@ void free_job_buffers(tacaw_job* j) {
   j->d_kcoef = nullptr;
   j->d_tw_px = j->d_tw_py = nullptr;
 }
+
+void free_job_buffers(tacaw_job* j) { free_buffers(j, false); }
 
 hipEvent_t take_event(tacaw_ctx* c) {
   if (!c->event_pool.empty()) {
@@ -561,17 +574,7 @@ tacaw_status materialize(tacaw_job* j, hipStream_t s0) {
 
 // Free every device buffer except the spectrum and (when kept) the exit waves.
 void release_working(tacaw_job* j) {
-  float2* keep_exit = (j->desc.flags & TACAW_KEEP_EXIT_WAVES) ? j->d_exit : nullptr;
-  float* keep_spec = j->d_spec;
-  if (!keep_exit && j->d_exit) {
-    (void)hipFree(j->d_exit);
-    j->present.clear();   // a new exit store holds no frames
-  }
-  j->d_exit = nullptr;
-  j->d_spec = nullptr;
-  free_job_buffers(j);
-  j->d_exit = keep_exit;
-  j->d_spec = keep_spec;
+  free_buffers(j, true);
   j->materialized = false;
 }
 
@@ -1061,6 +1064,7 @@ tacaw_status tacaw_job_destroy(tacaw_job* job) {
     set_error("job is in the serving loop: cancel and wait first");
     return TACAW_EBUSY;
   }
+  wait_released(job);   // the serving loop's release of this job has run
   (void)hipSetDevice(job->ctx->device);
   (void)hipDeviceSynchronize();
   if (job->retained) {

@@ -237,13 +237,23 @@ struct tacaw_job {
   double t_submit = 0, t_admit = 0, t_done = 0;
   size_t retained = 0;               // bytes counted in ctx->resident after a served job ends
   bool served = false;
+  // the serving loop has published this job's end but its release thread
+  // has not yet freed the working buffers (guarded by ctx->mu)
+  bool release_pending = false;
 };
+
+// Wait until the serving loop's release thread is done with the job.
+inline void wait_released(tacaw_job* j) {
+  std::unique_lock<std::mutex> lk(j->ctx->mu);
+  j->ctx->cv.wait(lk, [&] { return !j->release_pending; });
+}
 
 // A plain, batched or frame-range run takes a job back from a finished,
 // cancelled or failed serving state to idle, so the results of that run are
 // not reported as cancelled or failed.  Queued and running jobs are left alone
 // (the callers refuse them first).
 inline void leave_serving_state(tacaw_job* j) {
+  wait_released(j);
   int s = j->serve_state.load();
   while (s >= 3 && !j->serve_state.compare_exchange_weak(s, 0)) {
   }

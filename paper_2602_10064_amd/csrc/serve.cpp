@@ -23,9 +23,11 @@
 // different requests overlap on the device.  When a job's last batch is done
 // its time stage runs.
 //
-// When a job is over, the housekeeping thread frees its working buffers and
-// only the spectrum (and, if kept, the exit waves) stays resident until the
-// job is destroyed.  A job's result is computed by the same per-row and
+// When a job is over, its state is published at once (tacaw_wait returns);
+// a release thread of its own then frees the working buffers, and only the
+// spectrum (and, if kept, the exit waves) stays resident until the job is
+// destroyed.  Materialisation runs on another thread, so a release never
+// waits behind a large job's setup.  A job's result is computed by the same per-row and
 // per-column arithmetic on the same frame batches as in the plain form, so it
 // is bitwise the same alone or in any mix.
 #include <stdlib.h>
@@ -114,41 +116,62 @@ double age_limit_ms() {
   return e ? atof(e) : 1000.0;
 }
 
-// Release a finished, cancelled or failed job's device memory and publish its
-// final state (runs on the housekeeping thread; the job's stream is idle).
-void release(tacaw_ctx* c, tacaw_job* j, int state) {
-  size_t keep = 0;
+// A job's work is over (its stream has passed it): publish its final state at
+// once, so that tacaw_wait returns without waiting for the frees, then hand
+// the release of its working buffers to the release thread.  Until that has
+// run, release_pending holds the job (destroy, resubmission and other runs
+// wait for it); the results themselves (spectrum, kept exit waves) are not
+// touched by the release.
+void publish(tacaw_ctx* c, Housekeeper& hk_release, tacaw_job* j, int state) {
+  j->t_done = now_ms();
+  // buffers that do not outlive the job's end leave the job's fields here,
+  // before the state is published, and are freed by the release thread
+  float2* exit_free = nullptr;
+  float* spec_free = nullptr;
   if (state == ST_DONE) {
     mark_all_present(j);
     j->has_result = true;
     j->last_stream = nullptr;
-    release_working(j);
-    keep = resident_bytes_after_done(j);
+    if (!(j->desc.flags & TACAW_KEEP_EXIT_WAVES)) {
+      exit_free = j->d_exit;
+      j->d_exit = nullptr;
+      j->present.clear();
+    }
   } else {
-    release_working(j);
-    if (j->d_exit) (void)hipFree(j->d_exit);
-    if (j->d_spec) (void)hipFree(j->d_spec);
+    j->has_result = false;
+    exit_free = j->d_exit;
+    spec_free = j->d_spec;
     j->d_exit = nullptr;
     j->d_spec = nullptr;
-    j->has_result = false;
+    j->present.clear();
   }
   {
     std::lock_guard<std::mutex> lk(c->mu);
-    c->resident -= j->fp.total();
-    c->resident += keep;
-    j->retained = keep;
+    j->release_pending = true;
     j->serve_state.store(state);
   }
   c->cv.notify_all();
+  hk_release.post([c, j, state, exit_free, spec_free] {
+    release_working(j);   // the working buffers; the job's results stay
+    if (exit_free) (void)hipFree(exit_free);
+    if (spec_free) (void)hipFree(spec_free);
+    const size_t keep = state == ST_DONE ? resident_bytes_after_done(j) : 0;
+    {
+      std::lock_guard<std::mutex> lk(c->mu);
+      c->resident -= j->fp.total();
+      c->resident += keep;
+      j->retained = keep;
+      j->release_pending = false;
+    }
+    c->cv.notify_all();
+  });
 }
 
-// The slot's job is over: wait for its stream, stamp the end, hand the
-// release to the housekeeper and free the slot.
-void finish(tacaw_ctx* c, Housekeeper& hk, Slot& s, int state) {
+// The slot's job is over: wait for its stream, publish it and free the slot.
+void finish(tacaw_ctx* c, Housekeeper& hk_release, Slot& s, int state) {
   tacaw_job* j = s.job;
   (void)hipStreamSynchronize(s.stream);
-  j->t_done = now_ms();
-  hk.post([c, j, state] { release(c, j, state); });
+  publish(c, hk_release, j, state);
   s.job = nullptr;
   s.inflight = false;
   s.time_issued = false;
@@ -193,14 +216,14 @@ void server_main(tacaw_ctx* c) {
     free_group_streams.push_back(st);
   }
   std::map<std::pair<int, int>, std::unique_ptr<ServeGroup>> groups;
-  Housekeeper hk;
+  // materialisation (slow for large jobs) and release run on threads of
+  // their own, so a release never waits behind a large job's setup
+  Housekeeper hk, hk_release;
   hk.start(c->device);
+  hk_release.start(c->device);
   const double age_ms = age_limit_ms();
   // a grouped job's work is over (its stream has passed it): publish it
-  auto end_grouped = [&](tacaw_job* j, int state) {
-    j->t_done = now_ms();
-    hk.post([c, j, state] { release(c, j, state); });
-  };
+  auto end_grouped = [&](tacaw_job* j, int state) { publish(c, hk_release, j, state); };
   for (;;) {
     bool progressed = false;
     {
@@ -366,7 +389,7 @@ void server_main(tacaw_ctx* c) {
       const int setup = s.setup.load();
       if (setup == 1) continue;   // still being materialised
       if (setup == 3) {
-        finish(c, hk, s, ST_FAILED);
+        finish(c, hk_release, s, ST_FAILED);
         progressed = true;
         continue;
       }
@@ -377,7 +400,7 @@ void server_main(tacaw_ctx* c) {
         progressed = true;
       }
       if (j->cancel_req.load() || c->stop) {
-        finish(c, hk, s, ST_CANCELLED);
+        finish(c, hk_release, s, ST_CANCELLED);
         progressed = true;
         continue;
       }
@@ -390,12 +413,12 @@ void server_main(tacaw_ctx* c) {
         st = run_time_stage(j, s.stream);
         s.time_issued = true;
       } else {
-        finish(c, hk, s, ST_DONE);
+        finish(c, hk_release, s, ST_DONE);
         progressed = true;
         continue;
       }
       if (st != TACAW_OK) {
-        finish(c, hk, s, ST_FAILED);
+        finish(c, hk_release, s, ST_FAILED);
         continue;
       }
       (void)hipEventRecord(s.ev, s.stream);
@@ -407,10 +430,11 @@ void server_main(tacaw_ctx* c) {
   for (auto& s : slots) {
     if (s.job) {
       while (s.setup.load() == 1) std::this_thread::sleep_for(std::chrono::microseconds(50));
-      finish(c, hk, s, ST_CANCELLED);
+      finish(c, hk_release, s, ST_CANCELLED);
     }
   }
-  hk.join();   // every posted setup and release has run
+  hk.join();           // every posted setup has run
+  hk_release.join();   // and every release
   for (auto& s : slots) {
     (void)hipEventDestroy(s.ev);
     (void)hipStreamDestroy(s.stream);
@@ -453,6 +477,7 @@ tacaw_status tacaw_submit(tacaw_ctx* c, tacaw_job* j) {
               c->budget / 1073741824.0);
     return TACAW_ENOMEM;
   }
+  wait_released(j);   // a job served before is fully released first
   std::lock_guard<std::mutex> lk(c->mu);
   if (c->stop) {
     set_error("context is shutting down");
