@@ -443,7 +443,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
 // nyq: m is the Nyquist index -n/2 of an even side, which takes the cosine
 // alone (the mean of the +n/2 and -n/2 terms).
 __device__ __forceinline__ float2 sf_term(int m, int ip, float fp, int n, float inv_n, bool nyq) {
-  const int t = (m * ip) % n;   // |m ip| < 2^21
+  // t = m ip mod n, exactly: |m ip| < 2^23, so it and its float are exact,
+  // and the float quotient is at most one off (corrected)
+  const int mi = m * ip;
+  int t = mi - n * (int)floorf((float)mi * inv_n);
+  t += t < 0 ? n : 0;
+  t -= t >= n ? n : 0;
   float rev = ((float)t + (float)m * fp) * inv_n;
   rev -= rintf(rev);
   const float c = __builtin_amdgcn_cosf(rev);
@@ -495,8 +500,9 @@ __device__ float corner_sin_sum(const KPotArgs& a, int f, int s, float q2c) {
 // complex product of a [rows x atoms] and an [atoms x columns] matrix, taken
 // KP_K atoms at a time: the workgroup writes the stage's exponentials to LDS
 // (real and imaginary planes, [row or column][atom]), then each wavefront
-// runs v_mfma_f32_16x16x4f32 on its 32 x 32 part (four 16 x 16 blocks, real
-// part = Re Re - Im Im, imaginary part = Re Im + Im Re).  The species' form
+// runs v_mfma_f32_16x16x4f32 on its 32 x 32 part (four 16 x 16 blocks, three
+// real products per complex one: Re Re, Im Im and (Re + Im)(Re + Im), whose
+// combinations give the real part Re Re - Im Im and the imaginary part).  The species' form
 // factor multiplies the finished sum element by element.  Atoms are taken in
 // list order and the instruction sequence is fixed, so results are
 // deterministic.
@@ -570,9 +576,11 @@ __global__ void __launch_bounds__(256) k_kpot(KPotArgs a) {
     for (int z = 0; z < a.n_species; ++z) {
       const int js = a.ks_start[s * a.n_species + z], je = a.ks_start[s * a.n_species + z + 1];
       if (js == je) continue;
-      v4f acc[4][2];
+      // three real products per complex one: P1 = Ar Br, P2 = Ai Bi,
+      // P3 = (Ar + Ai)(Br + Bi); Re = P1 - P2, Im = P3 - P1 - P2
+      v4f acc[4][3];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) acc[u][0] = acc[u][1] = v4f{0.f, 0.f, 0.f, 0.f};
+      for (int u = 0; u < 4; ++u) acc[u][0] = acc[u][1] = acc[u][2] = v4f{0.f, 0.f, 0.f, 0.f};
       for (int c = js; c < je; c += KP_K) {
         bool on = gj < je - c;
         AtomPos p{};
@@ -603,21 +611,22 @@ __global__ void __launch_bounds__(256) k_kpot(KPotArgs a) {
         const int kn = min(KP_K, ((je - c) + 3) & ~3);
         for (int k0 = 0; k0 < kn; k0 += 4) {
           const int kk = k0 + lane / 16;
-          float ar[2], ai[2], br[2], bi[2];
+          float ar[2], ai[2], as[2], br[2], bi[2], bs[2];
 #pragma unroll
           for (int v = 0; v < 2; ++v) {
             ar[v] = eyr[16 * v + lane % 16][kk];
             ai[v] = eyi[16 * v + lane % 16][kk];
             br[v] = exr[32 * wave + 16 * v + lane % 16][kk];
             bi[v] = exi[32 * wave + 16 * v + lane % 16][kk];
+            as[v] = ar[v] + ai[v];
+            bs[v] = br[v] + bi[v];
           }
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             const int ry = u >> 1, cx = u & 1;
             acc[u][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[ry], br[cx], acc[u][0], 0, 0, 0);
-            acc[u][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai[ry], bi[cx], acc[u][0], 0, 0, 0);
-            acc[u][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[ry], bi[cx], acc[u][1], 0, 0, 0);
-            acc[u][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[ry], br[cx], acc[u][1], 0, 0, 0);
+            acc[u][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[ry], bi[cx], acc[u][1], 0, 0, 0);
+            acc[u][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(as[ry], bs[cx], acc[u][2], 0, 0, 0);
           }
         }
       }
@@ -629,8 +638,10 @@ __global__ void __launch_bounds__(256) k_kpot(KPotArgs a) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const float ff = kform(cf, q2[u][e]);
-          vs[h][u][0][e] = fmaf(ff, acc[u][0][e], vs[h][u][0][e]);
-          vs[h][u][1][e] = fmaf(ff, acc[u][1][e], vs[h][u][1][e]);
+          const float re = acc[u][0][e] - acc[u][1][e];
+          const float im = acc[u][2][e] - acc[u][0][e] - acc[u][1][e];
+          vs[h][u][0][e] = fmaf(ff, re, vs[h][u][0][e]);
+          vs[h][u][1][e] = fmaf(ff, im, vs[h][u][1][e]);
         }
     }
   }
@@ -2423,10 +2434,24 @@ hipError_t launch_splat_lanes(const SplatLane* lanes, int n, hipStream_t s) {
   SplatTable t{};
   t.n = n;
   int blocks = 0;
-  // TACAW_SPLAT_FPW and TACAW_SPLAT_ROUND are read at every launch
+  // TACAW_SPLAT_FPW and TACAW_SPLAT_ROUND are read at every launch.  Frames
+  // per wavefront: TACAW_SPLAT_FPW, else the most (16, 8, 4, 2, 1) that still
+  // gives the launch at least 16384 work items (16 workgroups per CU); more
+  // frames per item share the item's list and coefficient set-up (c2: 12.5
+  // ms per step at 16 frames, 12.9 at 4).
   const char* fe = getenv("TACAW_SPLAT_FPW");
   const int fpw_v = fe ? atoi(fe) : 0;
-  const int fpw_env = fpw_v >= 1 && fpw_v <= 64 ? fpw_v : SPLAT_FPW;
+  int fpw_env = fpw_v >= 1 && fpw_v <= 64 ? fpw_v : 0;
+  if (fpw_env == 0) {
+    for (fpw_env = 16; fpw_env > 1; fpw_env /= 2) {
+      long items = 0;
+      for (int i = 0; i < n; ++i) {
+        const SplatArgs& a = lanes[i].a;
+        items += (long)a.tiles_x * a.tiles_y * lanes[i].n_slices_launch * ((a.fb + fpw_env - 1) / fpw_env);
+      }
+      if (items >= 16384) break;
+    }
+  }
   for (int i = 0; i < n; ++i) {
     t.l[i] = lanes[i];
     t.l[i].block_start = blocks;

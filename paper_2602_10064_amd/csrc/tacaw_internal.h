@@ -19,7 +19,6 @@ constexpr int SPLAT_TX = 32;   // splat tile: columns
 constexpr int SPLAT_TY = 32;   // splat tile: rows
 constexpr int COEF_STRIDE = 6; // per (species, term): amplitude, exp2 x, exp2 y, cutoff x, cutoff y,
                                // log2 of the amplitude
-constexpr int SPLAT_FPW = 4;   // default frames per splat wavefront (candidate lists are frame independent)
 constexpr int SPLAT_MAX_SPECIES = 16;  // species whose coefficients are staged in LDS
 constexpr int COL_CT = 16;     // columns per column-pass workgroup (128-byte rows)
 
