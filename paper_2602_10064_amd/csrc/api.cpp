@@ -336,10 +336,15 @@ static tacaw_status kspace_potentials(tacaw_job* job, hipStream_t s, int f0, int
   a.n_frames = a.fb = fb * k.npairs;
   a.f0 = 0;
   a.plane = 1;
-  st = timed(job, TACAW_K_OTHER, s, [&] { return launch_col_pass(a, COL_INVERSE_ONLY, s); });
+  // the register kernels where the size has them (else the LDS kernels)
+  PassLane l{};
+  l.a = a;
+  l.mode = COL_INVERSE_ONLY;
+  st = timed(job, TACAW_K_OTHER, s, [&] { return launch_col_lanes(&l, 1, 2, s); });
   if (st != TACAW_OK) return st;
-  a.vout = job->d_V;
-  return timed(job, TACAW_K_OTHER, s, [&] { return launch_row_pass(a, ROW_INVERSE_ONLY, s); });
+  l.a.vout = job->d_V;
+  l.mode = ROW_INVERSE_ONLY;
+  return timed(job, TACAW_K_OTHER, s, [&] { return launch_row_lanes(&l, 1, 2, s); });
 }
 
 tacaw_status run_batch_range(tacaw_job* job, hipStream_t s, int f_begin, int f_end) {

@@ -879,7 +879,7 @@ __device__ __forceinline__ void fft_r8(float2 (&x)[8], float2* lds, const float2
 // DEPTH 1: the next row's reads are in flight while a row is transformed
 // (five wavefronts per SIMD); DEPTH 2: the next two rows' (three rotating
 // register buffers, four wavefronts per SIMD).
-template <int N, int DEPTH>
+template <int N, int DEPTH, bool VOUT = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DEPTH == 1 ? 5 : 4)))
 k_row_r8(PassTable tab) {
   constexpr int G = R8<N>::G;
@@ -953,7 +953,9 @@ k_row_r8(PassTable tab) {
     }
   };
 
-  // transform one row held in (x, v) and store it to out
+  // transform one row held in (x, v) and store it to out (inverse-only rows
+  // of the reciprocal-space potentials with vout set: the real and imaginary
+  // parts to the two potential planes of the wave instead)
   auto transform = [&](float2 (&x)[8], const float (&v)[8], float2* out, int rid) {
     if (mode != ROW_FIRST) fft_r8<N, true>(x, lds, tw, t);
     if (transmit) {
@@ -962,8 +964,23 @@ k_row_r8(PassTable tab) {
       fft_r8<N, false>(x, lds, tw, t);
     }
     if (rid < total) {
+      if (VOUT && !transmit && a.vout) {
+        const int w = rid / a.ny;
+        const int y = rid - w * a.ny;
+        const int p = w / a.fb;
+        const int fl = w - p * a.fb;
+        const size_t plane = (size_t)a.ny * N;
+        float* o0 = a.vout + 2 * ((size_t)p * a.n_frames + a.f0 + fl) * plane + (size_t)y * N;
+        float* o1 = o0 + plane;
 #pragma unroll
-      for (int r = 0; r < 8; ++r) out[t + r * G] = x[r];
+        for (int r = 0; r < 8; ++r) {
+          o0[t + r * G] = x[r].x;
+          o1[t + r * G] = x[r].y;
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) out[t + r * G] = x[r];
+      }
     }
   };
   int rid0 = (lb * 4 + wave) * RPW;
@@ -2016,7 +2033,10 @@ struct TimeCfg {
   static constexpr int KT0 = (144 * 1024) / ((F + 1) * 8);
   static constexpr int KTT = 1024 / G;
   static constexpr int KTM = KT0 < KTT ? KT0 : KTT;
-  static constexpr int KT = KTM >= 32 ? 32 : KTM >= 16 ? 16 : KTM >= 8 ? 8 : KTM >= 4 ? 4 : KTM >= 2 ? 2 : 1;
+  // at F >= 1024, at most 8 k-points per block: two blocks fit a CU's LDS
+  // and overlap their load and transform phases (c2: 1.43 against 1.58 ms)
+  static constexpr int KTC = F >= 1024 && KTM > 8 ? 8 : KTM;
+  static constexpr int KT = KTC >= 32 ? 32 : KTC >= 16 ? 16 : KTC >= 8 ? 8 : KTC >= 4 ? 4 : KTC >= 2 ? 2 : 1;
   static constexpr int THREADS = KT * G;
   static constexpr int LD = F + 1;
 };
@@ -2194,7 +2214,14 @@ static hipError_t row_r8_launch(PassTable& t, hipStream_t s) {
     t.l[i].block_start = blocks;
     blocks += (int)b;
   }
-  TACAW_LAUNCH((k_row_r8<N, DEPTH>), dim3(blocks), dim3(256), 0, s, t);
+  // lanes writing two potential planes (reciprocal-space route) take their
+  // own instantiation, so the multislice rows carry none of that code
+  bool vout = false;
+  for (int i = 0; i < t.n; ++i) vout = vout || t.l[i].a.vout != nullptr;
+  if (vout)
+    TACAW_LAUNCH((k_row_r8<N, DEPTH, true>), dim3(blocks), dim3(256), 0, s, t);
+  else
+    TACAW_LAUNCH((k_row_r8<N, DEPTH, false>), dim3(blocks), dim3(256), 0, s, t);
   return hipGetLastError();
 }
 
