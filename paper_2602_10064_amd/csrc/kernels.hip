@@ -1532,6 +1532,150 @@ __global__ void __launch_bounds__(512) k_col_6s(PassTable tab, int total_tiles) 
 }
 
 // ---------------------------------------------------------------------------
+// Column pass for ny = 256 as 256 = 8 x 32 (six-step) on tiles of 16 columns
+// (whole 128-byte row segments), 512 threads:
+//   layout A: column c = lane % 16, r0 = 4 wave + lane / 16, values at rows
+//             r0 + 32 j (j < 8): 8-point transform over j, twiddle
+//             W256^(r0 k1), exchange through LDS to
+//   layout B: k1 = wave, column lane / 4, u = lane % 4, values at r0 = u + 4 q:
+//             8-point transform over q, twiddle W32^(u k2), a wavefront-local
+//             exchange that gives lane u the values of k2 = u and u + 4 for
+//             every u-index, and two 4-point transforms over that index:
+//             frequency k1 + 8 k2 + 64 k3 (k3 < 4).
+// The propagator is applied in that order and the inverse retraces the steps
+// with conjugate twiddles; the last slice stores the spectrum from layout B.
+// LDS slots: 16 r0 + (c ^ 4 (r0 % 4)) within region k1 for the cross-wavefront
+// exchanges, and 16 (k2 / 4) + 4 ((k2 % 4) ^ (c % 4)) + (u ^ (c % 4)) within
+// column c's 32 slots of region k1 for the local ones; every 16-lane access
+// hits 16 distinct 8-byte slots modulo 16 (checked by enumeration, with the
+// index arithmetic checked against a reference FFT in the same enumeration).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(512) k_col_6q(PassTable tab, int total_tiles) {
+  constexpr int N = 256, CT = 16;
+  __shared__ float2 xs[4096];
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int ca = lane & 15, r0 = 4 * wave + (lane >> 4);   // layout A
+  const int k1 = wave, cb = lane >> 2, u = lane & 3;       // layout B
+  const int sa = 16 * r0 + (ca ^ (4 * (r0 & 3)));          // + 512 k1
+  const int sb = 512 * k1 + 16 * u + (cb ^ (4 * u));       // + 64 q (r0 = u + 4 q)
+  float2* lw = xs + 512 * k1 + 32 * cb;                    // local exchange region
+  const int cs = cb & 3;
+  auto lslot = [cs](int k2, int uu) { return 16 * (k2 >> 2) + 4 * ((k2 & 3) ^ cs) + (uu ^ cs); };
+  // twiddles, the same for every tile (all lanes of a table have ny = 256)
+  float2 ta[8], tb[8];   // entries 1..7
+  {
+    const float2* tw = tab.l[0].a.tw_y;
+#pragma unroll
+    for (int k = 1; k < 8; ++k) {
+      ta[k] = tw[(r0 * k) & (N - 1)];
+      tb[k] = tw[(8 * u * k) & (N - 1)];
+    }
+  }
+  auto locate = [&](int it, int& L, int& x0, float2*& wp) {
+    const int tile_g = xcd_remap(it, total_tiles);
+    L = find_lane(tab, tile_g);
+    const PassArgs& a = tab.l[L].a;
+    const int tile = tile_g - tab.l[L].block_start;
+    const int tiles_per_wave = a.nx / CT;
+    const int w = tile / tiles_per_wave;
+    x0 = (tile % tiles_per_wave) * CT;
+    const int p = w / a.fb;
+    const int fl = w % a.fb;
+    wp = a.exit + ((size_t)p * a.n_frames + a.f0 + fl) * (size_t)N * a.nx;
+  };
+  float2 pre[8];
+  int L = 0, x0 = 0;
+  float2* wp = nullptr;
+  int it = blockIdx.x;
+  if (it < total_tiles) {
+    locate(it, L, x0, wp);
+    const int nx = tab.l[L].a.nx;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) pre[j] = wp[(size_t)(r0 + 32 * j) * nx + x0 + ca];
+  }
+  for (; it < total_tiles; it += gridDim.x) {
+    const PassArgs& a = tab.l[L].a;
+    const int mode = tab.l[L].mode;
+    const int nx = a.nx;
+    const int cur_x0 = x0;
+    float2* cur_wp = wp;
+    float2 x[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) x[j] = pre[j];
+    // the next tile's loads complete during this tile's arithmetic
+    const int nit = it + gridDim.x;
+    if (nit < total_tiles) {
+      locate(nit, L, x0, wp);
+      const int nnx = tab.l[L].a.nx;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) pre[j] = wp[(size_t)(r0 + 32 * j) * nnx + x0 + ca];
+    }
+    // layout A: 8-point transform over j, twiddle, to LDS
+    dft8<false>(x);
+#pragma unroll
+    for (int k = 1; k < 8; ++k) x[k] = cmul(x[k], ta[k]);
+    __syncthreads();   // the previous tile's reads of the exchange buffer are done
+#pragma unroll
+    for (int k = 0; k < 8; ++k) xs[512 * k + sa] = x[k];
+    __syncthreads();
+    // layout B: 8-point transform over q, twiddle, local exchange, two
+    // 4-point transforms over the u-index
+#pragma unroll
+    for (int q = 0; q < 8; ++q) x[q] = xs[sb + 64 * q];
+    dft8<false>(x);
+#pragma unroll
+    for (int k = 1; k < 8; ++k) x[k] = cmul(x[k], tb[k]);
+    wave_lds_sync();
+#pragma unroll
+    for (int k = 0; k < 8; ++k) lw[lslot(k, u)] = x[k];
+    wave_lds_sync();
+#pragma unroll
+    for (int v = 0; v < 8; ++v) x[v] = lw[lslot(u + 4 * (v >> 2), v & 3)];
+    dft4<false>(x);
+    dft4<false>(x + 4);   // x[4 h + k3] = psi(k1 + 8 (u + 4 h) + 64 k3) of column cur_x0 + cb
+    const float2 pxv = a.px[cur_x0 + cb];
+    const bool last = mode == COL_LAST;
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int k3 = 0; k3 < 4; ++k3)
+        x[4 * h + k3] = cmul(x[4 * h + k3], cmul(pxv, a.py[k1 + 8 * (u + 4 * h) + 64 * k3]));
+    if (last) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int k3 = 0; k3 < 4; ++k3)
+          cur_wp[(size_t)(k1 + 8 * (u + 4 * h) + 64 * k3) * nx + cur_x0 + cb] = x[4 * h + k3];
+      continue;
+    }
+    // inverse, the same steps backwards
+    dft4<true>(x);
+    dft4<true>(x + 4);   // x[4 h + v]: u-index v of k2 = u + 4 h
+    wave_lds_sync();
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) lw[lslot(u + 4 * h, v)] = x[4 * h + v];
+    wave_lds_sync();
+    x[0] = lw[lslot(0, u)];
+#pragma unroll
+    for (int k = 1; k < 8; ++k) x[k] = cmulc(lw[lslot(k, u)], tb[k]);
+    dft8<true>(x);    // over k2: x[q] at r0 = u + 4 q
+    wave_lds_sync();
+#pragma unroll
+    for (int q = 0; q < 8; ++q) xs[sb + 64 * q] = x[q];
+    __syncthreads();
+    // layout A: conjugate twiddle, 8-point transform over k1, store
+    x[0] = xs[sa];
+#pragma unroll
+    for (int k = 1; k < 8; ++k) x[k] = cmulc(xs[512 * k + sa], ta[k]);
+    dft8<true>(x);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) cur_wp[(size_t)(r0 + 32 * j) * nx + cur_x0 + ca] = x[j];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // The same six-step column transform on tiles of 16 columns, so that every
 // load and store instruction of a wavefront covers whole 128-byte row
 // segments (4 rows x 16 columns), with 512 threads and 68 KiB of LDS per
@@ -2389,11 +2533,35 @@ static hipError_t col_6w_launch(PassTable& t, hipStream_t s) {
   return hipGetLastError();
 }
 
+static hipError_t col_6q_launch(PassTable& t, hipStream_t s) {
+  int tiles = 0;
+  for (int i = 0; i < t.n; ++i) {
+    const PassArgs& a = t.l[i].a;
+    if (a.ny != 256 || a.nx % 16 != 0) return hipErrorInvalidValue;
+    t.l[i].block_start = tiles;
+    tiles += a.n_probes * a.fb * (a.nx / 16);
+  }
+  // grid stride over the tiles; TACAW_COL_GRID caps the grid (default 2048:
+  // 236 against 240 us per spectrum-image launch at 1024)
+  const char* ge = getenv("TACAW_COL_GRID");
+  const int cap = ge && atoi(ge) > 0 ? atoi(ge) : 2048;
+  const int grid = std::min(tiles, cap);
+  TACAW_LAUNCH(k_col_6q, dim3(grid), dim3(512), 0, s, t, tiles);
+  return hipGetLastError();
+}
+
 hipError_t launch_col_lanes(const PassLane* lanes, int n, int variant, hipStream_t s) {
   if (n < 1 || n > MAX_LANES || !same_grid(lanes, n)) return hipErrorInvalidValue;
   PassTable t{};
   t.n = n;
   for (int i = 0; i < n; ++i) t.l[i] = lanes[i];
+  if (variant == 7) {
+    // six-step kernel at 256 rows on 16-column tiles: regular and last-slice modes
+    bool ok = lanes[0].a.ny == 256 && lanes[0].a.nx % 16 == 0;
+    for (int i = 0; i < n; ++i) ok = ok && lanes[i].mode != COL_INVERSE_ONLY;
+    if (ok) return col_6q_launch(t, s);
+    variant = 3;
+  }
   if (variant == 6) {
     // six-step kernel on 16-column tiles: ny = 512, regular and last-slice modes
     bool ok = lanes[0].a.ny == 512 && lanes[0].a.nx % 16 == 0;

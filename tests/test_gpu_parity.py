@@ -164,9 +164,12 @@ def test_errors_do_not_poison_context(tacaw, ctx):
         assert np.isfinite(j.spectrum()).all()
 
 
-def test_c3_shape_reduced_probes_frames(tacaw, ctx, oracle):
+@pytest.mark.parametrize("col_variant", ["default", "7"])
+def test_c3_shape_reduced_probes_frames(tacaw, ctx, oracle, monkeypatch, col_variant):
     # full c3 geometry (38400 atoms, 1000x866 potential grid, 256^2 windows,
     # 20 slices, 30 mrad at 60 kV) with a 3x3 scan and 4 frames
+    if col_variant != "default":
+        monkeypatch.setenv("TACAW_COL_VARIANT", col_variant)
     job = w.c3_probe(n_frames=4, n_scan=3)
     check_job(tacaw, ctx, oracle, job)
 
@@ -262,11 +265,12 @@ def test_512_rows_narrow_grid(tacaw, ctx, oracle, monkeypatch, variant):
     check_job(tacaw, ctx, oracle, job)
 
 
-@pytest.mark.parametrize("variant", ["2", "3", "4"])
+@pytest.mark.parametrize("variant", ["2", "3", "4", "7"])
 def test_256_rows_column_kernels(tacaw, ctx, oracle, monkeypatch, variant):
     # 256 rows: the register column kernel on 8-column tiles (2), 16-column
-    # tiles (3) and 8-column tiles with two LDS buffers (4); probes in windows
-    # of a larger potential grid, ragged frame batches
+    # tiles (3) and 8-column tiles with two LDS buffers (4), and the six-step
+    # kernel on 16-column tiles (7); probes in windows of a larger potential
+    # grid, ragged frame batches
     monkeypatch.setenv("TACAW_COL_VARIANT", variant)
     monkeypatch.setenv("TACAW_FB", "3")
     job = w.random_small_job(48, nx=48, ny=256, n_slices=3, n_frames=10, cell=(6.0, 32.0, 4.0), n_atoms=24,
