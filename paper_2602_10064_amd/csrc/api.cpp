@@ -626,6 +626,7 @@ tacaw_status tacaw_ctx_create(int device, size_t hbm_budget_bytes, tacaw_ctx** o
   }
   tacaw_ctx* c = new tacaw_ctx();
   c->device = device;
+  load_tune_cache(c);   // tuned row and column variants of earlier runs, if any
   c->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)fr);
   *out = c;
   return TACAW_OK;

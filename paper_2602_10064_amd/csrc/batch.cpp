@@ -236,15 +236,14 @@ tacaw_status LaneGroup::step(std::vector<tacaw_job*>* finished) {
   return TACAW_OK;
 }
 
-}  // namespace tacaw
-
-namespace {
-
+// The tuned variants of earlier runs (TACAW_TUNE_CACHE, JSON lines), read
+// once per context: at creation, and by the autotuner and the batched
+// executor for contexts created before the variable was set.
 void load_tune_cache(tacaw_ctx* c) {
   if (c->tune_loaded) return;
-  c->tune_loaded = true;
   const char* path = getenv("TACAW_TUNE_CACHE");
-  if (!path) return;
+  if (!path) return;   // read later, once the variable is set
+  c->tune_loaded = true;
   c->tune_cache = path;
   std::ifstream in(path);
   std::string line;
@@ -259,7 +258,7 @@ void load_tune_cache(tacaw_ctx* c) {
   }
 }
 
-}  // namespace
+}  // namespace tacaw
 
 namespace {
 

@@ -129,6 +129,7 @@ struct LaneGroup {
 // Whether a job shares pass launches with other jobs of its grid in the
 // batched executor and the serving loop (else it runs as in the plain form).
 bool shares_launches(const tacaw_job* j);
+void load_tune_cache(tacaw_ctx* c);
 
 struct tacaw_ctx_impl;
 
