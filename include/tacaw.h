@@ -251,7 +251,9 @@ tacaw_status tacaw_autotune(tacaw_job* job, void* hip_stream, int* row_variant, 
  * launches with the other running jobs of their grid size: one launch
  * advances one frame batch of each by one slice.  Larger jobs run on their
  * own stream, one frame batch in flight, overlapping the others.  The result
- * is bitwise the one the job gets alone. */
+ * is bitwise the one the job gets alone.  TACAW_SERVE_BATCH_WINDOW_MS (default
+ * 0) holds a new grid size's first shared launch that long after its first
+ * request is ready, so that requests arriving together start together. */
 tacaw_status tacaw_submit(tacaw_ctx* ctx, tacaw_job* job);
 
 /* *done = 1 once a submitted job has its spectrum (or was cancelled). */

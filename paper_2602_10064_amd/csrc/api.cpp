@@ -204,10 +204,8 @@ PassArgs pass_args(tacaw_job* j) {
 // Whether waves of this job run resident in LDS (k_res): square 64 or 128
 // grids, real-space potentials, unless TACAW_RESIDENT is 0 (then the row and
 // column passes).  Measured faster than the passes at every wave count tried,
-// 64 waves (64^2, one workgroup per wave) included.  `waves` (the waves of
-// the launch) is for a future threshold.
-bool resident_for(const tacaw_job* j, long waves) {
-  (void)waves;
+// 64 waves (64^2, one workgroup per wave) included.
+bool resident_for(const tacaw_job* j) {
   const HostPlan& hp = j->hp;
   if (!resident_supported(hp.nx, hp.ny) || hp.kspace) return false;
   const char* e = getenv("TACAW_RESIDENT");
@@ -371,7 +369,7 @@ tacaw_status run_batch_range(tacaw_job* job, hipStream_t s, int f_begin, int f_e
     const int G = hp.splat_group;
     for (int f0 = f_begin; f0 < f_end; f0 += hp.fb) {
       const int fb = std::min(hp.fb, f_end - f0);
-      const bool res = resident_for(job, (long)hp.P * fb);
+      const bool res = resident_for(job);
       for (int g0 = 0; g0 < hp.ns; g0 += G) {
         const int gn = std::min(G, hp.ns - g0);
         SplatArgs sa = splat_args_of(job, f0, fb);

@@ -148,9 +148,7 @@ tacaw_status LaneGroup::step(std::vector<tacaw_job*>* finished) {
   if (n == 0) return TACAW_OK;
   // resident step: every lane runs to the end of its slice group in one
   // launch, the waves held in LDS (square 64 and 128 grids)
-  long waves = 0;
-  for (auto& l : active) waves += (long)l.job->hp.P * l.fb;
-  const bool res = resident_for(active[0].job, waves);
+  const bool res = resident_for(active[0].job);
   // potentials: a lane at the start of a slice group builds that group's
   // slices (the job's splat_group) in this iteration's potential launch
   SplatLane sl[MAX_LANES];

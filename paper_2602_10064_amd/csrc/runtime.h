@@ -84,7 +84,7 @@ struct JobState;
 // context's timing is on).
 tacaw_status timed_launch(tacaw_ctx* c, int cls, hipStream_t s, const std::function<hipError_t()>& launch);
 PassArgs pass_args(tacaw_job* j);
-bool resident_for(const tacaw_job* j, long waves);
+bool resident_for(const tacaw_job* j);
 ResLane res_lane(tacaw_job* j, int f0, int fb, int sl, int n, int v_slices, int v_slice0);
 int row_variant_for(tacaw_ctx* c, int n);
 int col_variant_for(tacaw_ctx* c, int n);

@@ -15,7 +15,9 @@
 // then the row and column passes of all lanes together), a finished frame
 // batch makes room for the next one of any member, and jobs join as they are
 // admitted and leave when their time stage is queued.  So slice steps of
-// different requests share launches.  Up to four groups (grid sizes) run at
+// different requests share launches.  A new group can hold its first launch
+// for a batching window (TACAW_SERVE_BATCH_WINDOW_MS) so that requests
+// arriving together start together.  Up to four groups (grid sizes) run at
 // once, with two iterations in flight each.
 //
 // Large jobs take one of four stream slots: each keeps one frame batch
@@ -116,6 +118,15 @@ double age_limit_ms() {
   return e ? atof(e) : 1000.0;
 }
 
+// Batching window: a lane group that has issued nothing yet waits this long
+// (TACAW_SERVE_BATCH_WINDOW_MS, default 0) after its first member is ready
+// before its first launch, so that requests arriving together share launches
+// from the start.
+double batch_window_ms() {
+  const char* e = getenv("TACAW_SERVE_BATCH_WINDOW_MS");
+  return e ? std::max(0.0, atof(e)) : 0.0;
+}
+
 // A job's work is over (its stream has passed it): publish its final state at
 // once, so that tacaw_wait returns without waiting for the frees, then hand
 // the release of its working buffers to the release thread.  Until that has
@@ -195,6 +206,8 @@ struct ServeGroup {
   std::vector<Joining> joining;
   std::set<tacaw_job*> cancelled;   // dropped members
   int64_t shared_seen = 0;
+  double first_ready_ms = 0;        // when the group's first member became ready
+  bool stepped = false;             // an iteration has been issued
   ServeGroup(tacaw_ctx* c, hipStream_t s, int nx, int ny) : lg(c, s, nx, ny, true) {}
   bool idle() const { return lg.left.empty() && inflight.empty() && joining.empty(); }
 };
@@ -222,6 +235,7 @@ void server_main(tacaw_ctx* c) {
   hk.start(c->device);
   hk_release.start(c->device);
   const double age_ms = age_limit_ms();
+  const double window_ms = batch_window_ms();
   // a grouped job's work is over (its stream has passed it): publish it
   auto end_grouped = [&](tacaw_job* j, int state) { publish(c, hk_release, j, state); };
   for (;;) {
@@ -318,6 +332,7 @@ void server_main(tacaw_ctx* c) {
           end_grouped(j, ST_FAILED);
         } else {
           j->serve_state.store(ST_RUNNING);
+          if (!g.stepped && g.lg.left.empty()) g.first_ready_ms = now_ms();
           g.lg.add(j);
           std::lock_guard<std::mutex> lk(c->mu);
           c->serve_grouped_jobs += 1;
@@ -347,7 +362,11 @@ void server_main(tacaw_ctx* c) {
         g.inflight.pop_front();
         progressed = true;
       }
-      if (!g.lg.done() && (int)g.inflight.size() < kGroupDepth) {
+      // a new group waits up to the batching window after its first member
+      // is ready, so that requests arriving together start together
+      const bool window_open = !g.stepped && !c->stop && now_ms() - g.first_ready_ms < window_ms;
+      if (!g.lg.done() && (int)g.inflight.size() < kGroupDepth && !window_open) {
+        g.stepped = true;
         std::vector<tacaw_job*> ended;
         tacaw_status st = g.lg.step(&ended);
         if (st != TACAW_OK) {

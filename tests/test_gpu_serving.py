@@ -173,10 +173,14 @@ def test_c5_requests_alone_vs_mix(tacaw):
             h.destroy()
 
 
-def test_shared_launches_across_requests(tacaw):
+def test_shared_launches_across_requests(tacaw, monkeypatch):
     """Small requests of one grid size run in shared launches (one launch
-    advances a frame batch of each by one slice), with results bitwise those
-    of each job alone; a second grid size forms a group of its own."""
+    advances a frame batch of each by one slice, or through a slice group on
+    the LDS-resident grids), with results bitwise those of each job alone; a
+    second grid size forms a group of its own.  A batching window lets the
+    requests submitted together start together, so the launches are shared
+    whatever the host's timing."""
+    monkeypatch.setenv("TACAW_SERVE_BATCH_WINDOW_MS", "500")
     jobs = [w.random_small_job(60 + i, nx=64, ny=64, n_slices=40 + 8 * (i % 3), n_frames=16 + 8 * (i % 2),
                                cell=(8.0, 8.0, 30.0), n_atoms=40) for i in range(6)]
     jobs += [w.random_small_job(70 + i, nx=96, ny=64, n_slices=40, n_frames=10, cell=(12.0, 8.0, 30.0), n_atoms=30,
