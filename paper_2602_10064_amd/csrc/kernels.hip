@@ -207,8 +207,8 @@ __device__ __forceinline__ float profile(int node, int ipos, float fpos, int n, 
 // of NPL lanes (one pair each); the first half of the parts fill column
 // profiles (unit amplitude), the second half row profiles (the term's
 // amplitude), node-major in LDS.  Pairs mp .. mp4 - 1 get zeros (the MFMA
-// steps take four pairs at a time).
-template <int NPL, int PS, bool IZ>
+// steps take four pairs at a time); FULL: mp = NPL, no lane is idle.
+template <int NPL, int PS, bool IZ, bool FULL>
 __device__ __forceinline__ void splat_fill(float (*gx)[PS], float (*gy)[PS], int lane, int mp, int mp4,
                                            const AtomPos& p, const float* c, int at, const SplatArgs& a, int s,
                                            size_t frame_off, int tx0, int ty0, bool simple_x, bool simple_y) {
@@ -217,7 +217,7 @@ __device__ __forceinline__ void splat_fill(float (*gx)[PS], float (*gy)[PS], int
   const bool along_y = part >= 32 / NPL;          // lanes 0-31: column profiles, 32-63: row profiles
   const int nbase = (part % (32 / NPL)) * NPL;    // first profile node of this lane
   float* dst = along_y ? &gy[nbase][pr] : &gx[nbase][pr];   // node nbase + j at dst[j * PS]
-  if (pr < mp) {
+  if (FULL || pr < mp) {   // FULL: a round of MP pairs, every lane has one
     // per-frame binning: an atom outside this slice in this frame adds nothing
     const bool gone = IZ && a.fslice != nullptr && at >= 0 && a.fslice[frame_off + at] != s;
     // lanes 0-31 and 32-63 run the same instructions on their own axis
@@ -261,6 +261,11 @@ __device__ __forceinline__ void splat_fill(float (*gx)[PS], float (*gy)[PS], int
   }
 }
 
+template <bool B>
+struct Flag {
+  static constexpr bool value = B;
+};
+
 template <int MP, bool IZ>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_splat(SplatTable tab) {
   // MP pairs per round (32 or 16).  Lanes split into 64 / MP parts of MP
@@ -278,7 +283,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
   __shared__ float gys[4][SPLAT_TY][PS];
   __shared__ float coef_s[SPLAT_MAX_SPECIES * N_GAUSS * COEF_STRIDE];
 
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  // the wave index is uniform across the wavefront: keep it (and what follows
+  // from it: the work item, its tile range and frame count) in scalar registers
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x % 64;
   // one work item (tile, slice, group of FPW frames) per wavefront; lanes of
   // the table start on block boundaries
   const int L = find_lane(tab, blockIdx.x);
@@ -312,7 +319,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
   typedef float v4f __attribute__((ext_vector_type(4)));
 
   // per round: this lane's atom and coefficients are the same for every
-  // frame; positions of the first PRE rounds are prefetched one frame ahead
+  // frame; positions of the first PRE = 2 rounds are prefetched one frame
+  // ahead
   constexpr int PRE = 2;
   int atom_r[PRE];
   int coef_r[PRE];
@@ -321,6 +329,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
   for (int r = 0; r < PRE; ++r) {
     atom_r[r] = -1;
     coef_r[r] = 0;
+    pn[r] = AtomPos{};
     const int c0 = cs + r * MP;
     if (c0 + pr < ce) {
       const int entry = a.tile_atoms[c0 + pr];
@@ -336,35 +345,23 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
     const int fl = fl0 + k;
     const size_t frame_off = (size_t)(a.f0 + fl) * a.n_atoms;
     v4f acc[4] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
-    int r = 0;
-    for (int c0 = cs; c0 < ce; c0 += MP, ++r) {
-      const int mp = min(MP, ce - c0);
-      const int mp4 = (mp + 3) & ~3;
-      AtomPos p{};
-      int coff = 0;  // this lane's coefficient offset
-      int at = -1;   // this lane's atom (sorted index)
-      if (r < PRE) {
-#pragma unroll
-        for (int q = 0; q < PRE; ++q)
-          if (q == r) {
-            p = pn[q];
-            coff = coef_r[q];
-            at = atom_r[q];
-            if (atom_r[q] >= 0 && k + 1 < nf) pn[q] = a.pos[frame_off + a.n_atoms + atom_r[q]];
-          }
-      } else if (pr < mp) {
-        const int entry = a.tile_atoms[c0 + pr];
-        at = entry >> 3;
-        p = a.pos[frame_off + at];
-        coff = (a.species[at] * N_GAUSS + (entry & 7)) * COEF_STRIDE;
-      }
+    // one round: pairs c0 .. c0 + mp - 1, this lane holding pair c0 + pr
+    // (position p, coefficient offset coff, atom at)
+    // (full: a round of MP pairs known at compile time, its MFMA steps unrolled)
+    auto round = [&](auto full, int c0, AtomPos p, int coff, int at) {
+      constexpr bool FULL = decltype(full)::value;
+      const int mp = FULL ? MP : min(MP, ce - c0);
+      const int mp4 = FULL ? MP : (mp + 3) & ~3;
       wave_lds_sync();  // the previous round's MFMA reads are done
       // A round of at most MP/2 (MP/4) pairs fills with MP/2 (MP/4) nodes per
       // lane: lane l takes pair l mod MP/2 from lane l mod MP/2, which holds
       // it (the same instruction stream, a quarter or half of the exp2 work)
-      if (mp > MP / 2) {
-        splat_fill<NPL, PS, IZ>(gx, gy, lane, mp, mp4, p, coef + coff, at, a, s, frame_off, tx0, ty0, simple_x,
-                                simple_y);
+      if (FULL || mp == MP) {
+        splat_fill<NPL, PS, IZ, true>(gx, gy, lane, mp, mp4, p, coef + coff, at, a, s, frame_off, tx0, ty0,
+                                      simple_x, simple_y);
+      } else if (mp > MP / 2) {
+        splat_fill<NPL, PS, IZ, false>(gx, gy, lane, mp, mp4, p, coef + coff, at, a, s, frame_off, tx0, ty0,
+                                       simple_x, simple_y);
       } else {
         const int src = lane % (mp > MP / 4 || MP / 4 < 8 ? MP / 2 : MP / 4);
         p.ix = __shfl(p.ix, src);
@@ -374,16 +371,17 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
         coff = __shfl(coff, src);
         at = __shfl(at, src);
         if (mp > MP / 4 || MP / 4 < 8)
-          splat_fill<NPL / 2, PS, IZ>(gx, gy, lane, mp, mp4, p, coef + coff, at, a, s, frame_off, tx0, ty0,
-                                      simple_x, simple_y);
+          splat_fill<NPL / 2, PS, IZ, false>(gx, gy, lane, mp, mp4, p, coef + coff, at, a, s, frame_off, tx0, ty0,
+                                             simple_x, simple_y);
         else
-          splat_fill<(MP / 4 < 8 ? 8 : NPL / 4), PS, IZ>(gx, gy, lane, mp, mp4, p, coef + coff, at, a, s,
-                                                         frame_off, tx0, ty0, simple_x, simple_y);
+          splat_fill<(MP / 4 < 8 ? 8 : NPL / 4), PS, IZ, false>(gx, gy, lane, mp, mp4, p, coef + coff, at, a, s,
+                                                                frame_off, tx0, ty0, simple_x, simple_y);
       }
       wave_lds_sync();
       // V[r][c] += sum_k gy[k][r] gx[k][c] over four 16 x 16 quarters; A is 16 x 4
       // (row lane % 16, k lane / 16), B is 4 x 16 (k lane / 16, column lane % 16)
-      for (int k0 = 0; k0 < mp4; k0 += 4) {
+#pragma unroll
+      for (int k0 = 0; k0 < (FULL ? MP : mp4); k0 += 4) {
         const int kk = k0 + lane / 16;
         const float a0 = gy[lane % 16][kk], a1 = gy[16 + lane % 16][kk];
         const float b0 = gx[lane % 16][kk], b1 = gx[16 + lane % 16][kk];
@@ -392,6 +390,29 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
         acc[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[2], 0, 0, 0);
         acc[3] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[3], 0, 0, 0);
       }
+    };
+    // the first two rounds take the positions prefetched a frame ahead and
+    // prefetch the next frame's; later rounds load their own
+    const AtomPos p0 = pn[0], p1 = pn[1];
+    if (k + 1 < nf) {
+      if (atom_r[0] >= 0) pn[0] = a.pos[frame_off + a.n_atoms + atom_r[0]];
+      if (atom_r[1] >= 0) pn[1] = a.pos[frame_off + a.n_atoms + atom_r[1]];
+    }
+    if (ce - cs >= MP)
+      round(Flag<true>{}, cs, p0, coef_r[0], atom_r[0]);
+    else if (cs < ce)
+      round(Flag<false>{}, cs, p0, coef_r[0], atom_r[0]);
+    if (cs + MP < ce) round(Flag<false>{}, cs + MP, p1, coef_r[1], atom_r[1]);
+    for (int c0 = cs + 2 * MP; c0 < ce; c0 += MP) {
+      AtomPos p{};
+      int coff = 0, at = -1;
+      if (c0 + pr < ce) {
+        const int entry = a.tile_atoms[c0 + pr];
+        at = entry >> 3;
+        p = a.pos[frame_off + at];
+        coff = (a.species[at] * N_GAUSS + (entry & 7)) * COEF_STRIDE;
+      }
+      round(Flag<false>{}, c0, p, coff, at);
     }
     // D layout: lane holds rows 4 (lane / 16) + j, j < 4, of column lane % 16
     float* out = a.V + ((size_t)fl * nsl + sl) * a.pny * a.pnx;
