@@ -315,8 +315,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
   const bool simple_y = a.img_y == 0 && 2 * (a.rcy + SPLAT_TY + 2) < a.pny;
   float (*gx)[PS] = gxs[wave];
   float (*gy)[PS] = gys[wave];
-  const int pr = lane % MP;   // pair of this lane in a full round (positions are loaded for it)
   typedef float v4f __attribute__((ext_vector_type(4)));
+  // A round of mp pairs fills NPL nodes per lane when mp > MP/2, else NPL/2
+  // (NPL/4 when mp <= MP/4 and MP/4 >= 8): lane l holds pair l mod (that
+  // node count), so a short round does a half or a quarter of the exp2 work
+  auto pair_of = [&](int mp) { return lane % (mp > MP / 2 ? MP : (mp > MP / 4 || MP / 4 < 8 ? MP / 2 : MP / 4)); };
 
   // per round: this lane's atom and coefficients are the same for every
   // frame; positions of the first PRE = 2 rounds are prefetched one frame
@@ -331,6 +334,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
     coef_r[r] = 0;
     pn[r] = AtomPos{};
     const int c0 = cs + r * MP;
+    const int pr = pair_of(min(MP, ce - c0));
     if (c0 + pr < ce) {
       const int entry = a.tile_atoms[c0 + pr];
       atom_r[r] = entry >> 3;
@@ -345,7 +349,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
     const int fl = fl0 + k;
     const size_t frame_off = (size_t)(a.f0 + fl) * a.n_atoms;
     v4f acc[4] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
-    // one round: pairs c0 .. c0 + mp - 1, this lane holding pair c0 + pr
+    // one round: pairs c0 .. c0 + mp - 1, this lane holding pair c0 + pair_of(mp)
     // (position p, coefficient offset coff, atom at)
     // (full: a round of MP pairs known at compile time, its MFMA steps unrolled)
     auto round = [&](auto full, int c0, AtomPos p, int coff, int at) {
@@ -353,9 +357,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
       const int mp = FULL ? MP : min(MP, ce - c0);
       const int mp4 = FULL ? MP : (mp + 3) & ~3;
       wave_lds_sync();  // the previous round's MFMA reads are done
-      // A round of at most MP/2 (MP/4) pairs fills with MP/2 (MP/4) nodes per
-      // lane: lane l takes pair l mod MP/2 from lane l mod MP/2, which holds
-      // it (the same instruction stream, a quarter or half of the exp2 work)
+      // the lane holds pair pair_of(mp) of the round
       if (FULL || mp == MP) {
         splat_fill<NPL, PS, IZ, true>(gx, gy, lane, mp, mp4, p, coef + coff, at, a, s, frame_off, tx0, ty0,
                                       simple_x, simple_y);
@@ -363,13 +365,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
         splat_fill<NPL, PS, IZ, false>(gx, gy, lane, mp, mp4, p, coef + coff, at, a, s, frame_off, tx0, ty0,
                                        simple_x, simple_y);
       } else {
-        const int src = lane % (mp > MP / 4 || MP / 4 < 8 ? MP / 2 : MP / 4);
-        p.ix = __shfl(p.ix, src);
-        p.iy = __shfl(p.iy, src);
-        p.fx = __shfl(p.fx, src);
-        p.fy = __shfl(p.fy, src);
-        coff = __shfl(coff, src);
-        at = __shfl(at, src);
         if (mp > MP / 4 || MP / 4 < 8)
           splat_fill<NPL / 2, PS, IZ, false>(gx, gy, lane, mp, mp4, p, coef + coff, at, a, s, frame_off, tx0, ty0,
                                              simple_x, simple_y);
@@ -406,6 +401,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
     for (int c0 = cs + 2 * MP; c0 < ce; c0 += MP) {
       AtomPos p{};
       int coff = 0, at = -1;
+      const int pr = pair_of(min(MP, ce - c0));
       if (c0 + pr < ce) {
         const int entry = a.tile_atoms[c0 + pr];
         at = entry >> 3;
