@@ -486,6 +486,9 @@ def main():
         "roofline": roofline,
         **({"roofline_kpot": roofline_kpot} if roofline_kpot else {}),
         "cpu_baseline": cpu,
+        # the device code and planner this run was built from (counter runs
+        # record it so that their bytes are used only while it holds)
+        "kernel_source_hash": kernel_source_hash(),
     }
     j.destroy()
     ctx.close()

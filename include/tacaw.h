@@ -272,9 +272,10 @@ tacaw_status tacaw_cancel(tacaw_job* job);
 tacaw_status tacaw_job_latency(const tacaw_job* job, double* queued_ms, double* total_ms);
 
 /* Counters of the context's serving loop since the context was created:
- * row and column pass launches that served more than one job
- * (*shared_launches), and served jobs that ran in shared launches
- * (*grouped_jobs).  Either pointer may be NULL. */
+ * pass launches (row, column, or LDS-resident multislice) that served more
+ * than one job (*shared_launches), and served jobs that shared at least one
+ * such launch with another job (*grouped_jobs).  Either pointer may be
+ * NULL. */
 tacaw_status tacaw_serve_stats(tacaw_ctx* ctx, int64_t* shared_launches, int64_t* grouped_jobs);
 
 /* Copy the spectrum I[p][m][ky][kx] (float32, n = n_probes * M * ny * nx,

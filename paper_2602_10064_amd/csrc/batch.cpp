@@ -194,13 +194,17 @@ tacaw_status LaneGroup::step(std::vector<tacaw_job*>* finished) {
   if (res) {
     st = timed_launch(c, TACAW_K_ROW, s, [&] { return launch_res_lanes(xl, n, s); });
     if (st != TACAW_OK) return st;
-    if (n > 1) shared_launches += 1;
   } else {
     st = timed_launch(c, TACAW_K_ROW, s, [&] { return launch_row_lanes(rl, n, rv, s); });
     if (st != TACAW_OK) return st;
     st = timed_launch(c, TACAW_K_COL, s, [&] { return launch_col_lanes(cl, n, cv, s); });
     if (st != TACAW_OK) return st;
-    if (n > 1) shared_launches += 2;   // the row and the column launch served several jobs
+  }
+  if (n > 1) {
+    // the pass launches (one resident launch, or a row and a column launch)
+    // served several jobs
+    shared_launches += res ? 1 : 2;
+    for (const Lane& L : active) L.job->shared_launch = true;
   }
   std::vector<Lane> still;
   for (int i = 0; i < n; ++i) {

@@ -169,7 +169,7 @@ struct tacaw_ctx {
   bool server_started = false;
   hipStream_t serve_stream = nullptr;
   int64_t serve_shared_launches = 0;   // pass launches of the serving loop that served several jobs
-  int64_t serve_grouped_jobs = 0;      // served jobs that ran in shared launches
+  int64_t serve_grouped_jobs = 0;      // served jobs that shared at least one launch with another job
   // batched executor and autotuner
   hipStream_t batch_streams[4] = {nullptr, nullptr, nullptr, nullptr};
   int row_variant[2048] = {0};   // by grid size: 0 untuned (use 1), else variant + 1
@@ -238,6 +238,8 @@ struct tacaw_job {
   double t_submit = 0, t_admit = 0, t_done = 0;
   size_t retained = 0;               // bytes counted in ctx->resident after a served job ends
   bool served = false;
+  // served: ran in at least one pass launch together with another job
+  bool shared_launch = false;
   // the serving loop has published this job's end but its release thread
   // has not yet freed the working buffers (guarded by ctx->mu)
   bool release_pending = false;

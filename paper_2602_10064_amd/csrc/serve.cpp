@@ -237,7 +237,13 @@ void server_main(tacaw_ctx* c) {
   const double age_ms = age_limit_ms();
   const double window_ms = batch_window_ms();
   // a grouped job's work is over (its stream has passed it): publish it
-  auto end_grouped = [&](tacaw_job* j, int state) { publish(c, hk_release, j, state); };
+  auto end_grouped = [&](tacaw_job* j, int state) {
+    if (j->shared_launch) {
+      std::lock_guard<std::mutex> lk(c->mu);
+      c->serve_grouped_jobs += 1;
+    }
+    publish(c, hk_release, j, state);
+  };
   for (;;) {
     bool progressed = false;
     {
@@ -334,8 +340,6 @@ void server_main(tacaw_ctx* c) {
           j->serve_state.store(ST_RUNNING);
           if (!g.stepped && g.lg.left.empty()) g.first_ready_ms = now_ms();
           g.lg.add(j);
-          std::lock_guard<std::mutex> lk(c->mu);
-          c->serve_grouped_jobs += 1;
         }
         progressed = true;
       }
@@ -521,6 +525,7 @@ tacaw_status tacaw_submit(tacaw_ctx* c, tacaw_job* j) {
   j->t_submit = now_ms();
   j->t_admit = j->t_done = 0;
   j->served = true;
+  j->shared_launch = false;
   j->serve_state.store(ST_QUEUED);
   c->queue.push_back(j);
   if (!c->server_started) {

@@ -234,7 +234,7 @@ class Context:
 
     def serve_stats(self) -> tuple:
         """(pass launches of the serving loop that served several jobs, served
-        jobs that ran in shared launches)."""
+        jobs that shared at least one launch with another job)."""
         a, b = ctypes.c_int64(), ctypes.c_int64()
         _check(lib().tacaw_serve_stats(self.handle, ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value
