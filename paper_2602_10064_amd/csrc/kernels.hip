@@ -2208,18 +2208,39 @@ __global__ void __launch_bounds__((TimeCfg<F>::THREADS)) k_time_ct(TimeArgs a) {
   constexpr int G = PL::G;
   constexpr int KT = TimeCfg<F>::KT;
   constexpr int LD = TimeCfg<F>::LD;
+  constexpr int THREADS = TimeCfg<F>::THREADS;
   extern __shared__ float2 smem[];
   float2* tw = smem;
   float2* cols = smem + F;
-  for (int i = threadIdx.x; i < F; i += blockDim.x) tw[i] = a.tw[i];
   const int tiles_per_probe = a.n_k / KT;
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
   const int p = tile / tiles_per_probe;
   const int k0 = (tile % tiles_per_probe) * KT;
   const float2* src = a.exit + (size_t)p * F * a.n_k + k0;
-  for (int e = threadIdx.x; e < KT * F; e += blockDim.x) {
-    const int c = e % KT, f = e / KT;
-    cols[c * LD + f] = src[(size_t)f * a.n_k + c];
+  // the block's KT x F values, PER per thread, loaded CH at a time with every
+  // load of a chunk in flight before the first LDS write (a load, wait, write
+  // loop would leave one HBM round trip per value outstanding)
+  constexpr int PER = KT * F / THREADS;
+  constexpr int CH = PER < 16 ? PER : 16;
+  static_assert(PER * THREADS == KT * F, "whole values per thread");
+#pragma unroll
+  for (int i = 0; i < (F + THREADS - 1) / THREADS; ++i)
+    if (F % THREADS == 0 || (int)threadIdx.x + i * THREADS < F) tw[threadIdx.x + i * THREADS] = a.tw[threadIdx.x + i * THREADS];
+#pragma unroll
+  for (int i0 = 0; i0 < PER; i0 += CH) {
+    float2 v[CH];
+#pragma unroll
+    for (int i = 0; i < CH; ++i)
+      if (i0 + i < PER) {
+        const int e = threadIdx.x + (i0 + i) * THREADS;
+        v[i] = src[(size_t)(e / KT) * a.n_k + e % KT];
+      }
+#pragma unroll
+    for (int i = 0; i < CH; ++i)
+      if (i0 + i < PER) {
+        const int e = threadIdx.x + (i0 + i) * THREADS;
+        cols[(e % KT) * LD + e / KT] = v[i];
+      }
   }
   __syncthreads();
   const int c = threadIdx.x / G;

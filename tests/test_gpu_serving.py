@@ -201,3 +201,23 @@ def test_shared_launches_across_requests(tacaw, monkeypatch):
             h.destroy()
     assert grouped == len(jobs)
     assert shared > 0
+
+
+def test_lone_requests_share_nothing(tacaw):
+    """Small requests served one after another (each waits for the previous)
+    run in lane groups of their own: no pass launch serves two of them, and
+    none counts as grouped; results are bitwise those of each job alone."""
+    jobs = [w.random_small_job(80 + i, nx=64, ny=64, n_slices=6, n_frames=8, cell=(8.0, 8.0, 6.0), n_atoms=20)
+            for i in range(3)]
+    with tacaw.Context(0) as ctx:
+        ref = [alone(tacaw, ctx, j) for j in jobs]
+    with tacaw.Context(0) as ctx:
+        for j, r in zip(jobs, ref):
+            h = tacaw.TacawJob(ctx, j, defer_alloc=True)
+            h.submit()
+            h.wait()
+            assert np.array_equal(h.spectrum().view(np.uint32), r.view(np.uint32)), j.name
+            h.destroy()
+        shared, grouped = ctx.serve_stats()
+        print(f"[gpu] shared launches {shared}, grouped jobs {grouped}", flush=True)
+    assert shared == 0 and grouped == 0
