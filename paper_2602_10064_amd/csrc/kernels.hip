@@ -1084,9 +1084,27 @@ __global__ void __launch_bounds__((ColCfg<N, VAR>::THREADS)) k_col(PassTable tab
   const int fl = w % a.fb;
   float2* wave = a.exit + ((size_t)p * a.n_frames + a.f0 + fl) * (size_t)N * a.nx;
 
-  for (int e = threadIdx.x; e < CT * N; e += blockDim.x) {
-    const int c = e % CT, yy = e / CT;
-    cols[c * LD + yy] = wave[(size_t)yy * a.nx + x0 + c];
+  // CT x N values, N / G per thread, loaded with every load of a chunk of up
+  // to 16 in flight before the LDS writes
+  constexpr int THREADS = ColCfg<N, VAR>::THREADS;
+  constexpr int PER = CT * N / THREADS;
+  constexpr int CH = PER < 16 ? PER : 16;
+  static_assert(PER * THREADS == CT * N, "whole values per thread");
+#pragma unroll
+  for (int i0 = 0; i0 < PER; i0 += CH) {
+    float2 v[CH];
+#pragma unroll
+    for (int i = 0; i < CH; ++i)
+      if (i0 + i < PER) {
+        const int e = threadIdx.x + (i0 + i) * THREADS;
+        v[i] = wave[(size_t)(e / CT) * a.nx + x0 + e % CT];
+      }
+#pragma unroll
+    for (int i = 0; i < CH; ++i)
+      if (i0 + i < PER) {
+        const int e = threadIdx.x + (i0 + i) * THREADS;
+        cols[(e % CT) * LD + e / CT] = v[i];
+      }
   }
   __syncthreads();
   const int c = threadIdx.x / G;
@@ -2138,9 +2156,20 @@ __global__ void __launch_bounds__(256) k_time(TimeArgs a) {
   const int p = tile / tiles_per_probe;
   const int k0 = (tile % tiles_per_probe) * KT;
   const float2* src = a.exit + (size_t)p * F * a.n_k + k0;
-  for (int e = threadIdx.x; e < KT * F; e += blockDim.x) {
-    const int c = e % KT, f = e / KT;
-    bufA[c * F + f] = src[(size_t)f * a.n_k + c];
+  // eight loads in flight per thread before their LDS writes
+  const int n_ld = KT * F;
+  for (int e0 = threadIdx.x; e0 < n_ld; e0 += 8 * blockDim.x) {
+    float2 v[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int e = e0 + i * blockDim.x;
+      if (e < n_ld) v[i] = src[(size_t)(e / KT) * a.n_k + e % KT];
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int e = e0 + i * blockDim.x;
+      if (e < n_ld) bufA[(e % KT) * F + e / KT] = v[i];
+    }
   }
   __syncthreads();
   const int c = threadIdx.x / TIME_G;
