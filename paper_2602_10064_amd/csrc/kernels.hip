@@ -737,16 +737,31 @@ __global__ void __launch_bounds__((RowCfg<N, VAR>::THREADS)) k_row(PassTable tab
     row = a.exit + (((size_t)p * a.n_frames + a.f0 + fl) * a.ny + y) * (size_t)N;
   }
 
+  // N / G values per thread; global reads go CH at a time, all in flight
+  // before their LDS writes
+  constexpr int PER = N / G;
+  constexpr int CH = PER < 8 ? PER : 8;
+  auto load_row = [&](const float2* src) {
+#pragma unroll
+    for (int i0 = 0; i0 < PER; i0 += CH) {
+      float2 v[CH];
+#pragma unroll
+      for (int i = 0; i < CH; ++i)
+        if (i0 + i < PER) v[i] = src[t + (i0 + i) * G];
+#pragma unroll
+      for (int i = 0; i < CH; ++i)
+        if (i0 + i < PER) buf[t + (i0 + i) * G] = v[i];
+    }
+  };
   if (active) {
     if (mode == ROW_FIRST) {
       if (a.plane) {
         for (int x = t; x < N; x += G) buf[x] = make_float2(a.plane_amp, 0.f);
       } else {
-        const float2* src = a.probe0 + ((size_t)p * a.ny + y) * (size_t)N;
-        for (int x = t; x < N; x += G) buf[x] = src[x];
+        load_row(a.probe0 + ((size_t)p * a.ny + y) * (size_t)N);
       }
     } else {
-      for (int x = t; x < N; x += G) buf[x] = row[x];
+      load_row(row);
     }
   }
   __syncthreads();
@@ -774,10 +789,22 @@ __global__ void __launch_bounds__((RowCfg<N, VAR>::THREADS)) k_row(PassTable tab
     if (yy >= a.pny) yy -= a.pny;
     const float* vrow =
         a.V + (((size_t)fl * a.v_slices + (a.slice - a.v_slice0)) * a.pny + yy) * (size_t)a.pnx;
-    for (int x = t; x < N; x += G) {
-      int xx = ox + x;
-      if (xx >= a.pnx) xx -= a.pnx;
-      buf[x] = cmul(buf[x], phase_factor(a.sigma * vrow[xx]));
+#pragma unroll
+    for (int i0 = 0; i0 < PER; i0 += CH) {
+      float vv[CH];
+#pragma unroll
+      for (int i = 0; i < CH; ++i)
+        if (i0 + i < PER) {
+          int xx = ox + t + (i0 + i) * G;
+          if (xx >= a.pnx) xx -= a.pnx;
+          vv[i] = vrow[xx];
+        }
+#pragma unroll
+      for (int i = 0; i < CH; ++i)
+        if (i0 + i < PER) {
+          const int x = t + (i0 + i) * G;
+          buf[x] = cmul(buf[x], phase_factor(a.sigma * vv[i]));
+        }
     }
   }
   __syncthreads();
