@@ -261,6 +261,7 @@ __device__ __forceinline__ void splat_fill(float (*gx)[PS], float (*gy)[PS], int
   }
 }
 
+// a compile-time flag handed to a generic lambda (instantiates one body per value)
 template <bool B>
 struct Flag {
   static constexpr bool value = B;
