@@ -236,12 +236,14 @@ tacaw_status tacaw_batch_destroy(tacaw_batch* batch);
  * of 64 to 1024 register-resident kernels with one or two rows in flight) and
  * the column-pass variants (tile widths, and for 64 to 1024 rows
  * register-resident kernels on 8- to 32-column tiles; at 512 rows also
- * 16-column tiles and the six-step kernel, 512 = 8 x 64 with lanes along x)
- * on one frame batch of `job` and keep the faster of each for the job's grid
- * size in the context (appended to the JSON-lines file named by
+ * 16-column tiles and the six-step kernels 512 = 8 x 64 with lanes along x
+ * on 8- and 16-column tiles, at 256 rows the six-step kernel 256 = 8 x 32 on
+ * 16-column tiles, at 384 rows the six-step kernel 384 = 6 x 64) on one
+ * frame batch of `job` and keep the faster of each for the job's grid size
+ * in the context (appended to the JSON-lines file named by
  * $TACAW_TUNE_CACHE, read back by later contexts).  Writes the chosen
- * variants (row 0-3, column 0-3 or 5) when the pointers are not NULL.  Resets
- * the context's timing totals. */
+ * variants (row 0-3, column 0-3 or 5-8) when the pointers are not NULL.
+ * Resets the context's timing totals. */
 tacaw_status tacaw_autotune(tacaw_job* job, void* hip_stream, int* row_variant, int* col_variant);
 
 /* Serving form: hand the job to the context's continuous-batching loop.

@@ -125,7 +125,9 @@ namespace tacaw {
 // width is not a multiple of 16), 4: variant 2 with two LDS buffers, 5:
 // six-step kernel for 512 rows, the default there, 6: the six-step kernel on
 // 16-column tiles, 7: the six-step kernel for 256 rows on 16-column tiles,
-// the default there (variant 3 where the width is not a multiple of 16)).  Tuned choices win;
+// the default there (variant 3 where the width is not a multiple of 16), 8:
+// the six-step kernel for 384 = 6 x 64 rows, the default there (variant 2
+// where the width is not a multiple of 8)).  Tuned choices win;
 // $TACAW_ROW_VARIANT and $TACAW_COL_VARIANT override untuned defaults.
 static bool has_register_fft(int n) {
   return n == 64 || n == 128 || n == 256 || n == 384 || n == 512 || n == 768 || n == 1024;
@@ -140,7 +142,7 @@ int col_variant_for(tacaw_ctx* c, int n) {
   const int v = (n > 0 && n < 2048) ? c->col_variant[n] : 0;
   if (v) return v - 1;
   if (const char* e = getenv("TACAW_COL_VARIANT")) return atoi(e);
-  return n == 512 ? 5 : n == 256 ? 7 : has_register_fft(n) ? 2 : 0;
+  return n == 512 ? 5 : n == 256 ? 7 : n == 384 ? 8 : has_register_fft(n) ? 2 : 0;
 }
 
 // Launch wrapper: when timing, the launch records a start and an end event

@@ -253,7 +253,7 @@ void load_tune_cache(tacaw_ctx* c) {
     int nx = 0, ny = 0, r = 0, cc = 0;
     if (sscanf(line.c_str(), "{\"nx\": %d, \"ny\": %d, \"row_variant\": %d, \"col_variant\": %d}", &nx, &ny, &r,
                &cc) == 4 &&
-        nx > 0 && nx < 2048 && ny > 0 && ny < 2048 && r >= 0 && r <= 3 && cc >= 0 && cc <= 7) {
+        nx > 0 && nx < 2048 && ny > 0 && ny < 2048 && r >= 0 && r <= 3 && cc >= 0 && cc <= 8) {
       c->row_variant[nx] = r + 1;
       c->col_variant[ny] = cc + 1;
     }
@@ -547,16 +547,23 @@ tacaw_status tacaw_autotune(tacaw_job* job, void* hip_stream, int* row_variant, 
   // tiles, ny 64-1024), 3 (16-column tiles, ny 256 and 512), 5 (six-step on
   // 8-column tiles, ny 512), 6 (six-step on 16-column tiles, ny 512, nx a
   // multiple of 16), 7 (six-step on 16-column tiles, ny 256, nx a multiple
-  // of 16)
+  // of 16), 8 (six-step on 8-column tiles, ny 384, nx a multiple of 8)
   auto reg = [](int n) { return n == 64 || n == 128 || n == 256 || n == 384 || n == 512 || n == 768 || n == 1024; };
   const int row_cand[4] = {0, 1, 2, 3};
   const int col_cand_512[6] = {0, 1, 2, 3, 5, 6};
   const int col_cand_256[5] = {0, 1, 2, 3, 7};
+  const int col_cand_384[4] = {0, 1, 2, 8};
   const int col_cand_other[3] = {0, 1, 2};
-  const int* col_cand = hp.ny == 512 ? col_cand_512 : hp.ny == 256 ? col_cand_256 : col_cand_other;
+  const int* col_cand = hp.ny == 512   ? col_cand_512
+                        : hp.ny == 256 ? col_cand_256
+                        : hp.ny == 384 ? col_cand_384
+                                       : col_cand_other;
   const int n_row_var = reg(hp.nx) ? 4 : 2;
-  const int n_col_var = hp.ny == 512 ? (hp.nx % 16 == 0 ? 6 : 5)
-                        : hp.ny == 256 && hp.nx % 16 == 0 ? 5 : reg(hp.ny) ? 3 : 2;
+  const int n_col_var = hp.ny == 512                       ? (hp.nx % 16 == 0 ? 6 : 5)
+                        : hp.ny == 256 && hp.nx % 16 == 0 ? 5
+                        : hp.ny == 384 && hp.nx % 8 == 0  ? 4
+                        : reg(hp.ny)                      ? 3
+                                                          : 2;
   const int n_var = std::max(n_row_var, n_col_var);
   double best_row[6] = {1e30, 1e30, 1e30, 1e30, 1e30, 1e30}, best_col[6] = {1e30, 1e30, 1e30, 1e30, 1e30, 1e30};
   const bool was_timing = c->timing;

@@ -1480,26 +1480,31 @@ __global__ void __launch_bounds__(RS<N>::THREADS) k_res(ResTable tab) {
 // 64 c + 8 (u ^ (c % 2)) + (k2 ^ u) for the local ones; every 16-lane group of
 // an access hits 16 distinct 8-byte slots modulo 16.
 // ---------------------------------------------------------------------------
+template <int R1>
 __global__ void __launch_bounds__(512) k_col_6s(PassTable tab, int total_tiles) {
-  constexpr int N = 512, CT = 8;
+  static_assert(R1 == 8 || R1 == 6, "512 = 8 x 64 and 384 = 6 x 64");
+  constexpr int N = 64 * R1, CT = 8;
   __shared__ float2 xs[4096];
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int ca = lane & 7, r0 = 8 * wave + (lane >> 3);   // layout A
   const int k1 = wave, cb = lane >> 3, u = lane & 7;      // layout B
+  // layout B has R1 wavefronts (k1 < R1); at 384 rows waves 6 and 7 only
+  // take part in the workgroup barriers there
+  const bool in_b = k1 < R1;
   // slots
   const int sa = 8 * r0 + (ca ^ (r0 & 7));                 // + 512 k1
   const int sb = 512 * k1 + 8 * u + (cb ^ u);              // + 64 q
   float2* lw = xs + 512 * k1 + 64 * cb;                    // local exchange region
   const int lodd = cb & 1;
-  // twiddles, the same for every tile (all lanes of a table have ny = 512)
-  float2 ta[8], tb[8];   // entries 1..7 (entry 0 is 1 and never used)
+  // twiddles, the same for every tile (all lanes of a table have ny = N):
+  // W_N^(r0 k) and W64^(u k) = W_N^(R1 u k), R1 u k < N
+  float2 ta[R1], tb[8];   // entries from 1 (entry 0 is 1 and never used)
   {
     const float2* tw = tab.l[0].a.tw_y;
 #pragma unroll
-    for (int k = 1; k < 8; ++k) {
-      ta[k] = tw[(r0 * k) & (N - 1)];
-      tb[k] = tw[(8 * u * k) & (N - 1)];
-    }
+    for (int k = 1; k < R1; ++k) ta[k] = tw[(N & (N - 1)) == 0 ? (r0 * k) & (N - 1) : (r0 * k) % N];
+#pragma unroll
+    for (int k = 1; k < 8; ++k) tb[k] = tw[R1 * u * k];
   }
   auto locate = [&](int it, int& L, int& x0, float2*& wp) {
     const int tile_g = xcd_remap(it, total_tiles);
@@ -1513,7 +1518,7 @@ __global__ void __launch_bounds__(512) k_col_6s(PassTable tab, int total_tiles) 
     const int fl = w % a.fb;
     wp = a.exit + ((size_t)p * a.n_frames + a.f0 + fl) * (size_t)N * a.nx;
   };
-  float2 pre[8];
+  float2 pre[R1];
   int L = 0, x0 = 0;
   float2* wp = nullptr;
   int it = blockIdx.x;
@@ -1521,7 +1526,7 @@ __global__ void __launch_bounds__(512) k_col_6s(PassTable tab, int total_tiles) 
     locate(it, L, x0, wp);
     const int nx = tab.l[L].a.nx;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) pre[j] = wp[(size_t)(r0 + 64 * j) * nx + x0 + ca];
+    for (int j = 0; j < R1; ++j) pre[j] = wp[(size_t)(r0 + 64 * j) * nx + x0 + ca];
   }
   for (; it < total_tiles; it += gridDim.x) {
     const PassArgs& a = tab.l[L].a;
@@ -1531,66 +1536,69 @@ __global__ void __launch_bounds__(512) k_col_6s(PassTable tab, int total_tiles) 
     float2* cur_wp = wp;
     float2 x[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) x[j] = pre[j];
+    for (int j = 0; j < R1; ++j) x[j] = pre[j];
     // the next tile's loads complete during this tile's arithmetic
     const int nit = it + gridDim.x;
     if (nit < total_tiles) {
       locate(nit, L, x0, wp);
       const int nnx = tab.l[L].a.nx;
 #pragma unroll
-      for (int j = 0; j < 8; ++j) pre[j] = wp[(size_t)(r0 + 64 * j) * nnx + x0 + ca];
+      for (int j = 0; j < R1; ++j) pre[j] = wp[(size_t)(r0 + 64 * j) * nnx + x0 + ca];
     }
-    // layout A: 8-point transform over j, twiddle, to LDS
-    dft8<false>(x);
+    // layout A: R1-point transform over j, twiddle, to LDS
+    dft<R1, false>(x);
 #pragma unroll
-    for (int k = 1; k < 8; ++k) x[k] = cmul(x[k], ta[k]);
+    for (int k = 1; k < R1; ++k) x[k] = cmul(x[k], ta[k]);
     __syncthreads();   // the previous tile's reads of the exchange buffer are done
 #pragma unroll
-    for (int k = 0; k < 8; ++k) xs[512 * k + sa] = x[k];
+    for (int k = 0; k < R1; ++k) xs[512 * k + sa] = x[k];
     __syncthreads();
-    // layout B: 8-point transform over q, twiddle, local exchange, over u
-#pragma unroll
-    for (int q = 0; q < 8; ++q) x[q] = xs[sb + 64 * q];
-    dft8<false>(x);
-#pragma unroll
-    for (int k = 1; k < 8; ++k) x[k] = cmul(x[k], tb[k]);
-    wave_lds_sync();
-#pragma unroll
-    for (int k = 0; k < 8; ++k) lw[8 * (u ^ lodd) + (k ^ u)] = x[k];
-    wave_lds_sync();
-#pragma unroll
-    for (int v = 0; v < 8; ++v) x[v] = lw[8 * (v ^ lodd) + (u ^ v)];
-    dft8<false>(x);   // x[k3] = psi(k1 + 8 u + 64 k3) of column cur_x0 + cb
-    const float2 pxv = a.px[cur_x0 + cb];
     const bool last = mode == COL_LAST;
+    if (in_b) {
+      // layout B: 8-point transform over q, twiddle, local exchange, over u
 #pragma unroll
-    for (int k = 0; k < 8; ++k) x[k] = cmul(x[k], cmul(pxv, a.py[k1 + 8 * u + 64 * k]));
-    if (last) {
+      for (int q = 0; q < 8; ++q) x[q] = xs[sb + 64 * q];
+      dft8<false>(x);
 #pragma unroll
-      for (int k = 0; k < 8; ++k) cur_wp[(size_t)(k1 + 8 * u + 64 * k) * nx + cur_x0 + cb] = x[k];
-      continue;
+      for (int k = 1; k < 8; ++k) x[k] = cmul(x[k], tb[k]);
+      wave_lds_sync();
+#pragma unroll
+      for (int k = 0; k < 8; ++k) lw[8 * (u ^ lodd) + (k ^ u)] = x[k];
+      wave_lds_sync();
+#pragma unroll
+      for (int v = 0; v < 8; ++v) x[v] = lw[8 * (v ^ lodd) + (u ^ v)];
+      dft8<false>(x);   // x[k3] = psi(k1 + R1 u + 8 R1 k3) of column cur_x0 + cb
+      const float2 pxv = a.px[cur_x0 + cb];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) x[k] = cmul(x[k], cmul(pxv, a.py[k1 + R1 * u + 8 * R1 * k]));
+      if (last) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) cur_wp[(size_t)(k1 + R1 * u + 8 * R1 * k) * nx + cur_x0 + cb] = x[k];
+      } else {
+        // inverse, the same steps backwards
+        dft8<true>(x);    // over k3: x[v] at u-index v, this lane's k2 = u
+        wave_lds_sync();
+#pragma unroll
+        for (int v = 0; v < 8; ++v) lw[8 * (v ^ lodd) + (u ^ v)] = x[v];
+        wave_lds_sync();
+        x[0] = lw[8 * (u ^ lodd) + u];
+#pragma unroll
+        for (int k = 1; k < 8; ++k) x[k] = cmulc(lw[8 * (u ^ lodd) + (k ^ u)], tb[k]);
+        dft8<true>(x);    // over k2: x[q] at r0 = u + 8 q
+        wave_lds_sync();
+#pragma unroll
+        for (int q = 0; q < 8; ++q) xs[sb + 64 * q] = x[q];
+      }
     }
-    // inverse, the same steps backwards
-    dft8<true>(x);    // over k3: x[v] at u-index v, this lane's k2 = u
-    wave_lds_sync();
-#pragma unroll
-    for (int v = 0; v < 8; ++v) lw[8 * (v ^ lodd) + (u ^ v)] = x[v];
-    wave_lds_sync();
-    x[0] = lw[8 * (u ^ lodd) + u];
-#pragma unroll
-    for (int k = 1; k < 8; ++k) x[k] = cmulc(lw[8 * (u ^ lodd) + (k ^ u)], tb[k]);
-    dft8<true>(x);    // over k2: x[q] at r0 = u + 8 q
-    wave_lds_sync();
-#pragma unroll
-    for (int q = 0; q < 8; ++q) xs[sb + 64 * q] = x[q];
+    if (last) continue;   // the same for the whole workgroup (one lane per tile)
     __syncthreads();
-    // layout A: conjugate twiddle, 8-point transform over k1, store
+    // layout A: conjugate twiddle, R1-point transform over k1, store
     x[0] = xs[sa];
 #pragma unroll
-    for (int k = 1; k < 8; ++k) x[k] = cmulc(xs[512 * k + sa], ta[k]);
-    dft8<true>(x);
+    for (int k = 1; k < R1; ++k) x[k] = cmulc(xs[512 * k + sa], ta[k]);
+    dft<R1, true>(x);
 #pragma unroll
-    for (int j = 0; j < 8; ++j) cur_wp[(size_t)(r0 + 64 * j) * nx + cur_x0 + ca] = x[j];
+    for (int j = 0; j < R1; ++j) cur_wp[(size_t)(r0 + 64 * j) * nx + cur_x0 + ca] = x[j];
   }
 }
 
@@ -2596,11 +2604,12 @@ static hipError_t col_r8_launch(PassTable& t, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int R1>
 static hipError_t col_6s_launch(PassTable& t, hipStream_t s) {
   int tiles = 0;
   for (int i = 0; i < t.n; ++i) {
     const PassArgs& a = t.l[i].a;
-    if (a.ny != 512 || a.nx % 8 != 0) return hipErrorInvalidValue;
+    if (a.ny != 64 * R1 || a.nx % 8 != 0) return hipErrorInvalidValue;
     t.l[i].block_start = tiles;
     tiles += a.n_probes * a.fb * (a.nx / 8);
   }
@@ -2609,7 +2618,7 @@ static hipError_t col_6s_launch(PassTable& t, hipStream_t s) {
   const char* ge = getenv("TACAW_COL_GRID");
   const int cap = ge && atoi(ge) > 0 ? atoi(ge) : 1024;
   const int grid = std::min(tiles, cap);
-  TACAW_LAUNCH(k_col_6s, dim3(grid), dim3(512), 0, s, t, tiles);
+  TACAW_LAUNCH(k_col_6s<R1>, dim3(grid), dim3(512), 0, s, t, tiles);
   return hipGetLastError();
 }
 
@@ -2666,11 +2675,13 @@ hipError_t launch_col_lanes(const PassLane* lanes, int n, int variant, hipStream
     if (ok) return col_6w_launch(t, s);
     variant = 5;
   }
-  if (variant == 5) {
-    // six-step kernel: ny = 512, regular and last-slice modes
-    bool ok = lanes[0].a.ny == 512 && lanes[0].a.nx % 8 == 0;
+  if (variant == 5 || variant == 8) {
+    // six-step kernel: ny = 512 (variant 5) or 384 (variant 8), regular and
+    // last-slice modes
+    const int ny = variant == 5 ? 512 : 384;
+    bool ok = lanes[0].a.ny == ny && lanes[0].a.nx % 8 == 0;
     for (int i = 0; i < n; ++i) ok = ok && lanes[i].mode != COL_INVERSE_ONLY;
-    if (ok) return col_6s_launch(t, s);
+    if (ok) return variant == 5 ? col_6s_launch<8>(t, s) : col_6s_launch<6>(t, s);
     variant = 2;
   }
   if (variant == 4) {

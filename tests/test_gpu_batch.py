@@ -152,18 +152,20 @@ def test_graph_replay_matches_eager(tacaw):
         other.destroy()
 
 
-def test_autotune_keeps_results(tacaw, tmp_path, monkeypatch):
+@pytest.mark.parametrize("grid,reps,default,col_cands", [(256, (6, 6, 2), (2, 7), (0, 1, 2, 3, 7)),
+                                                         (384, (9, 9, 2), (2, 8), (0, 1, 2, 8))])
+def test_autotune_keeps_results(tacaw, tmp_path, monkeypatch, grid, reps, default, col_cands):
     monkeypatch.setenv("TACAW_TUNE_CACHE", str(tmp_path / "tune.jsonl"))
-    job = w.c2_plain(n_frames=8, grid=256, n_slices=8, reps=(6, 6, 2))
+    job = w.c2_plain(n_frames=8, grid=grid, n_slices=8, reps=reps)
     with tacaw.Context(0) as ctx:
         h = tacaw.TacawJob(ctx, job)
         h.run()
         before = h.spectrum()
         rv, cv = h.autotune()
-        assert rv in (0, 1, 2, 3) and cv in (0, 1, 2, 3, 7)
+        assert rv in (0, 1, 2, 3) and cv in col_cands
         h.run()
         after = h.spectrum()
-        if (rv, cv) == (2, 7):      # the untuned default at 256^2: the same kernels
+        if (rv, cv) == default:     # the untuned default: the same kernels
             assert np.array_equal(after.view(np.uint32), before.view(np.uint32))
         else:
             # another FFT tiling: the exit waves agree to FP32 rounding; the
@@ -174,7 +176,7 @@ def test_autotune_keeps_results(tacaw, tmp_path, monkeypatch):
             assert err < 2e-4, err
         h.destroy()
     text = (tmp_path / "tune.jsonl").read_text()
-    assert '"nx": 256' in text
+    assert f'"nx": {grid}' in text
     # a new context reads the tuned choice back and reproduces the tuned run
     monkeypatch.setenv("TACAW_TUNE_CACHE", str(tmp_path / "tune.jsonl"))
     with tacaw.Context(0) as ctx:

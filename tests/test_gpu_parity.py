@@ -278,6 +278,28 @@ def test_256_rows_column_kernels(tacaw, ctx, oracle, monkeypatch, variant):
     check_job(tacaw, ctx, oracle, job)
 
 
+@pytest.mark.parametrize("variant", ["2", "8"])
+def test_384_rows_column_kernels(tacaw, ctx, oracle, monkeypatch, variant):
+    # 384 rows: the 12-value register column kernel (2) and the six-step
+    # kernel 384 = 6 x 64 on 8-column tiles (8, whose second layout has six
+    # wavefronts); probes in windows of a larger potential grid, ragged frame
+    # batches, 48 columns (six tiles)
+    monkeypatch.setenv("TACAW_COL_VARIANT", variant)
+    monkeypatch.setenv("TACAW_FB", "3")
+    job = w.random_small_job(49, nx=48, ny=384, n_slices=3, n_frames=10, cell=(6.0, 48.0, 4.0), n_atoms=24,
+                             aperture_mrad=25.0, n_probes=2, pot_grid=(64, 448))
+    check_job(tacaw, ctx, oracle, job)
+
+
+def test_384_square_six_step(tacaw, ctx, oracle, monkeypatch):
+    # the six-step kernel on a 384^2 plane-wave job with several column tiles
+    # per frame and a last slice (exit waves stored from the second layout)
+    monkeypatch.setenv("TACAW_COL_VARIANT", "8")
+    monkeypatch.setenv("TACAW_FB", "2")
+    job = w.random_small_job(50, nx=384, ny=384, n_slices=3, n_frames=5, cell=(40.0, 40.0, 4.0), n_atoms=25)
+    check_job(tacaw, ctx, oracle, job)
+
+
 def test_splat_rounds_of_16(tacaw, ctx, oracle, monkeypatch):
     # potentials built in rounds of 16 (atom, term) pairs: same values as
     # rounds of 32 up to the order of the FP32 sums, parity with the oracle
