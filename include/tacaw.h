@@ -233,7 +233,8 @@ tacaw_status tacaw_batch_launch(tacaw_batch* batch, void* hip_stream);
 tacaw_status tacaw_batch_destroy(tacaw_batch* batch);
 
 /* Autotuner: time the row-pass variants (rows per workgroup, and for grids
- * of 64 to 1024 register-resident kernels with one or two rows in flight) and
+ * of 64 to 1024 register-resident kernels with one or two rows in flight; at
+ * 384 also the six-step row kernel, 384 = 6 x 64) and
  * the column-pass variants (tile widths, and for 64 to 1024 rows
  * register-resident kernels on 8- to 32-column tiles; at 512 rows also
  * 16-column tiles and the six-step kernels 512 = 8 x 64 with lanes along x
@@ -242,7 +243,7 @@ tacaw_status tacaw_batch_destroy(tacaw_batch* batch);
  * frame batch of `job` and keep the faster of each for the job's grid size
  * in the context (appended to the JSON-lines file named by
  * $TACAW_TUNE_CACHE, read back by later contexts).  Writes the chosen
- * variants (row 0-3, column 0-3 or 5-8) when the pointers are not NULL.
+ * variants (row 0-4, column 0-3 or 5-8) when the pointers are not NULL.
  * Resets the context's timing totals. */
 tacaw_status tacaw_autotune(tacaw_job* job, void* hip_stream, int* row_variant, int* col_variant);
 

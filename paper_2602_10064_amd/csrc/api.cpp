@@ -118,8 +118,10 @@ void drain_records(tacaw_ctx* c) {
 namespace tacaw {
 
 // Tile variant of the row pass (0: base rows per block, 1: doubled, 2: the
-// register kernel for 64, 128, 256 and 512, 3: the same with two rows in
-// flight per wavefront) and of the column pass (0: half
+// register kernel for 64, 128, 256 and 512 (12- or 16-value registers for
+// 384, 768 and 1024), 3: the same with two rows in flight per wavefront, 4:
+// the six-step row kernel for 384 = 6 x 64, the default there) and of the
+// column pass (0: half
 // width, 1: full width, 2: register kernel on 8-16 column tiles for 64-512
 // rows, 3: 16-column register tiles for 256 and 512 rows (variant 2 where the
 // width is not a multiple of 16), 4: variant 2 with two LDS buffers, 5:
@@ -136,7 +138,7 @@ int row_variant_for(tacaw_ctx* c, int n) {
   const int v = (n > 0 && n < 2048) ? c->row_variant[n] : 0;
   if (v) return v - 1;
   if (const char* e = getenv("TACAW_ROW_VARIANT")) return atoi(e);
-  return has_register_fft(n) ? 2 : 1;
+  return n == 384 ? 4 : has_register_fft(n) ? 2 : 1;
 }
 int col_variant_for(tacaw_ctx* c, int n) {
   const int v = (n > 0 && n < 2048) ? c->col_variant[n] : 0;

@@ -253,7 +253,7 @@ void load_tune_cache(tacaw_ctx* c) {
     int nx = 0, ny = 0, r = 0, cc = 0;
     if (sscanf(line.c_str(), "{\"nx\": %d, \"ny\": %d, \"row_variant\": %d, \"col_variant\": %d}", &nx, &ny, &r,
                &cc) == 4 &&
-        nx > 0 && nx < 2048 && ny > 0 && ny < 2048 && r >= 0 && r <= 3 && cc >= 0 && cc <= 8) {
+        nx > 0 && nx < 2048 && ny > 0 && ny < 2048 && r >= 0 && r <= 4 && cc >= 0 && cc <= 8) {
       c->row_variant[nx] = r + 1;
       c->col_variant[ny] = cc + 1;
     }
@@ -542,14 +542,14 @@ tacaw_status tacaw_autotune(tacaw_job* job, void* hip_stream, int* row_variant, 
   const HostPlan& hp = job->hp;
   const int fb = std::min(hp.fb, hp.F);
   // row variants: 0, 1 (LDS rows), 2, 3 (register FFT with one or two rows
-  // in flight, grids 64-1024);
+  // in flight, grids 64-1024), 4 (six-step rows, nx 384);
   // column variants: 0, 1 (LDS columns), 2 (register FFT on 8-32 column
   // tiles, ny 64-1024), 3 (16-column tiles, ny 256 and 512), 5 (six-step on
   // 8-column tiles, ny 512), 6 (six-step on 16-column tiles, ny 512, nx a
   // multiple of 16), 7 (six-step on 16-column tiles, ny 256, nx a multiple
   // of 16), 8 (six-step on 8-column tiles, ny 384, nx a multiple of 8)
   auto reg = [](int n) { return n == 64 || n == 128 || n == 256 || n == 384 || n == 512 || n == 768 || n == 1024; };
-  const int row_cand[4] = {0, 1, 2, 3};
+  const int row_cand[5] = {0, 1, 2, 3, 4};
   const int col_cand_512[6] = {0, 1, 2, 3, 5, 6};
   const int col_cand_256[5] = {0, 1, 2, 3, 7};
   const int col_cand_384[4] = {0, 1, 2, 8};
@@ -558,7 +558,7 @@ tacaw_status tacaw_autotune(tacaw_job* job, void* hip_stream, int* row_variant, 
                         : hp.ny == 256 ? col_cand_256
                         : hp.ny == 384 ? col_cand_384
                                        : col_cand_other;
-  const int n_row_var = reg(hp.nx) ? 4 : 2;
+  const int n_row_var = hp.nx == 384 ? 5 : reg(hp.nx) ? 4 : 2;
   const int n_col_var = hp.ny == 512                       ? (hp.nx % 16 == 0 ? 6 : 5)
                         : hp.ny == 256 && hp.nx % 16 == 0 ? 5
                         : hp.ny == 384 && hp.nx % 8 == 0  ? 4

@@ -2069,6 +2069,201 @@ __global__ void __launch_bounds__(256) k_row_rv(PassTable tab) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Row pass for nx = 384 as 384 = 6 x 64 (six-step), one row per wavefront and
+// the exchanges in the wavefront's own LDS slots:
+//   layout A (natural): lane t holds x at t + 64 j (j < 6): a 6-point
+//             transform over j, twiddle W384^(t k1), exchange to
+//   layout B (lanes < 48): k1 = lane / 8, u = lane % 8, values at t = u + 8 q:
+//             an 8-point transform over q, twiddle W64^(u k2), an exchange
+//             within the 8 lanes of k1, an 8-point transform over u: index
+//             k1 + 6 u + 48 k3 held as k3 < 8.
+// A row of a later slice goes kx (A) -> x (B, conjugate steps), takes the
+// transmission at its scrambled x positions, and returns x (B) -> kx (A) by
+// the forward steps in reverse order (the transpose of the A -> B transform,
+// which is again the forward DFT).  A first-slice row starts from the
+// incident wave in x (A), takes the transmission there, and goes forward
+// A -> B, stored from its scrambled kx positions.  Exchange slots: value k of
+// position t at 64 k + (t ^ 8 (k mod 2)); the local exchanges use the
+// six-step column kernel's map inside the 64 slots of k1.  Every 16-lane
+// group of an access hits 16 distinct 8-byte slots modulo 16.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int r6_slot(int t, int k) { return 64 * k + (t ^ (8 * (k & 1))); }
+
+__global__ void __launch_bounds__(256) k_row_6r(PassTable tab) {
+  constexpr int N = 384;
+  __shared__ float2 xs_mem[4][N];
+  const int L = find_lane(tab, blockIdx.x);
+  const PassArgs& a = tab.l[L].a;
+  const int mode = tab.l[L].mode;   // ROW_FIRST or ROW_REGULAR (checked at launch)
+  const int lb = blockIdx.x - tab.l[L].block_start;
+  const int blocks_per_lane = (L + 1 < tab.n ? tab.l[L + 1].block_start : (int)gridDim.x) - tab.l[L].block_start;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+  const int t = threadIdx.x % 64;                  // layout A
+  const int k1 = t >> 3, u = t & 7;                // layout B (t < 48)
+  const bool in_b = t < 48;
+  const int lodd = k1 & 1;
+  float2* xs = xs_mem[wave];
+  float2* lw = xs + 64 * k1;                       // local exchange slots of k1
+  // twiddles: W384^(t k) (k < 6) and W64^(u k) = W384^(6 u k) (k < 8)
+  float2 ta[6], tb[8];
+  {
+    const float2* tw = a.tw_x;   // every lane of a table has nx = 384
+#pragma unroll
+    for (int k = 1; k < 6; ++k) ta[k] = tw[(t * k) % N];
+#pragma unroll
+    for (int k = 1; k < 8; ++k) tb[k] = tw[6 * u * k];
+  }
+  const bool first = mode == ROW_FIRST;
+  const int total = a.n_probes * a.fb * a.ny;   // below 2^31 (checked at launch)
+  const int stride = blocks_per_lane * 4;
+  // global reads of one row: the wave in layout A (a first-slice row: the
+  // incident wave), and the potential at this lane's x positions (layout A
+  // for a first-slice row, layout B otherwise)
+  auto fetch = [&](int rid, float2 (&xv)[6], float (&vv)[8], float2*& out) {
+    if (rid >= total) return;
+    const int w = rid / a.ny;
+    const int y = rid - w * a.ny;
+    const int p = w / a.fb;
+    const int fl = w - p * a.fb;
+    float2* row = a.exit + (((size_t)p * a.n_frames + a.f0 + fl) * a.ny + y) * (size_t)N;
+    out = row;
+    if (first) {
+      if (a.plane) {
+#pragma unroll
+        for (int j = 0; j < 6; ++j) xv[j] = make_float2(a.plane_amp, 0.f);
+      } else {
+        const float2* src = a.probe0 + ((size_t)p * a.ny + y) * (size_t)N;
+#pragma unroll
+        for (int j = 0; j < 6; ++j) xv[j] = src[t + 64 * j];
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 6; ++j) xv[j] = row[t + 64 * j];
+    }
+    const int ox = a.plane ? 0 : a.origin[2 * p];
+    const int oy = a.plane ? 0 : a.origin[2 * p + 1];
+    int yy = oy + y;
+    if (yy >= a.pny) yy -= a.pny;
+    const float* vrow = a.V + (((size_t)fl * a.v_slices + (a.slice - a.v_slice0)) * a.pny + yy) * (size_t)a.pnx;
+    // every lane reads an in-range position (lanes 48-63 of a later-slice
+    // row, and entries 6-7 of a first-slice row, read one they do not use)
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int x = first ? t + 64 * (r < 6 ? r : 0) : (in_b ? k1 + 6 * u + 48 * r : u);
+      int xx = ox + x;
+      if (xx >= a.pnx) xx -= a.pnx;
+      vv[r] = vrow[xx];
+    }
+  };
+  float2 xn[6];
+  float vn[8];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) xn[j] = make_float2(0.f, 0.f);
+#pragma unroll
+  for (int r = 0; r < 8; ++r) vn[r] = 0.f;
+  float2* out_next = nullptr;
+  int rid = lb * 4 + wave;
+  fetch(rid, xn, vn, out_next);
+  for (; rid < total; rid += stride) {
+    float2* out = out_next;
+    float2 x[8];
+    float v[8];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) x[j] = xn[j];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) v[r] = vn[r];
+    fetch(rid + stride, xn, vn, out_next);
+    if (first) {
+      // transmission in x (layout A), then kx by the forward steps A -> B
+#pragma unroll
+      for (int j = 0; j < 6; ++j) x[j] = cmul(x[j], phase_factor(a.sigma * v[j]));
+      dft6<false>(x);
+#pragma unroll
+      for (int k = 1; k < 6; ++k) x[k] = cmul(x[k], ta[k]);
+    } else {
+      // x by the conjugate steps A -> B
+      dft6<true>(x);
+#pragma unroll
+      for (int k = 1; k < 6; ++k) x[k] = cmulc(x[k], ta[k]);
+    }
+    wave_lds_sync();   // the previous row's reads of xs are done
+#pragma unroll
+    for (int k = 0; k < 6; ++k) xs[r6_slot(t, k)] = x[k];
+    wave_lds_sync();
+    if (in_b) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) x[q] = xs[r6_slot(u + 8 * q, k1)];
+    }
+    if (first) {
+      if (in_b) {
+        dft8<false>(x);
+#pragma unroll
+        for (int k = 1; k < 8; ++k) x[k] = cmul(x[k], tb[k]);
+      }
+    } else if (in_b) {
+      dft8<true>(x);
+#pragma unroll
+      for (int k = 1; k < 8; ++k) x[k] = cmulc(x[k], tb[k]);
+    }
+    wave_lds_sync();   // every lane's reads of xs are done
+    if (in_b) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) lw[8 * (u ^ lodd) + (k ^ u)] = x[k];
+    }
+    wave_lds_sync();
+    if (in_b) {
+#pragma unroll
+      for (int w = 0; w < 8; ++w) x[w] = lw[8 * (w ^ lodd) + (u ^ w)];
+    }
+    if (first) {
+      // x[k3] = psi(kx = k1 + 6 u + 48 k3)
+      if (in_b) {
+        dft8<false>(x);
+        if (rid < total) {
+#pragma unroll
+          for (int k = 0; k < 8; ++k) out[k1 + 6 * u + 48 * k] = x[k];
+        }
+      }
+      continue;
+    }
+    if (in_b) {
+      // x[k3] = psi(x = k1 + 6 u + 48 k3): transmission, then back to kx by
+      // the forward steps in reverse order
+      dft8<true>(x);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) x[k] = cmul(x[k], phase_factor(a.sigma * v[k]));
+      dft8<false>(x);   // over k3: x[w] at u-index w, this lane's k2 = u
+    }
+    wave_lds_sync();   // every lane's reads of the local slots are done
+    if (in_b) {
+#pragma unroll
+      for (int w = 0; w < 8; ++w) lw[8 * (w ^ lodd) + (u ^ w)] = x[w];
+    }
+    wave_lds_sync();
+    if (in_b) {
+      x[0] = lw[8 * (u ^ lodd) + u];
+#pragma unroll
+      for (int k = 1; k < 8; ++k) x[k] = cmul(lw[8 * (u ^ lodd) + (k ^ u)], tb[k]);
+      dft8<false>(x);   // over k2: x[q] at t = u + 8 q
+    }
+    wave_lds_sync();   // every lane's reads of the local slots are done
+    if (in_b) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) xs[r6_slot(u + 8 * q, k1)] = x[q];
+    }
+    wave_lds_sync();
+    x[0] = xs[r6_slot(t, 0)];
+#pragma unroll
+    for (int k = 1; k < 6; ++k) x[k] = cmul(xs[r6_slot(t, k)], ta[k]);
+    dft6<false>(x);
+    if (rid < total) {
+#pragma unroll
+      for (int j = 0; j < 6; ++j) out[t + 64 * j] = x[j];
+    }
+  }
+}
+
 template <int N>
 struct CV {
   static constexpr int G = RV<N>::G;
@@ -2497,6 +2692,29 @@ static hipError_t row_rv_launch(PassTable& t, hipStream_t s) {
   return hipGetLastError();
 }
 
+static hipError_t row_6r_launch(PassTable& t, hipStream_t s) {
+  constexpr int rows_per_block = 4;
+  constexpr long max_blocks = 2048;
+  long rows[MAX_LANES], total = 0;
+  for (int i = 0; i < t.n; ++i) {
+    const PassArgs& a = t.l[i].a;
+    if (a.nx != 384 || (t.l[i].mode != ROW_FIRST && t.l[i].mode != ROW_REGULAR)) return hipErrorInvalidValue;
+    rows[i] = (long)a.n_probes * a.fb * a.ny;
+    if (rows[i] + 4 * max_blocks * rows_per_block >= (1L << 31)) return hipErrorInvalidValue;
+    total += rows[i];
+  }
+  const long need = (total + rows_per_block - 1) / rows_per_block;
+  int blocks = 0;
+  for (int i = 0; i < t.n; ++i) {
+    const long own = (rows[i] + rows_per_block - 1) / rows_per_block;
+    const long b = need <= max_blocks ? own : std::max(1L, std::min(own, rows[i] * max_blocks / total));
+    t.l[i].block_start = blocks;
+    blocks += (int)b;
+  }
+  TACAW_LAUNCH(k_row_6r, dim3(blocks), dim3(256), 0, s, t);
+  return hipGetLastError();
+}
+
 template <int N>
 static hipError_t col_rv_launch(PassTable& t, hipStream_t s) {
   constexpr int CT = CV<N>::CT;
@@ -2562,6 +2780,13 @@ hipError_t launch_row_lanes(const PassLane* lanes, int n, int variant, hipStream
   PassTable t{};
   t.n = n;
   for (int i = 0; i < n; ++i) t.l[i] = lanes[i];
+  if (variant == 4) {
+    // six-step row kernel at 384: first-slice and regular rows
+    bool ok = lanes[0].a.nx == 384;
+    for (int i = 0; i < n; ++i) ok = ok && (lanes[i].mode == ROW_FIRST || lanes[i].mode == ROW_REGULAR);
+    if (ok) return row_6r_launch(t, s);
+    variant = 2;
+  }
   if (variant == 2 || variant == 3) {
     const bool deep = variant == 3;
     switch (lanes[0].a.nx) {

@@ -152,9 +152,10 @@ def test_graph_replay_matches_eager(tacaw):
         other.destroy()
 
 
-@pytest.mark.parametrize("grid,reps,default,col_cands", [(256, (6, 6, 2), (2, 7), (0, 1, 2, 3, 7)),
-                                                         (384, (9, 9, 2), (2, 8), (0, 1, 2, 8))])
-def test_autotune_keeps_results(tacaw, tmp_path, monkeypatch, grid, reps, default, col_cands):
+@pytest.mark.parametrize("grid,reps,default,row_cands,col_cands",
+                         [(256, (6, 6, 2), (2, 7), (0, 1, 2, 3), (0, 1, 2, 3, 7)),
+                          (384, (9, 9, 2), (4, 8), (0, 1, 2, 3, 4), (0, 1, 2, 8))])
+def test_autotune_keeps_results(tacaw, tmp_path, monkeypatch, grid, reps, default, row_cands, col_cands):
     monkeypatch.setenv("TACAW_TUNE_CACHE", str(tmp_path / "tune.jsonl"))
     job = w.c2_plain(n_frames=8, grid=grid, n_slices=8, reps=reps)
     with tacaw.Context(0) as ctx:
@@ -162,7 +163,7 @@ def test_autotune_keeps_results(tacaw, tmp_path, monkeypatch, grid, reps, defaul
         h.run()
         before = h.spectrum()
         rv, cv = h.autotune()
-        assert rv in (0, 1, 2, 3) and cv in col_cands
+        assert rv in row_cands and cv in col_cands
         h.run()
         after = h.spectrum()
         if (rv, cv) == default:     # the untuned default: the same kernels

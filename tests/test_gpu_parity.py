@@ -291,10 +291,26 @@ def test_384_rows_column_kernels(tacaw, ctx, oracle, monkeypatch, variant):
     check_job(tacaw, ctx, oracle, job)
 
 
+@pytest.mark.parametrize("variant", ["2", "4"])
+def test_384_wide_row_kernels(tacaw, ctx, oracle, monkeypatch, variant):
+    # 384-wide rows: the 12-value register row kernel (2) and the six-step
+    # row kernel 384 = 6 x 64 (4: first-slice rows from the incident probe
+    # through the forward steps, later rows through the conjugate steps, the
+    # transmission at scrambled positions and back); probes in windows of a
+    # larger potential grid (wrapped potential rows), ragged frame batches
+    monkeypatch.setenv("TACAW_ROW_VARIANT", variant)
+    monkeypatch.setenv("TACAW_FB", "3")
+    job = w.random_small_job(51, nx=384, ny=48, n_slices=3, n_frames=10, cell=(48.0, 6.0, 4.0), n_atoms=24,
+                             aperture_mrad=25.0, n_probes=2, pot_grid=(448, 64))
+    check_job(tacaw, ctx, oracle, job)
+
+
 def test_384_square_six_step(tacaw, ctx, oracle, monkeypatch):
-    # the six-step kernel on a 384^2 plane-wave job with several column tiles
-    # per frame and a last slice (exit waves stored from the second layout)
+    # the six-step row and column kernels on a 384^2 plane-wave job with
+    # several column tiles per frame and a last slice (exit waves stored from
+    # the second layout)
     monkeypatch.setenv("TACAW_COL_VARIANT", "8")
+    monkeypatch.setenv("TACAW_ROW_VARIANT", "4")
     monkeypatch.setenv("TACAW_FB", "2")
     job = w.random_small_job(50, nx=384, ny=384, n_slices=3, n_frames=5, cell=(40.0, 40.0, 4.0), n_atoms=25)
     check_job(tacaw, ctx, oracle, job)
