@@ -1,7 +1,7 @@
 """CPU emulation of the six-step FFT kernels' data movement (no GPU).
 
-The column kernel for ny = 64 R1 (R1 = 8: 512 rows, R1 = 6: 384 rows) and the
-384-wide row kernel move values between two register layouts through LDS
+The column kernels for ny = 64 R1 (R1 = 8: 512 rows, R1 = 6: 384 rows) and
+for ny = 256 on 16-column tiles, and the 384-wide row kernel, move values between two register layouts through LDS
 slots.  These tests restate the kernels' lane and slot formulas, push a
 random tile through an emulated LDS array exactly as the kernels do, and
 check the results against numpy's FFT; they also check that every slot map
@@ -144,6 +144,78 @@ def test_six_step_column_slots(R1):
         for w in range(R1):
             assert conflict_free(wr[64 * w:64 * w + 64]) and conflict_free(rd[64 * w:64 * w + 64])
             assert np.all(wr[64 * w:64 * w + 64] // 512 == w)
+
+
+# --- column kernel for 256 = 8 x 32 rows on 16-column tiles, 512 threads -----
+
+def q_lanes():
+    tid = np.arange(512)
+    wave, lane = tid // 64, tid % 64
+    ca, r0 = lane & 15, 4 * wave + (lane >> 4)             # layout A
+    k1, cb, u = wave, lane >> 2, lane & 3                  # layout B
+    sa = 16 * r0 + (ca ^ (4 * (r0 & 3)))
+    sb = 512 * k1 + 16 * u + (cb ^ (4 * u))
+    lw = 512 * k1 + 32 * cb
+    cs = cb & 3
+    return ca, r0, k1, cb, u, sa, sb, lw, cs
+
+
+def lslot(k2, uu, cs):
+    return 16 * (k2 >> 2) + 4 * ((k2 & 3) ^ cs) + (uu ^ cs)
+
+
+def test_six_step_column_256_slice_step():
+    N = 256
+    rng = np.random.default_rng(256)
+    tile = rng.standard_normal((N, 16)) + 1j * rng.standard_normal((N, 16))
+    prop = np.exp(1j * rng.standard_normal((N, 16)))
+    ca, r0, k1, cb, u, sa, sb, lw, cs = q_lanes()
+    xs = np.full(4096, np.nan, complex)
+    # forward: layout A
+    x = tile[r0[:, None] + 32 * np.arange(8)[None, :], ca[:, None]]
+    x = dft(x, False)
+    x[:, 1:] *= tw(N, r0[:, None] * np.arange(1, 8)[None, :], False)
+    for k in range(8):
+        xs[512 * k + sa] = x[:, k]
+    # layout B
+    y = np.stack([xs[sb + 64 * q] for q in range(8)], axis=1)
+    y = dft(y, False)
+    y[:, 1:] *= tw(32, u[:, None] * np.arange(1, 8)[None, :], False)
+    for k in range(8):
+        xs[lw + lslot(k, u, cs)] = y[:, k]
+    z = np.stack([xs[lw + lslot(u + 4 * (v >> 2), v & 3, cs)] for v in range(8)], axis=1)
+    z = np.concatenate([dft(z[:, :4], False), dft(z[:, 4:], False)], axis=1)
+    rows = np.stack([k1 + 8 * (u + 4 * (e >> 2)) + 64 * (e & 3) for e in range(8)], axis=1)
+    spec = np.fft.fft(tile, axis=0)
+    assert np.allclose(z, spec[rows, cb[:, None]], rtol=0, atol=1e-9 * np.abs(spec).max())
+    assert len(set(zip(rows.ravel().tolist(), np.repeat(cb, 8).tolist()))) == 16 * N
+    # propagator, then the inverse retraced
+    z = z * prop[rows, cb[:, None]]
+    z = np.concatenate([dft(z[:, :4], True), dft(z[:, 4:], True)], axis=1)
+    for h in range(2):
+        for v in range(4):
+            xs[lw + lslot(u + 4 * h, v, cs)] = z[:, 4 * h + v]
+    y = np.stack([xs[lw + lslot(k, u, cs)] for k in range(8)], axis=1)
+    y[:, 1:] *= tw(32, u[:, None] * np.arange(1, 8)[None, :], True)
+    y = dft(y, True)
+    for q in range(8):
+        xs[sb + 64 * q] = y[:, q]
+    x = np.stack([xs[512 * k + sa] for k in range(8)], axis=1)
+    x[:, 1:] *= tw(N, r0[:, None] * np.arange(1, 8)[None, :], True)
+    x = dft(x, True)
+    out = np.zeros((N, 16), complex)
+    out[r0[:, None] + 32 * np.arange(8)[None, :], ca[:, None]] = x
+    want = np.fft.ifft(prop * spec, axis=0) * N
+    assert np.allclose(out, want, rtol=0, atol=1e-9 * np.abs(want).max())
+    # bank checks: every wavefront instruction of every exchange
+    for w in range(8):
+        sl = slice(64 * w, 64 * w + 64)
+        for k in range(8):
+            assert conflict_free((512 * k + sa)[sl]) and conflict_free((lw + lslot(k, u, cs))[sl])
+        for q in range(8):
+            assert conflict_free((sb + 64 * q)[sl])
+        for v in range(8):
+            assert conflict_free((lw + lslot(u + 4 * (v >> 2), v & 3, cs))[sl])
 
 
 # --- row kernel for 384 = 6 x 64, one row per wavefront ------------------------
