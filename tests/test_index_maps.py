@@ -1,8 +1,9 @@
 """CPU emulation of the six-step FFT kernels' data movement (no GPU).
 
 The column kernels for ny = 64 R1 (R1 = 8: 512 rows, R1 = 6: 384 rows) and
-for ny = 256 on 16-column tiles, and the 384-wide row kernel, move values between two register layouts through LDS
-slots.  These tests restate the kernels' lane and slot formulas, push a
+for ny = 256 on 16-column tiles, and the 384-wide row kernel, move values
+between two register layouts through LDS slots.  These tests restate the
+kernels' lane and slot formulas, push a
 random tile through an emulated LDS array exactly as the kernels do, and
 check the results against numpy's FFT; they also check that every slot map
 is a bijection onto its region and that each 16-lane group of an 8-byte LDS
